@@ -1,0 +1,204 @@
+/*
+ * afqmc.h -- C ABI of the MI355X phaseless-AFQMC hot path.
+ *
+ * The library propagates a population of Slater-determinant walkers with
+ * phaseless auxiliary-field QMC for a Hamiltonian given in Cholesky form,
+ * following Motta & Zhang, arXiv:1711.02242:
+ *
+ *   H = H0 + sum_{pq,s} h_pq a+_ps a_qs + 1/2 sum_{pqrs,st} v_pqrs a+_ps a+_qt a_st a_rs
+ *   v_pqrs = sum_g L^g_pr L^g_qs                               (Sec. II, eq:bo_ham2;
+ *                                                               Sec. II.B.2, eq:chol)
+ *
+ * One call of afqmc_step is one step of the random walk of Sec. III.E for
+ * every walker: force bias from the half-rotated Cholesky tensor
+ * (eq:fb, eq:precomputing2), auxiliary fields, Taylor-expanded propagation
+ * of the Hubbard-Stratonovich exponent between exact one-body half steps
+ * (eq:primitive, Theorem 1.4, Sec. III.D.2), periodic re-orthonormalization
+ * (Sec. III.D.5), overlap and Green's function (Theorem 1.1-1.2,
+ * eq:precomputing), local energy (eq:localenergy2, eq:localenergy3), the
+ * phaseless weight (eq:if_rle, eq:cap) and periodic comb population control
+ * (Sec. III.D.4).  afqmc_energy returns the sums of the mixed estimator
+ * (eq:localenergy with theta = 0).
+ *
+ * Conventions
+ *  - Real, row-major, FP64 host arrays for the Hamiltonian and the trial.
+ *  - Complex numbers are (re, im) pairs of doubles, interleaved.
+ *  - Walker orbitals are stored orbital-major: U[w][c][p] is coefficient p
+ *    (0..M-1) of occupied orbital c of walker w; orbitals c = 0..n_up-1 are
+ *    spin up, c = n_up..n_up+n_dn-1 spin down.  (U[w][c][p] = (U_sigma)_{p,c'}
+ *    in the paper's M x N_sigma notation.)
+ *  - Every function returns AFQMC_OK (0) or a negative afqmc_status code; the
+ *    text of a code is afqmc_error_string(code).  Functions that only enqueue
+ *    device work return errors of argument checking and of the launches; a
+ *    numerical fault inside a walker (non-finite energy, singular overlap) does
+ *    not abort: that walker's weight becomes 0 and a sticky bit is set in the
+ *    status word, reported by the next synchronizing call (afqmc_energy).
+ *  - All device work of a system is enqueued on the HIP stream given to
+ *    afqmc_setup, in order.  Calls on one system must be serialized by the
+ *    caller; different systems may be used concurrently on different streams.
+ */
+#ifndef AFQMC_H
+#define AFQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define AFQMC_API __attribute__((visibility("default")))
+#else
+#define AFQMC_API
+#endif
+
+typedef enum {
+  AFQMC_OK = 0,
+  AFQMC_E_ARG = -1,          /* invalid size, pointer, or non-symmetric h1 / L   */
+  AFQMC_E_UNSUPPORTED = -2,  /* precision or size outside what is built          */
+  AFQMC_E_SINGULAR = -3,     /* trial determinant with V^T V singular             */
+  AFQMC_E_NOMEM = -4,        /* device allocation failed, or workspace too small  */
+  AFQMC_E_HIP = -5,          /* a HIP runtime call or launch failed               */
+  AFQMC_E_NUMERIC = -6,      /* no live walker left, or non-finite estimator      */
+  AFQMC_E_STATE = -7         /* call out of order (e.g. step before init)         */
+} afqmc_status;
+
+/* Arithmetic of the bulk contractions (local-energy contraction, propagator
+ * build and Taylor propagation).  Overlaps, inverses, determinants, QR,
+ * weights and all reductions are FP64 in every mode; walker orbitals are
+ * always stored as complex128. */
+typedef enum {
+  AFQMC_FP64 = 0,     /* FP64 everywhere                                        */
+  AFQMC_FP32 = 1,     /* FP32 MFMA with FP32 accumulation                       */
+  AFQMC_BF16X3 = 2    /* BF16 split products hi*hi + hi*lo + lo*hi, FP32 accum.  */
+} afqmc_precision;
+
+/* Bits of the sticky status word. */
+#define AFQMC_STATUS_NONFINITE  0x1u   /* a walker produced NaN/Inf and was killed     */
+#define AFQMC_STATUS_SINGULAR   0x2u   /* a walker's overlap matrix was singular       */
+#define AFQMC_STATUS_ECAP       0x4u   /* the local-energy cap was applied (eq:cap)    */
+#define AFQMC_STATUS_WCAP       0x8u   /* the weight cap was applied (App. B.1)        */
+#define AFQMC_STATUS_FBCAP     0x10u   /* the force-bias cap was applied (App. B.1)    */
+#define AFQMC_STATUS_PHASE     0x20u   /* cos(dtheta) <= 0 killed a walker (eq:if_rle) */
+
+typedef struct afqmc_sys_s* afqmc_sys;   /* opaque, library-owned */
+
+typedef struct {
+  int32_t M;            /* orbitals, >= 1                                            */
+  int32_t n_up, n_dn;   /* electrons per spin, 0 <= n <= M, n_up + n_dn >= 1         */
+  int32_t n_chol;       /* Cholesky vectors N_g, >= 0                                */
+  double dtau;          /* time step, > 0                                            */
+  double e_trial;       /* E_T in the weight; NaN -> E_L(Phi_T, Phi_T) (App. B.2)   */
+  int32_t n_taylor;     /* Taylor terms beyond the identity, 1..20 (Sec. III.D.2)    */
+  int32_t qr_period;    /* re-orthonormalize after steps k with (k+1) % p == 0; 0 = never */
+  int32_t pop_period;   /* comb after steps k with (k+1) % p == 0; 0 = never          */
+  int32_t precision;    /* afqmc_precision                                            */
+  double el_cap_C;      /* local-energy cap |Re E_L - E_T| <= sqrt(C/dtau), > 0 (eq:cap) */
+  double w_max;         /* weight cap; NaN -> max(100, n_walkers/10) (App. B.1)       */
+  double fb_cap;        /* cap on |xbar_g|, > 0 (App. B.1)                            */
+  uint32_t flags;       /* reserved, must be 0                                        */
+  uint32_t reserved;
+} afqmc_params;
+
+typedef struct {
+  int32_t n_walkers;     /* >= 1 */
+  int32_t reserved;
+  void* U;               /* device, [n_walkers][n_up+n_dn][M] complex128 (see Conventions) */
+  double* weight;        /* device, [n_walkers]   W >= 0; W == 0 marks a dead walker         */
+  double* arg_ovlp;      /* device, [n_walkers]   arg <Phi_T|Psi> in (-pi, pi]               */
+  double* log_ovlp;      /* device, [n_walkers]   log |<Phi_T|Psi>| (diagnostic)            */
+  double* e_loc;         /* device, [n_walkers][2] complex E_L of the current determinant    */
+  int64_t* walker_id;    /* device, [n_walkers]   ids that select the field stream           */
+  void* workspace;       /* device, afqmc_workspace_bytes() bytes, 256-byte aligned          */
+  size_t workspace_bytes;
+  int64_t step;          /* steps taken; afqmc_step advances it                             */
+} afqmc_walkers;
+
+typedef struct {
+  uint64_t seed;         /* Philox4x64-10 key word 0                                         */
+  uint64_t job_id;       /* Philox4x64-10 key word 1                                         */
+  const double* x;       /* NULL: draw the fields on the device from the counter stream
+                            (block, walker_id, step, 0); else device [n_walkers][n_chol]
+                            fields for this step, read as given                              */
+  double u_comb;         /* comb uniform in (0,1) if population control is due; NaN: draw it
+                            from the counter stream (0, 0, step, 1)                          */
+} afqmc_fields;
+
+typedef struct {
+  double e_trial;        /* E_T in use                                     */
+  double e_hf;           /* E_L(Phi_T, Phi_T)                              */
+  size_t device_bytes;   /* library-owned device memory of this system     */
+} afqmc_info;
+
+/* Copy the Hamiltonian and trial to the device and precompute everything that
+ * does not depend on the walkers (Sec. II.B.2 eq:mcd1; Sec. III.D.2):
+ *   v0 = h1 - 1/2 sum_g L^g L^g,  E_h = exp(-dtau/2 v0) (FP64 eigendecomposition),
+ *   half-rotated Lh^g_s = V_s^T L^g and h~_s = V_s^T h1 in every precision used,
+ *   E_HF = E_L(Phi_T, Phi_T).
+ * h1      host, M*M row-major, real symmetric (|h - h^T| <= 1e-12 max|h|)
+ * L_chol  host, n_chol*M*M row-major, each L^g real symmetric; may be NULL if n_chol == 0
+ * phi_up  host, M*n_up row-major (the M x N_up trial matrix V_up); phi_dn likewise.
+ *         The trial need not be orthonormal (Theorem 1.5) but V_s^T V_s must be invertible.
+ * stream  hipStream_t on which every later call of this system enqueues its work
+ *         (NULL = the null stream).
+ * On success *out owns device memory until afqmc_destroy. */
+AFQMC_API int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double* L_chol,
+                const double* phi_up, const double* phi_dn, void* stream, afqmc_sys* out);
+
+/* Device bytes of workspace that n_walkers walkers need (for admission by HBM footprint). */
+AFQMC_API int afqmc_workspace_bytes(afqmc_sys s, int32_t n_walkers, size_t* bytes);
+
+/* Sizes and energies of a system (host values, no device work). */
+AFQMC_API int afqmc_get_info(afqmc_sys s, afqmc_info* info);
+
+/* Start every walker at {Psi_I = Phi_T, W = 1, theta = 0} (Sec. II.C, Sec. III.E step 1):
+ * writes U, weight, walker_id = index, step = 0, and computes the overlap phase, E_L and
+ * the cached force-bias traces.  Asynchronous. */
+AFQMC_API int afqmc_walkers_init(afqmc_sys s, afqmc_walkers* w);
+
+/* Recompute, from the current U, everything cached per walker: arg_ovlp, log_ovlp, e_loc
+ * and the force-bias traces (Theorem 1.1-1.2, eq:precomputing2, eq:localenergy3).  Weights
+ * and step are untouched.  Used after writing U directly (restart, tests).  Asynchronous. */
+AFQMC_API int afqmc_measure(afqmc_sys s, afqmc_walkers* w);
+
+/* One step of the random walk for every walker with W > 0 (Sec. III.E), then w->step++.
+ * Asynchronous; allocates nothing. */
+AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
+
+/* Draw (or copy) the fields the next afqmc_step would use, into device x_out
+ * [n_walkers][n_chol] doubles.  Asynchronous. */
+AFQMC_API int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc_fields* f, double* x_out);
+
+/* Mixed-estimator sums over the walkers (eq:localenergy, theta = 0), reduced on the device
+ * in a fixed order, copied to the host, synchronizing the stream:
+ *   out[0] = sum_w W_w Re E_L^cap(Psi_w)   (eq:cap applied to Re E_L)
+ *   out[1] = sum_w W_w Im E_L(Psi_w)
+ *   out[2] = sum_w W_w
+ *   out[3] = number of walkers with W > 0
+ *   out[4] = status word (AFQMC_STATUS_* bits accumulated since setup or the last clear)
+ * Returns AFQMC_E_NUMERIC if no walker is alive or a sum is not finite. */
+AFQMC_API int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[5]);
+
+/* Read and clear the sticky status word (synchronizes the stream). */
+AFQMC_API int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear);
+
+/* Kernel timing with HIP events on the system's stream.  enable = 1 starts recording
+ * (and resets the totals), 0 stops.  afqmc_kernel_time returns the accumulated time in
+ * milliseconds and the number of launches of one kernel group, synchronizing the stream:
+ *   0 = local-energy contraction, 1 = overlap / inverse, 2 = fields and force bias,
+ *   3 = propagator build, 4 = Taylor propagation, 5 = QR, 6 = weights, 7 = comb,
+ *   8 = energy assembly. */
+AFQMC_API int afqmc_kernel_timing(afqmc_sys s, int enable);
+AFQMC_API int afqmc_kernel_time(afqmc_sys s, int kernel, double* ms, int64_t* launches);
+
+/* Free the device memory owned by the system. */
+AFQMC_API int afqmc_destroy(afqmc_sys s);
+
+AFQMC_API const char* afqmc_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFQMC_H */

@@ -1,0 +1,365 @@
+"""Plain FP64 phaseless AFQMC (test infrastructure only; see package docstring).
+
+Notation follows arXiv:1711.02242.  M orbitals, N_sigma electrons of spin
+sigma, N_g Cholesky vectors, s = sqrt(dtau).  A walker of spin sigma is the
+M x N_sigma matrix U_sigma (Sec. II.A, eq:SDdef); the trial is the real
+M x N_sigma matrix V_sigma (Sec. III.D.1).
+
+Readings taken where the paper leaves a choice (each is listed, with its
+reason, in the design notes of the repository):
+
+* two-body energy carries the 1/2 of eq:bo_ham2 (eq:localenergy2/3 print the
+  bracket without it);
+* v_g = i L_g (Sec. II.B.2) so the force bias is -i s sum_sigma tr(Lh Theta)
+  (eq:precomputing2) and the propagator exponent is i s sum (x - xbar) L;
+* symmetric Trotter split (eq:primitive) with the one-body halves applied
+  exactly, only the field exponent Taylor-expanded (Sec. III.D.2) to
+  ``n_taylor`` = 6 terms;
+* the weight uses the local energy of the walker before the move (eq:if_rle,
+  importance function expanded around the current walker) and
+  max(0, cos dtheta) with dtheta the phase of the overlap ratio;
+* local-energy cap |E_L - E_T| <= sqrt(C/dtau), force-bias modulus cap,
+  weight cap (eq:cap, App. B.1), with the trial energy E_T in place of the
+  growth-phase average;
+* comb resampling to a fixed population for the branching step (Sec. III.D.4).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# Setup (Sec. II.B.2, eq:mcd1; Sec. III.D.2, eq:precomputing2)
+# --------------------------------------------------------------------------
+
+@dataclass
+class Setup:
+    h0: float
+    h1: np.ndarray        # (M, M)
+    L: np.ndarray         # (N_g, M, M)
+    V: list               # per spin, (M, N_sigma) real trial orbitals
+    dtau: float
+    v0: np.ndarray        # (M, M)  one-body part after the Cholesky rewrite
+    Eh: np.ndarray        # (M, M)  exp(-dtau/2 v0)
+    Lh: list              # per spin, (N_g, N_sigma, M) half-rotated Cholesky V^T L_g
+    ht: list              # per spin, (N_sigma, M) half-rotated one-body V^T h1
+    E_T: float            # trial energy E_L(Phi_T, Phi_T)
+
+    @property
+    def M(self):
+        return self.h1.shape[0]
+
+    @property
+    def n_chol(self):
+        return self.L.shape[0]
+
+
+def one_body_v0(h1: np.ndarray, L: np.ndarray) -> np.ndarray:
+    """v0_pq = h_pq - 1/2 sum_r v_prrq with v_prrq = sum_g L^g_pr L^g_rq (eq:mcd1)."""
+    return h1 - 0.5 * np.einsum("gpr,grq->pq", L, L)
+
+
+def sym_expm(A: np.ndarray, c: float) -> np.ndarray:
+    """exp(c A) for a real symmetric matrix A, by its eigendecomposition."""
+    w, Q = np.linalg.eigh(A)
+    return (Q * np.exp(c * w)) @ Q.T
+
+
+def setup(h0, h1, L, phi_up, phi_dn, dtau, e_trial=None) -> Setup:
+    h1 = np.asarray(h1, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    V = [np.asarray(phi_up, dtype=np.float64), np.asarray(phi_dn, dtype=np.float64)]
+    v0 = one_body_v0(h1, L)
+    Eh = sym_expm(v0, -0.5 * dtau)
+    # Half rotation: (Lh_g)_rq = sum_p (V^dagger)_rp L^g_pq, V real (eq:precomputing2).
+    Lh = [np.einsum("pr,gpq->grq", Vs, L) for Vs in V]
+    ht = [Vs.T @ h1 for Vs in V]
+    S = Setup(h0=float(h0), h1=h1, L=L, V=V, dtau=float(dtau), v0=v0, Eh=Eh, Lh=Lh, ht=ht,
+              E_T=0.0)
+    if e_trial is None:
+        th = [overlap_theta(V[s], V[s].astype(np.complex128))[1] for s in range(2)]
+        e_trial = local_energy(S, th)[0].real
+    S.E_T = float(e_trial)
+    return S
+
+
+# --------------------------------------------------------------------------
+# Overlap and Green's function (Theorem 1.1-1.2; eq:precomputing)
+# --------------------------------------------------------------------------
+
+def overlap_theta(V: np.ndarray, U: np.ndarray):
+    """For one spin: (log det T, Theta) with T = V^dagger U and Theta = U T^{-1}.
+
+    <Phi|Psi> = prod_sigma det(V_sigma^dagger U_sigma) (Theorem 1.1) and
+    G_pq = (U T^{-1} V^dagger)_qp = (Theta V^dagger)_qp (Theorem 1.2, eq:precomputing).
+    The log determinant is returned as a complex number log|det| + i arg det.
+    """
+    T = V.conj().T @ U
+    sign, logabs = np.linalg.slogdet(T)
+    Theta = U @ np.linalg.inv(T)
+    return complex(logabs + 1j * np.angle(sign)), Theta
+
+
+def green_function(V: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """G_pq = <Phi| a+_p a_q |Psi> / <Phi|Psi> for one spin (Theorem 1.2, thm:1rdm)."""
+    T = V.conj().T @ U
+    return (U @ np.linalg.inv(T) @ V.conj().T).T
+
+
+# --------------------------------------------------------------------------
+# Local energy and force bias (eq:precomputing2, eq:localenergy2, eq:localenergy3)
+# --------------------------------------------------------------------------
+
+def local_energy(S: Setup, Theta: list):
+    """Local energy E_L = <Phi_T|H|Psi>/<Phi_T|Psi> and the traces t_g.
+
+    Omega^g_sigma = Lh^g_sigma Theta_sigma (N_sigma x N_sigma) for every g;
+    t_g = sum_sigma tr Omega^g_sigma (so <L_g>_m = t_g);
+    E_L = h0 + sum_sigma tr(ht_sigma Theta_sigma)
+          + 1/2 sum_g [ t_g^2 - sum_sigma tr(Omega^g_sigma Omega^g_sigma) ].
+    Returns (E_L complex, t of shape (N_g,) complex).
+    """
+    t = np.zeros(S.n_chol, dtype=np.complex128)
+    exch = 0.0 + 0.0j
+    e1 = 0.0 + 0.0j
+    for s in range(2):
+        if Theta[s].shape[1] == 0:
+            continue
+        Om = np.matmul(S.Lh[s], Theta[s])                     # (N_g, N, N)
+        t += np.trace(Om, axis1=1, axis2=2)
+        exch += np.sum(Om * Om.transpose(0, 2, 1))
+        e1 += np.trace(S.ht[s] @ Theta[s])
+    e2 = 0.5 * (np.sum(t * t) - exch)
+    return complex(S.h0 + e1 + e2), t
+
+
+def force_bias(t: np.ndarray, dtau: float, fb_cap: float) -> np.ndarray:
+    """xbar_g = -sqrt(dtau) <v_g>_m = -i sqrt(dtau) t_g (eq:fb, eq:precomputing2),
+    with its modulus capped at ``fb_cap`` keeping the phase (App. B.1)."""
+    xbar = -1j * math.sqrt(dtau) * t
+    mod = np.abs(xbar)
+    over = mod > fb_cap
+    xbar[over] *= fb_cap / mod[over]
+    return xbar
+
+
+# --------------------------------------------------------------------------
+# Propagation (Theorem 1.4; eq:primitive; Sec. III.D.2)
+# --------------------------------------------------------------------------
+
+def propagator_exponent(S: Setup, x: np.ndarray, xbar: np.ndarray) -> np.ndarray:
+    """A = i sqrt(dtau) sum_g (x_g - xbar_g) L^g, the matrix of sqrt(dtau) sum (x-xbar) v_g."""
+    return 1j * math.sqrt(S.dtau) * np.einsum("g,gpq->pq", x - xbar, S.L)
+
+
+def taylor_apply(A: np.ndarray, X: np.ndarray, n_taylor: int) -> np.ndarray:
+    """sum_{n=0}^{n_taylor} A^n X / n!, each term from the previous one as A term / n."""
+    Y = X.copy()
+    term = X
+    for n in range(1, n_taylor + 1):
+        term = A @ term / n
+        Y = Y + term
+    return Y
+
+
+def propagate(S: Setup, A: np.ndarray, U: np.ndarray, n_taylor: int) -> np.ndarray:
+    """U <- exp(-dtau/2 v0) T_n(A) exp(-dtau/2 v0) U for one spin (Thouless, Theorem 1.4)."""
+    return S.Eh @ taylor_apply(A, S.Eh @ U, n_taylor)
+
+
+# --------------------------------------------------------------------------
+# Re-orthonormalization (Sec. III.D.5; Theorem 1.5)
+# --------------------------------------------------------------------------
+
+def modified_gram_schmidt(U: np.ndarray):
+    """Orthonormalize the columns of U in order, subtracting the projection on each
+    earlier orthonormal column in turn.  Returns (Q, r) with U = Q R, R upper
+    triangular and r = diag(R) > 0, so det R = prod(r) is real and positive."""
+    M, N = U.shape
+    Q = U.astype(np.complex128).copy()
+    r = np.zeros(N)
+    for k in range(N):
+        v = Q[:, k].copy()
+        for j in range(k):
+            v = v - np.vdot(Q[:, j], v) * Q[:, j]
+        nrm = math.sqrt(float(np.vdot(v, v).real))
+        r[k] = nrm
+        Q[:, k] = v / nrm
+    return Q, r
+
+
+# --------------------------------------------------------------------------
+# Phaseless weight (eq:if_rle, eq:weight_update_2, eq:cap)
+# --------------------------------------------------------------------------
+
+def capped_energy(e_re, E_T: float, dtau: float, C: float):
+    """Re E_L bounded to E_T +- sqrt(C/dtau) (eq:cap with E_T for the reference energy)."""
+    half = math.sqrt(C / dtau)
+    return np.clip(e_re, E_T - half, E_T + half)
+
+
+def wrap_angle(a):
+    """Angle folded into (-pi, pi]."""
+    a = np.asarray(a, dtype=np.float64)
+    w = np.mod(a + np.pi, 2.0 * np.pi) - np.pi
+    return np.where(w == -np.pi, np.pi, w)
+
+
+def phaseless_weight(W, e_loc_old, arg_old, arg_new, dtau, E_T, C, w_max):
+    """W' = min(w_max, W exp(-dtau (Re E_L^cap(old) - E_T)) max(0, cos(arg_new - arg_old)))."""
+    e_cap = capped_energy(np.real(e_loc_old), E_T, dtau, C)
+    proj = np.maximum(0.0, np.cos(np.asarray(arg_new) - np.asarray(arg_old)))
+    Wn = W * np.exp(-dtau * (e_cap - E_T)) * proj
+    return np.minimum(Wn, w_max)
+
+
+# --------------------------------------------------------------------------
+# Population control (Sec. III.D.4): comb / systematic resampling
+# --------------------------------------------------------------------------
+
+def comb(W: np.ndarray, u: float):
+    """Comb resampling to the same population size.
+
+    Positions (u + j) * (sum W / n), j = 0..n-1, fall into the half-open
+    cumulative-weight intervals [C_{i-1}, C_i) of the walkers in index order;
+    walker j of the new population copies the walker whose interval holds
+    position j, and every new weight is sum W / n.  Returns (parent, W_new).
+    """
+    n = W.size
+    C = np.cumsum(W)
+    total = C[-1]
+    if not total > 0.0:
+        raise ValueError("comb: no walker has positive weight")
+    pos = (u + np.arange(n, dtype=np.float64)) * (total / n)
+    parent = np.searchsorted(C, pos, side="right")
+    last_alive = int(np.nonzero(W > 0)[0][-1])
+    parent = np.minimum(parent, last_alive)
+    return parent.astype(np.int64), np.full(n, total / n)
+
+
+# --------------------------------------------------------------------------
+# Walker population and the step (Sec. III.E)
+# --------------------------------------------------------------------------
+
+@dataclass
+class Params:
+    dtau: float
+    n_taylor: int = 6
+    qr_period: int = 5
+    pop_period: int = 5
+    el_cap_C: float = 2.0
+    w_max: float | None = None
+    fb_cap: float = 1.0
+
+    def wmax(self, n_walkers: int) -> float:
+        return self.w_max if self.w_max is not None else max(100.0, n_walkers / 10.0)
+
+
+@dataclass
+class Walkers:
+    U: list               # per spin, (n_w, M, N_sigma) complex128
+    W: np.ndarray         # (n_w,)
+    arg: np.ndarray       # (n_w,) arg <Phi_T|Psi>, in (-pi, pi]
+    logabs: np.ndarray    # (n_w,) log |<Phi_T|Psi>| (diagnostic)
+    e_loc: np.ndarray     # (n_w,) complex E_L of the current walker
+    t: np.ndarray         # (n_w, N_g) complex traces of the current walker
+    walker_id: np.ndarray  # (n_w,) int64
+    step: int = 0
+
+    @property
+    def n(self):
+        return self.W.size
+
+
+def measure(S: Setup, U_up: np.ndarray, U_dn: np.ndarray):
+    """Overlap phase, log|overlap|, E_L and t for one walker."""
+    lg_up, th_up = overlap_theta(S.V[0], U_up)
+    lg_dn, th_dn = overlap_theta(S.V[1], U_dn)
+    lg = lg_up + lg_dn
+    e, t = local_energy(S, [th_up, th_dn])
+    return float(wrap_angle(lg.imag)), float(lg.real), e, t
+
+
+def init_walkers(S: Setup, n_walkers: int, U_up=None, U_dn=None) -> Walkers:
+    """Every walker starts as {Psi_I = Phi_T, W = 1, theta = 0} (Sec. II.C, Sec. III.E)
+    unless explicit determinants are given."""
+    if U_up is None:
+        U_up = np.repeat(S.V[0][None].astype(np.complex128), n_walkers, axis=0)
+    if U_dn is None:
+        U_dn = np.repeat(S.V[1][None].astype(np.complex128), n_walkers, axis=0)
+    U_up = np.array(U_up, dtype=np.complex128)
+    U_dn = np.array(U_dn, dtype=np.complex128)
+    n = U_up.shape[0]
+    arg = np.zeros(n)
+    logabs = np.zeros(n)
+    e = np.zeros(n, dtype=np.complex128)
+    t = np.zeros((n, S.n_chol), dtype=np.complex128)
+    for w in range(n):
+        arg[w], logabs[w], e[w], t[w] = measure(S, U_up[w], U_dn[w])
+    return Walkers(U=[U_up, U_dn], W=np.ones(n), arg=arg, logabs=logabs, e_loc=e, t=t,
+                   walker_id=np.arange(n, dtype=np.int64), step=0)
+
+
+def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
+         info: dict | None = None) -> Walkers:
+    """One step of the random walk for every walker (Sec. III.E), in place.
+
+    ``x`` (n_w, N_g) are the auxiliary fields drawn for this step; ``u_comb``
+    is the comb's uniform, needed when population control is due after it.
+    Walkers with zero weight are skipped until population control replaces them.
+    """
+    k = wk.step
+    n = wk.n
+    wmax = P.wmax(n)
+    do_qr = P.qr_period > 0 and (k + 1) % P.qr_period == 0
+    do_pop = P.pop_period > 0 and (k + 1) % P.pop_period == 0
+    for w in range(n):
+        if not wk.W[w] > 0.0:
+            continue
+        xbar = force_bias(wk.t[w], P.dtau, P.fb_cap)
+        A = propagator_exponent(S, x[w], xbar)
+        U_up = propagate(S, A, wk.U[0][w], P.n_taylor)
+        U_dn = propagate(S, A, wk.U[1][w], P.n_taylor)
+        if do_qr:
+            U_up = modified_gram_schmidt(U_up)[0]
+            U_dn = modified_gram_schmidt(U_dn)[0]
+        arg_new, logabs_new, e_new, t_new = measure(S, U_up, U_dn)
+        wk.W[w] = phaseless_weight(wk.W[w], wk.e_loc[w], wk.arg[w], arg_new, P.dtau, S.E_T,
+                                   P.el_cap_C, wmax)
+        wk.U[0][w] = U_up
+        wk.U[1][w] = U_dn
+        wk.arg[w] = arg_new
+        wk.logabs[w] = logabs_new
+        wk.e_loc[w] = e_new
+        wk.t[w] = t_new
+    if do_pop:
+        if u_comb is None:
+            raise ValueError("population control is due: u_comb is required")
+        parent, Wn = comb(wk.W, u_comb)
+        if info is not None:
+            info["parent"] = parent
+        for arr in (wk.U[0], wk.U[1]):
+            arr[:] = arr[parent]
+        wk.arg = wk.arg[parent]
+        wk.logabs = wk.logabs[parent]
+        wk.e_loc = wk.e_loc[parent]
+        wk.t = wk.t[parent]
+        wk.W = Wn
+        wk.walker_id = np.arange(n, dtype=np.int64)
+    wk.step = k + 1
+    return wk
+
+
+def mixed_energy(S: Setup, P: Params, wk: Walkers):
+    """Mixed estimator sum_w W_w Re E_L^cap(Psi_w) / sum_w W_w (eq:localenergy, theta = 0)
+    plus the raw sums: (E_mix, sum W Re E_cap, sum W Im E_L, sum W, n_alive)."""
+    e_cap = capped_energy(wk.e_loc.real, S.E_T, P.dtau, P.el_cap_C)
+    sw = float(np.sum(wk.W))
+    swe = float(np.sum(wk.W * e_cap))
+    swi = float(np.sum(wk.W * wk.e_loc.imag))
+    alive = int(np.count_nonzero(wk.W > 0))
+    return swe / sw, swe, swi, sw, alive

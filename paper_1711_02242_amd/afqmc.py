@@ -1,0 +1,197 @@
+"""Python binding of the HIP AFQMC library: argument marshalling only.
+
+Every step of the path runs in the library's kernels.  PyTorch supplies device
+memory (walker arrays and workspace as CUDA/ROCm tensors) and the stream.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class System:
+    """A Hamiltonian in Cholesky form plus a single-determinant trial, resident on the GPU.
+
+    h1 (M, M), L (n_chol, M, M), phi_up (M, n_up), phi_dn (M, n_dn): real float64 host arrays.
+    """
+
+    def __init__(self, h0, h1, L_chol, phi_up, phi_dn, *, dtau: float, precision: str = "fp64",
+                 n_taylor: int = 6, qr_period: int = 5, pop_period: int = 5, el_cap_C: float = 2.0,
+                 w_max: float | None = None, fb_cap: float = 1.0, e_trial: float | None = None,
+                 stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise L.AfqmcError("no GPU visible: the AFQMC library runs on the GPU only")
+        self.lib = L.load()
+        h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        M = h1.shape[0]
+        L_chol = np.ascontiguousarray(L_chol, dtype=np.float64).reshape(-1, M, M)
+        phi_up = np.ascontiguousarray(phi_up, dtype=np.float64).reshape(M, -1)
+        phi_dn = np.ascontiguousarray(phi_dn, dtype=np.float64).reshape(M, -1)
+        self.M, self.n_up, self.n_dn, self.n_chol = M, phi_up.shape[1], phi_dn.shape[1], L_chol.shape[0]
+        self.ntot = self.n_up + self.n_dn
+        self.dtau = float(dtau)
+        self.precision = precision
+        p = L.Params(M=M, n_up=self.n_up, n_dn=self.n_dn, n_chol=self.n_chol, dtau=self.dtau,
+                     e_trial=math.nan if e_trial is None else float(e_trial), n_taylor=n_taylor,
+                     qr_period=qr_period, pop_period=pop_period,
+                     precision=L.PRECISIONS[precision], el_cap_C=el_cap_C,
+                     w_max=math.nan if w_max is None else float(w_max), fb_cap=fb_cap, flags=0,
+                     reserved=0)
+        self.params = p
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        handle = C.c_void_p()
+        rc = self.lib.afqmc_setup(C.byref(p), float(h0), h1.ctypes.data, L_chol.ctypes.data,
+                                  phi_up.ctypes.data, phi_dn.ctypes.data,
+                                  C.c_void_p(_stream_handle(self.stream)), C.byref(handle))
+        L.check(rc, "afqmc_setup")
+        self.handle = handle
+        info = L.InfoC()
+        L.check(self.lib.afqmc_get_info(self.handle, C.byref(info)), "afqmc_get_info")
+        self.e_trial = info.e_trial
+        self.e_hf = info.e_hf
+        self.device_bytes = info.device_bytes
+
+    @classmethod
+    def from_synthetic(cls, s, **kw):
+        return cls(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.check(self.lib.afqmc_destroy(self.handle), "afqmc_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- walkers
+    def workspace_bytes(self, n_walkers: int) -> int:
+        b = C.c_size_t()
+        L.check(self.lib.afqmc_workspace_bytes(self.handle, int(n_walkers), C.byref(b)),
+                "afqmc_workspace_bytes")
+        return int(b.value)
+
+    def walkers(self, n_walkers: int) -> "Walkers":
+        return Walkers(self, n_walkers)
+
+    def init(self, wk: "Walkers") -> None:
+        L.check(self.lib.afqmc_walkers_init(self.handle, wk.c_ref()), "afqmc_walkers_init")
+        wk.sync_from_c()
+
+    def measure(self, wk: "Walkers") -> None:
+        L.check(self.lib.afqmc_measure(self.handle, wk.c_ref()), "afqmc_measure")
+
+    def _fields(self, seed, job_id, x, u_comb):
+        xp = None
+        if x is not None:
+            xp = C.c_void_p(int(x.data_ptr()))
+        return L.FieldsC(seed=int(seed), job_id=int(job_id), x=xp,
+                         u_comb=math.nan if u_comb is None else float(u_comb))
+
+    def step(self, wk: "Walkers", seed: int = 0, job_id: int = 0, x=None, u_comb=None) -> None:
+        """One step of the random walk.  ``x``: optional device tensor (n_walkers, n_chol) float64."""
+        if x is not None:
+            torch = _torch()
+            assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous()
+            assert tuple(x.shape) == (wk.n, self.n_chol)
+        f = self._fields(seed, job_id, x, u_comb)
+        L.check(self.lib.afqmc_step(self.handle, wk.c_ref(), C.byref(f)), "afqmc_step")
+        wk.sync_from_c()
+
+    def fields_draw(self, wk: "Walkers", seed: int = 0, job_id: int = 0):
+        torch = _torch()
+        out = torch.empty((wk.n, self.n_chol), dtype=torch.float64, device="cuda")
+        f = self._fields(seed, job_id, None, None)
+        L.check(self.lib.afqmc_fields_draw(self.handle, wk.c_ref(), C.byref(f),
+                                           C.c_void_p(int(out.data_ptr()))), "afqmc_fields_draw")
+        return out
+
+    def energy(self, wk: "Walkers", check: bool = True):
+        """(sum W Re E_cap, sum W Im E, sum W, n_alive, status) -- synchronizes the stream."""
+        out = (C.c_double * 5)()
+        rc = self.lib.afqmc_energy(self.handle, wk.c_ref(), out)
+        if check:
+            L.check(rc, "afqmc_energy")
+        return out[0], out[1], out[2], int(out[3]), int(out[4])
+
+    def mixed_energy(self, wk: "Walkers") -> float:
+        a, _, c, _, _ = self.energy(wk)
+        return a / c
+
+    def status(self, clear: bool = False) -> int:
+        st = C.c_uint32()
+        L.check(self.lib.afqmc_get_status(self.handle, C.byref(st), int(clear)), "afqmc_get_status")
+        return int(st.value)
+
+    # ---------------------------------------------------------------- timing
+    def kernel_timing(self, enable: bool) -> None:
+        L.check(self.lib.afqmc_kernel_timing(self.handle, int(enable)), "afqmc_kernel_timing")
+
+    def kernel_time(self, group: str | int):
+        k = L.KERNEL_GROUPS.index(group) if isinstance(group, str) else int(group)
+        ms = C.c_double()
+        n = C.c_int64()
+        L.check(self.lib.afqmc_kernel_time(self.handle, k, C.byref(ms), C.byref(n)),
+                "afqmc_kernel_time")
+        return ms.value, int(n.value)
+
+
+class Walkers:
+    """Caller-owned device arrays of a walker population (torch tensors on the GPU)."""
+
+    def __init__(self, system: System, n_walkers: int):
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        n = int(n_walkers)
+        self.n = n
+        self.system = system
+        self.U = torch.zeros((n, system.ntot, system.M), dtype=torch.complex128, device=dev)
+        self.weight = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.arg_ovlp = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.log_ovlp = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.e_loc = torch.zeros(n, dtype=torch.complex128, device=dev)
+        self.walker_id = torch.arange(n, dtype=torch.int64, device=dev)
+        nb = system.workspace_bytes(n)
+        self._ws_raw = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-int(self._ws_raw.data_ptr())) % 256
+        self.workspace = self._ws_raw[off:off + nb]
+        self.step = 0
+        self._c = L.WalkersC()
+
+    def c_ref(self):
+        c = self._c
+        c.n_walkers = self.n
+        c.reserved = 0
+        c.U = int(self.U.data_ptr())
+        c.weight = int(self.weight.data_ptr())
+        c.arg_ovlp = int(self.arg_ovlp.data_ptr())
+        c.log_ovlp = int(self.log_ovlp.data_ptr())
+        c.e_loc = int(self.e_loc.data_ptr())
+        c.walker_id = int(self.walker_id.data_ptr())
+        c.workspace = int(self.workspace.data_ptr())
+        c.workspace_bytes = int(self.workspace.numel())
+        c.step = int(self.step)
+        return C.byref(c)
+
+    def sync_from_c(self):
+        self.step = int(self._c.step)

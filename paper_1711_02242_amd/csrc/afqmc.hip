@@ -1,0 +1,735 @@
+// Host side of the AFQMC C ABI (include/afqmc.h): setup precompute, workspace
+// layout, and the launch sequence of one walker step (arXiv:1711.02242, Sec. III.E).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/afqmc.h"
+#include "common.hpp"
+#include "kernels_fp64.hpp"
+#include "kernels_mfma.hpp"
+
+namespace {
+
+enum { KG_CONTRACT = 0, KG_OVERLAP, KG_FIELDS, KG_ABUILD, KG_PROP, KG_QR, KG_WEIGHT, KG_COMB,
+       KG_ASSEMBLE, KG_COUNT };
+
+struct TimedLaunch {
+  int group;
+  hipEvent_t a, b;
+};
+
+struct WsLayout {
+  size_t thetaT, tcur, tpart, exch, e1, logdet, wflag, enew, y, A, X0, X1, Y, parent, csum,
+      wnew, asnap, lsnap, esum, thetaP, total;
+};
+
+}  // namespace
+
+struct afqmc_sys_s {
+  afqmc_params p;
+  int M, nup, ndn, ntot, G;
+  double h0, e_trial, e_hf, s;
+  hipStream_t stream;
+  int device;
+  // device, library-owned
+  double* L = nullptr;     // [G][M][M]
+  double* Eh = nullptr;    // [M][M]
+  double* V = nullptr;     // [ntot][M]
+  double* Lh = nullptr;    // [G][ntot][M]
+  double* ht = nullptr;    // [ntot][M]
+  unsigned* status = nullptr;
+  MfmaTables mt;           // packed low-precision copies for the MFMA contraction
+  size_t device_bytes = 0;
+  // timing
+  bool timing = false;
+  std::vector<TimedLaunch> launches;
+  double acc_ms[KG_COUNT] = {0};
+  int64_t acc_n[KG_COUNT] = {0};
+};
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+WsLayout layout(const afqmc_sys_s* S, size_t nw) {
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += al256(bytes);
+    return r;
+  };
+  const size_t M = S->M, G = S->G, nt = S->ntot;
+  L.thetaT = take(nw * nt * M * 16);
+  L.tcur = take(nw * G * 16);
+  L.tpart = take(nw * 2 * G * 16);
+  L.exch = take(nw * 2 * 16);
+  L.e1 = take(nw * 2 * 16);
+  L.logdet = take(nw * 2 * 16);
+  L.wflag = take(nw * 2 * 4);
+  L.enew = take(nw * 16);
+  L.y = take(nw * G * 16);
+  L.A = take(nw * M * M * 16);
+  L.X0 = take(nw * nt * M * 16);
+  L.X1 = take(nw * nt * M * 16);
+  L.Y = take(nw * nt * M * 16);
+  L.parent = take(nw * 4);
+  L.csum = take(nw * 8);
+  L.wnew = take(64);
+  L.asnap = take(nw * 8);
+  L.lsnap = take(nw * 8);
+  L.esum = take(64);
+  L.thetaP = take(mfma_theta_bytes(S->mt, nw));
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return AFQMC_E_HIP;       \
+  } while (0)
+
+// Event bracket of one launch group when timing is on.
+struct Timer {
+  afqmc_sys_s* S;
+  int group;
+  hipEvent_t a{}, b{};
+  Timer(afqmc_sys_s* s, int g) : S(s), group(g) {
+    if (S->timing) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, S->stream);
+    }
+  }
+  ~Timer() {
+    if (S->timing) {
+      hipEventRecord(b, S->stream);
+      S->launches.push_back(TimedLaunch{group, a, b});
+    }
+  }
+};
+
+void flush_timing(afqmc_sys_s* S) {
+  if (S->launches.empty()) return;
+  (void)hipStreamSynchronize(S->stream);
+  for (auto& t : S->launches) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, t.a, t.b);
+    S->acc_ms[t.group] += ms;
+    S->acc_n[t.group] += 1;
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  S->launches.clear();
+}
+
+// exp(c A) for a real symmetric M x M matrix by scaling and squaring of the Taylor series.
+void host_expm_sym(const std::vector<double>& A, int M, double c, std::vector<double>& out) {
+  double nrm = 0.0;
+  for (int i = 0; i < M; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < M; ++j) r += fabs(A[(size_t)i * M + j]);
+    nrm = fmax(nrm, r);
+  }
+  nrm *= fabs(c);
+  int sq = 0;
+  while (nrm > 0.25) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double cs = c / std::ldexp(1.0, sq);
+  std::vector<double> term((size_t)M * M, 0.0), next((size_t)M * M), res((size_t)M * M, 0.0);
+  for (int i = 0; i < M; ++i) term[(size_t)i * M + i] = 1.0;
+  res = term;
+  for (int n = 1; n < 40; ++n) {
+    double mx = 0.0;
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < M; ++k) acc += A[(size_t)i * M + k] * term[(size_t)k * M + j];
+        next[(size_t)i * M + j] = acc * cs / n;
+        mx = fmax(mx, fabs(next[(size_t)i * M + j]));
+      }
+    term.swap(next);
+    for (size_t e = 0; e < res.size(); ++e) res[e] += term[e];
+    if (mx < 1e-300 || mx < 1e-19) break;
+  }
+  for (int q = 0; q < sq; ++q) {
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < M; ++k) acc += res[(size_t)i * M + k] * res[(size_t)k * M + j];
+        next[(size_t)i * M + j] = acc;
+      }
+    res.swap(next);
+  }
+  for (int i = 0; i < M; ++i)
+    for (int j = i + 1; j < M; ++j) {
+      const double v = 0.5 * (res[(size_t)i * M + j] + res[(size_t)j * M + i]);
+      res[(size_t)i * M + j] = res[(size_t)j * M + i] = v;
+    }
+  out = res;
+}
+
+// Inverse of a small real matrix by Gauss-Jordan with partial pivoting; false if singular.
+bool host_inverse(std::vector<double>& a, int n) {
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(a[(size_t)i * n + k]) > fabs(a[(size_t)piv * n + k])) piv = i;
+    if (!(fabs(a[(size_t)piv * n + k]) > 0.0)) return false;
+    for (int j = 0; j < n; ++j) {
+      std::swap(a[(size_t)k * n + j], a[(size_t)piv * n + j]);
+      std::swap(inv[(size_t)k * n + j], inv[(size_t)piv * n + j]);
+    }
+    const double d = a[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)k * n + j] /= d;
+      inv[(size_t)k * n + j] /= d;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = a[(size_t)i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)i * n + j] -= f * a[(size_t)k * n + j];
+        inv[(size_t)i * n + j] -= f * inv[(size_t)k * n + j];
+      }
+    }
+  }
+  a = inv;
+  return true;
+}
+
+template <typename T>
+int dev_upload(afqmc_sys_s* S, T** dst, const T* src, size_t count) {
+  if (count == 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T)) != hipSuccess) return AFQMC_E_NOMEM;
+  S->device_bytes += count * sizeof(T);
+  if (src) HIPCHK(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return AFQMC_OK;
+}
+
+void free_sys(afqmc_sys_s* S) {
+  if (!S) return;
+  for (auto& t : S->launches) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  hipFree(S->L);
+  hipFree(S->Eh);
+  hipFree(S->V);
+  hipFree(S->Lh);
+  hipFree(S->ht);
+  hipFree(S->status);
+  mfma_free_tables(S->mt);
+  delete S;
+}
+
+int check_walkers(const afqmc_sys_s* S, const afqmc_walkers* w) {
+  if (!w || w->n_walkers < 1 || !w->U || !w->weight || !w->arg_ovlp || !w->log_ovlp ||
+      !w->e_loc || !w->walker_id || !w->workspace)
+    return AFQMC_E_ARG;
+  if ((reinterpret_cast<uintptr_t>(w->workspace) & 255u) != 0) return AFQMC_E_ARG;
+  if (w->workspace_bytes < layout(S, (size_t)w->n_walkers).total) return AFQMC_E_NOMEM;
+  return AFQMC_OK;
+}
+
+int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, int check_weight) {
+  Timer tm(S, KG_OVERLAP);
+  const int nmax = std::max(S->nup, S->ndn);
+  const size_t shm = (size_t)nmax * (nmax + 1) * 16 + 64 * 4 + 8 * 8;
+  dim3 grid(w->n_walkers, 2);
+  void* ws = w->workspace;
+#define OVL(NM)                                                                                \
+  do {                                                                                         \
+    (void)hipFuncSetAttribute((const void*)k_overlap_theta<NM>,                                      \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                 \
+    hipLaunchKernelGGL(k_overlap_theta<NM>, grid, dim3(256), shm, S->stream, S->M, S->nup,      \
+                       S->ndn, S->V, S->ht, (const cd*)w->U, w->weight, check_weight,          \
+                       at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet), at<cd>(ws, L.e1),           \
+                       at<unsigned>(ws, L.wflag));                                            \
+  } while (0)
+  if (nmax <= 8)
+    OVL(8);
+  else if (nmax <= 16)
+    OVL(16);
+  else if (nmax <= 32)
+    OVL(32);
+  else
+    OVL(64);
+#undef OVL
+  HIPCHK(hipGetLastError());
+  return AFQMC_OK;
+}
+
+int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
+  void* ws = w->workspace;
+  if (S->p.precision == AFQMC_FP64 || !S->mt.enabled) {
+    Timer tm(S, KG_CONTRACT);
+    const int nmax = std::max(S->nup, S->ndn);
+    const size_t shm = (size_t)nmax * (S->M + 1) * 16 + (size_t)nmax * (nmax + 1) * 16 + 64;
+    (void)hipFuncSetAttribute((const void*)k_contract_fp64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shm);
+    hipLaunchKernelGGL(k_contract_fp64, dim3(w->n_walkers, 2), dim3(256), shm, S->stream, S->M,
+                       S->nup, S->ndn, S->G, S->Lh, at<cd>(ws, L.thetaT), w->weight,
+                       at<cd>(ws, L.tpart), at<cd>(ws, L.exch));
+    HIPCHK(hipGetLastError());
+  } else {
+    {
+      Timer tm(S, KG_OVERLAP);
+      HIPCHK(mfma_pack_theta(S->mt, S->stream, w->n_walkers, S->M, S->nup, S->ndn,
+                             at<cd>(ws, L.thetaT), w->weight, at<void>(ws, L.thetaP)));
+    }
+    Timer tm(S, KG_CONTRACT);
+    HIPCHK(mfma_contract(S->mt, S->stream, w->n_walkers, S->G, at<void>(ws, L.thetaP), w->weight,
+                         at<cd>(ws, L.tpart), at<cd>(ws, L.exch)));
+  }
+  {
+    Timer tm(S, KG_ASSEMBLE);
+    hipLaunchKernelGGL(k_energy_assemble, dim3(w->n_walkers), dim3(256), 0, S->stream, S->G, S->h0,
+                       at<cd>(ws, L.tpart), at<cd>(ws, L.exch), at<cd>(ws, L.e1), w->weight, 1,
+                       at<cd>(ws, L.tcur), at<cd>(ws, L.enew));
+    HIPCHK(hipGetLastError());
+  }
+  return AFQMC_OK;
+}
+
+int do_measure(afqmc_sys_s* S, afqmc_walkers* w) {
+  const WsLayout L = layout(S, (size_t)w->n_walkers);
+  void* ws = w->workspace;
+  int rc = launch_overlap(S, w, L, 1);
+  if (rc) return rc;
+  rc = launch_contract(S, w, L);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_measure_finish, dim3((w->n_walkers + 255) / 256), dim3(256), 0, S->stream,
+                     w->n_walkers, at<cd>(ws, L.logdet), at<unsigned>(ws, L.wflag),
+                     at<cd>(ws, L.enew), w->weight, w->arg_ovlp, w->log_ovlp, (cd*)w->e_loc,
+                     S->status);
+  HIPCHK(hipGetLastError());
+  return AFQMC_OK;
+}
+
+int launch_fields(afqmc_sys_s* S, const afqmc_walkers* w, const afqmc_fields* f, const WsLayout& L,
+                  double* xout) {
+  Timer tm(S, KG_FIELDS);
+  const int nblk = (S->G + 3) / 4;
+  const long n = (long)w->n_walkers * nblk;
+  if (n == 0) return AFQMC_OK;
+  void* ws = w->workspace;
+  hipLaunchKernelGGL(k_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S->stream,
+                     w->n_walkers, S->G, S->s, S->p.fb_cap, at<cd>(ws, L.tcur), w->weight,
+                     w->walker_id, f->seed, f->job_id, w->step, f->x, at<cd>(ws, L.y), xout,
+                     S->status);
+  HIPCHK(hipGetLastError());
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* afqmc_error_string(int code) {
+  switch (code) {
+    case AFQMC_OK: return "ok";
+    case AFQMC_E_ARG: return "invalid argument";
+    case AFQMC_E_UNSUPPORTED: return "unsupported precision or size";
+    case AFQMC_E_SINGULAR: return "trial overlap matrix is singular";
+    case AFQMC_E_NOMEM: return "out of device memory or workspace too small";
+    case AFQMC_E_HIP: return "HIP runtime error";
+    case AFQMC_E_NUMERIC: return "no live walker or non-finite estimator";
+    case AFQMC_E_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double* L_chol,
+                const double* phi_up, const double* phi_dn, void* stream, afqmc_sys* out) {
+  if (!p || !h1 || !out) return AFQMC_E_ARG;
+  *out = nullptr;
+  const int M = p->M, nup = p->n_up, ndn = p->n_dn, G = p->n_chol;
+  if (M < 1 || nup < 0 || ndn < 0 || nup > M || ndn > M || nup + ndn < 1 || G < 0)
+    return AFQMC_E_ARG;
+  if (!(p->dtau > 0.0) || p->n_taylor < 1 || p->n_taylor > 20 || p->qr_period < 0 ||
+      p->pop_period < 0 || !(p->el_cap_C > 0.0) || !(p->fb_cap > 0.0) || p->flags != 0)
+    return AFQMC_E_ARG;
+  if ((G > 0 && !L_chol) || (nup > 0 && !phi_up) || (ndn > 0 && !phi_dn)) return AFQMC_E_ARG;
+  if (p->precision < AFQMC_FP64 || p->precision > AFQMC_BF16X3) return AFQMC_E_UNSUPPORTED;
+  if (std::max(nup, ndn) > 64) return AFQMC_E_UNSUPPORTED;
+  // symmetry checks
+  double hmax = 0.0, hasym = 0.0;
+  for (int i = 0; i < M; ++i)
+    for (int j = 0; j < M; ++j) {
+      hmax = fmax(hmax, fabs(h1[(size_t)i * M + j]));
+      hasym = fmax(hasym, fabs(h1[(size_t)i * M + j] - h1[(size_t)j * M + i]));
+      if (!std::isfinite(h1[(size_t)i * M + j])) return AFQMC_E_ARG;
+    }
+  if (hasym > 1e-12 * fmax(1.0, hmax)) return AFQMC_E_ARG;
+  for (int g = 0; g < G; ++g) {
+    const double* Lg = L_chol + (size_t)g * M * M;
+    double lmax = 0.0, lasym = 0.0;
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) {
+        if (!std::isfinite(Lg[(size_t)i * M + j])) return AFQMC_E_ARG;
+        lmax = fmax(lmax, fabs(Lg[(size_t)i * M + j]));
+        lasym = fmax(lasym, fabs(Lg[(size_t)i * M + j] - Lg[(size_t)j * M + i]));
+      }
+    if (lasym > 1e-12 * fmax(1.0, lmax)) return AFQMC_E_ARG;
+  }
+
+  afqmc_sys_s* S = new (std::nothrow) afqmc_sys_s();
+  if (!S) return AFQMC_E_NOMEM;
+  S->p = *p;
+  S->M = M;
+  S->nup = nup;
+  S->ndn = ndn;
+  S->ntot = nup + ndn;
+  S->G = G;
+  S->h0 = h0;
+  S->s = sqrt(p->dtau);
+  S->stream = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetDevice(&S->device);
+  const int nt = S->ntot;
+
+  // v0 = h1 - 1/2 sum_g L^g L^g  (eq:mcd1)
+  std::vector<double> v0(h1, h1 + (size_t)M * M);
+  for (int g = 0; g < G; ++g) {
+    const double* Lg = L_chol + (size_t)g * M * M;
+    for (int i = 0; i < M; ++i)
+      for (int k = 0; k < M; ++k) {
+        const double a = 0.5 * Lg[(size_t)i * M + k];
+        if (a == 0.0) continue;
+        const double* row = Lg + (size_t)k * M;
+        double* dst = v0.data() + (size_t)i * M;
+        for (int j = 0; j < M; ++j) dst[j] -= a * row[j];
+      }
+  }
+  for (int i = 0; i < M; ++i)
+    for (int j = i + 1; j < M; ++j) {
+      const double v = 0.5 * (v0[(size_t)i * M + j] + v0[(size_t)j * M + i]);
+      v0[(size_t)i * M + j] = v0[(size_t)j * M + i] = v;
+    }
+  std::vector<double> Eh;
+  host_expm_sym(v0, M, -0.5 * p->dtau, Eh);
+
+  // Trial orbitals as rows: V[c][p] = (V_s)_{p, c'}
+  std::vector<double> Vr((size_t)nt * M);
+  for (int c = 0; c < nup; ++c)
+    for (int q = 0; q < M; ++q) Vr[(size_t)c * M + q] = phi_up[(size_t)q * nup + c];
+  for (int c = 0; c < ndn; ++c)
+    for (int q = 0; q < M; ++q) Vr[(size_t)(nup + c) * M + q] = phi_dn[(size_t)q * ndn + c];
+  // Half rotation (eq:precomputing2): Lh[g][c][q] = sum_p V[c][p] L^g_pq; ht[c][q] = sum_p V[c][p] h_pq
+  std::vector<double> Lh((size_t)G * nt * M, 0.0), ht((size_t)nt * M, 0.0);
+  for (int g = 0; g < G; ++g) {
+    const double* Lg = L_chol + (size_t)g * M * M;
+    for (int c = 0; c < nt; ++c) {
+      double* dst = Lh.data() + ((size_t)g * nt + c) * M;
+      const double* vc = Vr.data() + (size_t)c * M;
+      for (int q = 0; q < M; ++q) {
+        const double a = vc[q];
+        if (a == 0.0) continue;
+        const double* row = Lg + (size_t)q * M;
+        for (int j = 0; j < M; ++j) dst[j] += a * row[j];
+      }
+    }
+  }
+  for (int c = 0; c < nt; ++c)
+    for (int q = 0; q < M; ++q) {
+      const double a = Vr[(size_t)c * M + q];
+      for (int j = 0; j < M; ++j) ht[(size_t)c * M + j] += a * h1[(size_t)q * M + j];
+    }
+
+  // E_HF = E_L(Phi_T, Phi_T): Theta_s = V_s (V_s^T V_s)^{-1} (real), then eq:localenergy3.
+  {
+    std::vector<double> th((size_t)nt * M, 0.0);  // rows of Theta^T
+    for (int s = 0; s < 2; ++s) {
+      const int N = s == 0 ? nup : ndn, off = s == 0 ? 0 : nup;
+      if (N == 0) continue;
+      std::vector<double> T((size_t)N * N, 0.0);
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+          double acc = 0.0;
+          for (int q = 0; q < M; ++q) acc += Vr[(size_t)(off + i) * M + q] * Vr[(size_t)(off + j) * M + q];
+          T[(size_t)i * N + j] = acc;
+        }
+      if (!host_inverse(T, N)) {
+        delete S;
+        return AFQMC_E_SINGULAR;
+      }
+      // Theta = V T^{-1}: Theta^T[c][q] = sum_i Tinv[i][c] V[i][q]
+      for (int c = 0; c < N; ++c)
+        for (int q = 0; q < M; ++q) {
+          double acc = 0.0;
+          for (int i = 0; i < N; ++i) acc += T[(size_t)i * N + c] * Vr[(size_t)(off + i) * M + q];
+          th[(size_t)(off + c) * M + q] = acc;
+        }
+    }
+    double e1 = 0.0, jsum = 0.0, xsum = 0.0;
+    for (int c = 0; c < nt; ++c)
+      for (int q = 0; q < M; ++q) e1 += ht[(size_t)c * M + q] * th[(size_t)c * M + q];
+    std::vector<double> om;
+    for (int g = 0; g < G; ++g) {
+      double t = 0.0;
+      for (int s = 0; s < 2; ++s) {
+        const int N = s == 0 ? nup : ndn, off = s == 0 ? 0 : nup;
+        om.assign((size_t)N * N, 0.0);
+        for (int r = 0; r < N; ++r)
+          for (int c = 0; c < N; ++c) {
+            double acc = 0.0;
+            const double* lr = Lh.data() + ((size_t)g * nt + off + r) * M;
+            const double* tc = th.data() + (size_t)(off + c) * M;
+            for (int q = 0; q < M; ++q) acc += lr[q] * tc[q];
+            om[(size_t)r * N + c] = acc;
+          }
+        for (int r = 0; r < N; ++r) {
+          t += om[(size_t)r * N + r];
+          for (int c = 0; c < N; ++c) xsum += om[(size_t)r * N + c] * om[(size_t)c * N + r];
+        }
+      }
+      jsum += t * t;
+    }
+    S->e_hf = h0 + e1 + 0.5 * (jsum - xsum);
+  }
+  S->e_trial = std::isnan(p->e_trial) ? S->e_hf : p->e_trial;
+
+  int rc;
+  if ((rc = dev_upload(S, &S->L, G ? L_chol : nullptr, (size_t)G * M * M)) ||
+      (rc = dev_upload(S, &S->Eh, Eh.data(), (size_t)M * M)) ||
+      (rc = dev_upload(S, &S->V, Vr.data(), (size_t)nt * M)) ||
+      (rc = dev_upload(S, &S->Lh, Lh.data(), Lh.size())) ||
+      (rc = dev_upload(S, &S->ht, ht.data(), ht.size())) ||
+      (rc = dev_upload<unsigned>(S, &S->status, nullptr, 1))) {
+    free_sys(S);
+    return rc;
+  }
+  if (hipMemset(S->status, 0, sizeof(unsigned)) != hipSuccess) {
+    free_sys(S);
+    return AFQMC_E_HIP;
+  }
+  if (p->precision != AFQMC_FP64) {
+    rc = mfma_build_tables(S->mt, p->precision, M, nup, ndn, G, Lh.data());
+    if (rc == AFQMC_OK) S->device_bytes += S->mt.bytes;
+    if (rc != AFQMC_OK) {
+      free_sys(S);
+      return rc;
+    }
+  }
+  *out = S;
+  return AFQMC_OK;
+}
+
+int afqmc_workspace_bytes(afqmc_sys s, int32_t n_walkers, size_t* bytes) {
+  if (!s || n_walkers < 1 || !bytes) return AFQMC_E_ARG;
+  *bytes = layout(s, (size_t)n_walkers).total;
+  return AFQMC_OK;
+}
+
+int afqmc_get_info(afqmc_sys s, afqmc_info* info) {
+  if (!s || !info) return AFQMC_E_ARG;
+  info->e_trial = s->e_trial;
+  info->e_hf = s->e_hf;
+  info->device_bytes = s->device_bytes;
+  return AFQMC_OK;
+}
+
+int afqmc_walkers_init(afqmc_sys s, afqmc_walkers* w) {
+  if (!s) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_init_walkers, dim3(w->n_walkers), dim3(256), 0, s->stream, w->n_walkers,
+                     s->ntot * s->M, s->V, (cd*)w->U, w->weight, w->walker_id);
+  HIPCHK(hipGetLastError());
+  w->step = 0;
+  return do_measure(s, w);
+}
+
+int afqmc_measure(afqmc_sys s, afqmc_walkers* w) {
+  if (!s) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  return do_measure(s, w);
+}
+
+int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc_fields* f, double* x_out) {
+  if (!s || !f || !x_out) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  return launch_fields(s, w, f, L, x_out);
+}
+
+int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
+  if (!s || !f) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  void* ws = w->workspace;
+  const int nw = w->n_walkers, M = s->M, nt = s->ntot;
+  const int64_t k = w->step;
+  // 1. fields and force bias
+  if ((rc = launch_fields(s, w, f, L, nullptr))) return rc;
+  // 2. propagator exponent A
+  if (s->G > 0) {
+    Timer tm(s, KG_ABUILD);
+    if (s->p.precision == AFQMC_FP64 || !s->mt.enabled) {
+      constexpr int WT = 8;
+      dim3 grid((M * M + 255) / 256, (nw + WT - 1) / WT);
+      hipLaunchKernelGGL(k_abuild_fp64<WT>, grid, dim3(256), 0, s->stream, nw, M, s->G, s->s, s->L,
+                         at<cd>(ws, L.y), at<cd>(ws, L.A));
+    } else {
+      constexpr int WT = 8;
+      dim3 grid((M * M + 255) / 256, (nw + WT - 1) / WT);
+      hipLaunchKernelGGL(k_abuild_fp64<WT>, grid, dim3(256), 0, s->stream, nw, M, s->G, s->s, s->L,
+                         at<cd>(ws, L.y), at<cd>(ws, L.A));
+    }
+    HIPCHK(hipGetLastError());
+  }
+  // 3. propagation U <- E_h T_n(A) E_h U
+  {
+    Timer tm(s, KG_PROP);
+    dim3 grid((M + 63) / 64, (nt + 31) / 32, nw);
+    cd* U = (cd*)w->U;
+    cd* X0 = at<cd>(ws, L.X0);
+    cd* X1 = at<cd>(ws, L.X1);
+    cd* Y = at<cd>(ws, L.Y);
+    hipLaunchKernelGGL((k_zmatmul_fp64<1, true>), grid, dim3(256), 0, s->stream, M, nt,
+                       (const void*)s->Eh, U, X0, Y, 1.0, w->weight);
+    if (s->G > 0) {
+      for (int n = 1; n <= s->p.n_taylor; ++n) {
+        const cd* in = (n % 2 == 1) ? X0 : X1;
+        cd* out = (n % 2 == 1) ? X1 : X0;
+        hipLaunchKernelGGL((k_zmatmul_fp64<2, false>), grid, dim3(256), 0, s->stream, M, nt,
+                           (const void*)at<cd>(ws, L.A), in, out, Y, 1.0 / n, w->weight);
+      }
+    }
+    hipLaunchKernelGGL((k_zmatmul_fp64<0, true>), grid, dim3(256), 0, s->stream, M, nt,
+                       (const void*)s->Eh, Y, U, nullptr, 1.0, w->weight);
+    HIPCHK(hipGetLastError());
+  }
+  // 4. periodic re-orthonormalization
+  if (s->p.qr_period > 0 && (k + 1) % s->p.qr_period == 0) {
+    Timer tm(s, KG_QR);
+    hipLaunchKernelGGL(k_mgs, dim3(nw, 2), dim3(256), 0, s->stream, M, s->nup, s->ndn, (cd*)w->U,
+                       w->weight, s->status);
+    HIPCHK(hipGetLastError());
+  }
+  // 5-6. overlap, Theta, local energy of the new determinants
+  if ((rc = launch_overlap(s, w, L, 1))) return rc;
+  if ((rc = launch_contract(s, w, L))) return rc;
+  // 7. phaseless weights
+  {
+    Timer tm(s, KG_WEIGHT);
+    const double wmax = std::isnan(s->p.w_max) ? std::max(100.0, nw / 10.0) : s->p.w_max;
+    hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, s->stream, nw, s->p.dtau,
+                       s->e_trial, sqrt(s->p.el_cap_C / s->p.dtau), wmax, at<cd>(ws, L.logdet),
+                       at<unsigned>(ws, L.wflag), at<cd>(ws, L.enew), w->weight, w->arg_ovlp,
+                       w->log_ovlp, (cd*)w->e_loc, s->status);
+    HIPCHK(hipGetLastError());
+  }
+  // 8. population control
+  if (s->p.pop_period > 0 && (k + 1) % s->p.pop_period == 0) {
+    Timer tm(s, KG_COMB);
+    const double u = f->u_comb;
+    hipLaunchKernelGGL(k_comb_select, dim3(1), dim3(64), 0, s->stream, nw, w->weight, u, f->seed,
+                       f->job_id, k, at<double>(ws, L.csum), at<int>(ws, L.parent),
+                       at<double>(ws, L.wnew), s->status);
+    const size_t rowb = (size_t)nt * M * 16;
+    HIPCHK(hipMemcpyAsync(at<void>(ws, L.X0), w->U, rowb * nw, hipMemcpyDeviceToDevice, s->stream));
+    if (s->G > 0)
+      HIPCHK(hipMemcpyAsync(at<void>(ws, L.y), at<void>(ws, L.tcur), (size_t)nw * s->G * 16,
+                            hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(at<void>(ws, L.enew), w->e_loc, (size_t)nw * 16, hipMemcpyDeviceToDevice,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(at<void>(ws, L.asnap), w->arg_ovlp, (size_t)nw * 8,
+                          hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(at<void>(ws, L.lsnap), w->log_ovlp, (size_t)nw * 8,
+                          hipMemcpyDeviceToDevice, s->stream));
+    hipLaunchKernelGGL(k_comb_gather, dim3(nw), dim3(256), 0, s->stream, nw, nt * M, s->G,
+                       at<int>(ws, L.parent), at<double>(ws, L.wnew), at<cd>(ws, L.X0),
+                       at<cd>(ws, L.y), at<cd>(ws, L.enew), at<double>(ws, L.asnap),
+                       at<double>(ws, L.lsnap), (cd*)w->U, at<cd>(ws, L.tcur), (cd*)w->e_loc,
+                       w->arg_ovlp, w->log_ovlp, w->weight, w->walker_id);
+    HIPCHK(hipGetLastError());
+  }
+  w->step = k + 1;
+  return AFQMC_OK;
+}
+
+int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[5]) {
+  if (!s || !out) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  double* d = at<double>(w->workspace, L.esum);
+  const double half = sqrt(s->p.el_cap_C / s->p.dtau);
+  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, s->e_trial, half,
+                     w->weight, (const cd*)w->e_loc, d);
+  HIPCHK(hipGetLastError());
+  double h[4];
+  unsigned st = 0;
+  HIPCHK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(&st, s->status, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (int i = 0; i < 4; ++i) out[i] = h[i];
+  out[4] = (double)st;
+  if (!(h[3] > 0.0) || !std::isfinite(h[0]) || !std::isfinite(h[1]) || !(h[2] > 0.0))
+    return AFQMC_E_NUMERIC;
+  return AFQMC_OK;
+}
+
+int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear) {
+  if (!s || !status) return AFQMC_E_ARG;
+  unsigned st = 0;
+  HIPCHK(hipMemcpyAsync(&st, s->status, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  *status = st;
+  if (clear) {
+    HIPCHK(hipMemsetAsync(s->status, 0, sizeof(unsigned), s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
+  return AFQMC_OK;
+}
+
+int afqmc_kernel_timing(afqmc_sys s, int enable) {
+  if (!s) return AFQMC_E_ARG;
+  flush_timing(s);
+  if (enable) {
+    for (int i = 0; i < KG_COUNT; ++i) {
+      s->acc_ms[i] = 0.0;
+      s->acc_n[i] = 0;
+    }
+  }
+  s->timing = enable != 0;
+  return AFQMC_OK;
+}
+
+int afqmc_kernel_time(afqmc_sys s, int kernel, double* ms, int64_t* launches) {
+  if (!s || kernel < 0 || kernel >= KG_COUNT || !ms || !launches) return AFQMC_E_ARG;
+  flush_timing(s);
+  *ms = s->acc_ms[kernel];
+  *launches = s->acc_n[kernel];
+  return AFQMC_OK;
+}
+
+int afqmc_destroy(afqmc_sys s) {
+  if (!s) return AFQMC_E_ARG;
+  (void)hipStreamSynchronize(s->stream);
+  free_sys(s);
+  return AFQMC_OK;
+}
+
+}  // extern "C"

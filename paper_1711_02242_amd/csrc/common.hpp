@@ -1,0 +1,119 @@
+// Shared device helpers of the AFQMC library: complex FP64 arithmetic, the
+// counter-based Philox4x64-10 stream (Salmon, Moraes, Dror, Shaw, SC'11) and
+// wavefront reductions for CDNA (64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef __HIP_DEVICE_COMPILE__
+#include <cmath>
+#endif
+
+#define AFQMC_WAVE 64
+
+struct cd {
+  double re, im;
+};
+
+__host__ __device__ inline cd mkc(double re, double im) { return cd{re, im}; }
+__host__ __device__ inline cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cd cmul(cd a, cd b) {
+  return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
+__host__ __device__ inline cd cconjmul(cd a, cd b) {  // conj(a) * b
+  return cd{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+__host__ __device__ inline cd cdiv(cd a, cd b) {
+  // Smith's algorithm keeps the intermediate magnitudes bounded.
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, den = b.re + b.im * r;
+    return cd{(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+  } else {
+    double r = b.re / b.im, den = b.re * r + b.im;
+    return cd{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+  }
+}
+// a += b * c
+__host__ __device__ inline void cfma(cd& a, cd b, cd c) {
+  a.re = fma(b.re, c.re, fma(-b.im, c.im, a.re));
+  a.im = fma(b.re, c.im, fma(b.im, c.re, a.im));
+}
+// a -= b * c
+__host__ __device__ inline void cfms(cd& a, cd b, cd c) {
+  a.re = fma(-b.re, c.re, fma(b.im, c.im, a.re));
+  a.im = fma(-b.re, c.im, fma(-b.im, c.re, a.im));
+}
+// a += b * r (r real)
+__host__ __device__ inline void cfmar(cd& a, cd b, double r) {
+  a.re = fma(b.re, r, a.re);
+  a.im = fma(b.im, r, a.im);
+}
+
+__host__ __device__ inline bool cfinite(cd a) { return isfinite(a.re) && isfinite(a.im); }
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10.  Round: (hi0, lo0) = M0 * x0, (hi1, lo1) = M1 * x2 (full 128-bit
+// products); x <- (hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0); the key is bumped by
+// the Weyl constants (W0, W1) before every round after the first.
+// ---------------------------------------------------------------------------
+struct u64x4 {
+  uint64_t v[4];
+};
+
+__device__ inline u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                      uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t lo0 = M0 * x0, hi0 = __umul64hi(M0, x0);
+    const uint64_t lo1 = M1 * x2, hi1 = __umul64hi(M1, x2);
+    const uint64_t n0 = hi1 ^ x1 ^ k0, n2 = hi0 ^ x3 ^ k1;
+    x0 = n0;
+    x1 = lo1;
+    x2 = n2;
+    x3 = lo0;
+  }
+  u64x4 o;
+  o.v[0] = x0;
+  o.v[1] = x1;
+  o.v[2] = x2;
+  o.v[3] = x3;
+  return o;
+}
+
+// uint64 -> double in (0, 1): ((r >> 11) + 0.5) * 2^-53.
+__device__ inline double u64_unit(uint64_t r) {
+  return ((double)(r >> 11) + 0.5) * 0x1p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront / block reductions (fixed order -> deterministic results).
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = AFQMC_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, AFQMC_WAVE);
+  return v;
+}
+
+// Sum over the block of one double per thread; every thread gets the result.
+// `red` must hold blockDim.x / 64 doubles.  Contains __syncthreads().
+__device__ inline double block_sum(double v, double* red) {
+  const int lane = threadIdx.x % AFQMC_WAVE, wid = threadIdx.x / AFQMC_WAVE;
+  const int nw = (blockDim.x + AFQMC_WAVE - 1) / AFQMC_WAVE;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}

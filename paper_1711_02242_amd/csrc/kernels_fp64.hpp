@@ -1,0 +1,672 @@
+// FP64 kernels of the walker step (arXiv:1711.02242, Sec. III.D-E).
+//
+// Layouts (w = walker, c = occupied orbital, spin-up orbitals first,
+// p, q = basis index, g = Cholesky index):
+//   U, ThetaT, Taylor buffers : cd [nw][ntot][M]   (row c = orbital c)
+//   L                         : double [G][M][M]
+//   Lh (half-rotated V^T L^g) : double [G][ntot][M]  (rows of spin s at off_s)
+//   ht (V^T h1)               : double [ntot][M]
+//   V  (trial orbitals)       : double [ntot][M]
+//   A  (propagator exponent)  : cd [nw][M][M]
+#pragma once
+
+#include "common.hpp"
+
+// Per-walker fault flags written by the overlap kernel.
+#define WFLAG_SINGULAR 1u
+
+// ---------------------------------------------------------------------------
+// Overlap, determinant and Theta (Theorem 1.1-1.2, eq:precomputing).
+// One block per (walker, spin).  T = V_s^T U_s (N x N), LU with partial
+// pivoting in LDS, log det T = sum log(pivot) + i pi * (#row swaps),
+// Theta_s = U_s T^{-1} (rows of Theta^T = columns of Theta), and
+// e1_s = tr(ht_s Theta_s).
+// ---------------------------------------------------------------------------
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_overlap_theta(
+    int M, int nup, int ndn, const double* __restrict__ V, const double* __restrict__ ht,
+    const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
+    cd* __restrict__ thetaT, cd* __restrict__ logdet /*[nw][2]*/, cd* __restrict__ e1 /*[nw][2]*/,
+    unsigned* __restrict__ wflag /*[nw][2]*/) {
+  extern __shared__ unsigned char smem_raw[];
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s == 0 ? nup : ndn;
+  const int off = s == 0 ? 0 : nup;
+  const int ntot = nup + ndn;
+  const int tid = threadIdx.x;
+  if (N == 0) {
+    if (tid == 0) {
+      logdet[2 * w + s] = mkc(0.0, 0.0);
+      e1[2 * w + s] = mkc(0.0, 0.0);
+      wflag[2 * w + s] = 0u;
+    }
+    return;
+  }
+  if (check_weight && !(weight[w] > 0.0)) return;
+  const int ld = N + 1;
+  cd* T = reinterpret_cast<cd*>(smem_raw);                       // [N][N+1]
+  int* perm = reinterpret_cast<int*>(T + N * ld);                // [N]
+  double* red = reinterpret_cast<double*>(perm + NMAX);          // [8]
+  __shared__ int s_piv;
+  __shared__ int s_nswap;
+  __shared__ int s_sing;
+
+  const cd* Uw = U + ((size_t)w * ntot + off) * M;
+  const double* Vs = V + (size_t)off * M;
+  // T_ij = sum_p V_pi U_pj
+  for (int e = tid; e < N * N; e += blockDim.x) {
+    const int i = e / N, j = e % N;
+    cd acc = mkc(0.0, 0.0);
+    const double* vi = Vs + (size_t)i * M;
+    const cd* uj = Uw + (size_t)j * M;
+    for (int p = 0; p < M; ++p) cfmar(acc, uj[p], vi[p]);
+    T[i * ld + j] = acc;
+  }
+  if (tid < N) perm[tid] = tid;
+  if (tid == 0) {
+    s_nswap = 0;
+    s_sing = 0;
+  }
+  __syncthreads();
+  // LU with partial pivoting: P T = L R, L unit lower, R upper.
+  for (int k = 0; k < N; ++k) {
+    if (tid == 0) {
+      int piv = k;
+      double best = -1.0;
+      for (int i = k; i < N; ++i) {
+        const cd v = T[i * ld + k];
+        const double m = v.re * v.re + v.im * v.im;
+        if (m > best) {
+          best = m;
+          piv = i;
+        }
+      }
+      s_piv = piv;
+      if (!(best > 0.0)) s_sing = 1;
+      if (piv != k) {
+        const int t = perm[k];
+        perm[k] = perm[piv];
+        perm[piv] = t;
+        s_nswap += 1;
+      }
+    }
+    __syncthreads();
+    const int piv = s_piv;
+    if (piv != k) {
+      for (int j = tid; j < N; j += blockDim.x) {
+        const cd a = T[k * ld + j];
+        T[k * ld + j] = T[piv * ld + j];
+        T[piv * ld + j] = a;
+      }
+    }
+    __syncthreads();
+    if (s_sing) break;
+    const cd pk = T[k * ld + k];
+    for (int i = k + 1 + tid; i < N; i += blockDim.x) T[i * ld + k] = cdiv(T[i * ld + k], pk);
+    __syncthreads();
+    const int rem = N - k - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      cfms(T[i * ld + j], T[i * ld + k], T[k * ld + j]);
+    }
+    __syncthreads();
+  }
+  if (s_sing) {
+    if (tid == 0) {
+      wflag[2 * w + s] = WFLAG_SINGULAR;
+      logdet[2 * w + s] = mkc(-INFINITY, 0.0);
+      e1[2 * w + s] = mkc(0.0, 0.0);
+    }
+    return;
+  }
+  if (tid == 0) {
+    double la = 0.0, ar = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const cd v = T[k * ld + k];
+      la += log(hypot(v.re, v.im));
+      ar += atan2(v.im, v.re);
+    }
+    ar += M_PI * (double)(s_nswap & 1);
+    logdet[2 * w + s] = mkc(la, ar);
+    wflag[2 * w + s] = 0u;
+  }
+  // Theta rows: theta_p T = u_p  <=>  z L R = u with z_k = theta_{perm[k]}.
+  double e1re = 0.0, e1im = 0.0;
+  cd* Tw = thetaT + ((size_t)w * ntot + off) * M;
+  const double* hts = ht + (size_t)off * M;
+  for (int p = tid; p < M; p += blockDim.x) {
+    cd y[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+      if (j < N) {
+        cd acc = Uw[(size_t)j * M + p];
+        for (int i = 0; i < j; ++i) cfms(acc, y[i], T[i * ld + j]);
+        y[j] = cdiv(acc, T[j * ld + j]);
+      }
+    }
+#pragma unroll
+    for (int jj = NMAX - 1; jj >= 0; --jj) {
+      if (jj < N) {
+        cd acc = y[jj];
+        for (int i = jj + 1; i < N; ++i) cfms(acc, y[i], T[i * ld + jj]);
+        y[jj] = acc;  // now z_jj
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+      if (k < N) {
+        const int c = perm[k];
+        Tw[(size_t)c * M + p] = y[k];
+        const double hv = hts[(size_t)c * M + p];
+        e1re = fma(hv, y[k].re, e1re);
+        e1im = fma(hv, y[k].im, e1im);
+      }
+    }
+  }
+  e1re = block_sum(e1re, red);
+  e1im = block_sum(e1im, red);
+  if (tid == 0) e1[2 * w + s] = mkc(e1re, e1im);
+}
+
+// ---------------------------------------------------------------------------
+// Local-energy contraction in FP64 (eq:localenergy3): for every g,
+// Omega = Lh^g_s Theta_s (N x N), tpart[w][s][g] = tr Omega and
+// exch[w][s] = sum_g tr(Omega Omega).  One block per (walker, spin).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_contract_fp64(
+    int M, int nup, int ndn, int G, const double* __restrict__ Lh, const cd* __restrict__ thetaT,
+    const double* __restrict__ weight, cd* __restrict__ tpart /*[nw][2][G]*/,
+    cd* __restrict__ exch /*[nw][2]*/) {
+  extern __shared__ unsigned char smem_raw[];
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s == 0 ? nup : ndn;
+  const int off = s == 0 ? 0 : nup;
+  const int ntot = nup + ndn;
+  const int tid = threadIdx.x;
+  if (N == 0) {
+    for (int g = tid; g < G; g += blockDim.x) tpart[((size_t)w * 2 + s) * G + g] = mkc(0.0, 0.0);
+    if (tid == 0) exch[2 * w + s] = mkc(0.0, 0.0);
+    return;
+  }
+  if (!(weight[w] > 0.0)) return;
+  const int ldt = M + 1;
+  cd* Th = reinterpret_cast<cd*>(smem_raw);        // [N][M+1]
+  cd* Om = Th + (size_t)N * ldt;                    // [N][N+1]
+  double* red = reinterpret_cast<double*>(Om + (size_t)N * (N + 1));
+  const cd* Tw = thetaT + ((size_t)w * ntot + off) * M;
+  for (int e = tid; e < N * M; e += blockDim.x) Th[(e / M) * ldt + e % M] = Tw[e];
+  __syncthreads();
+  double xr = 0.0, xi = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const double* Lg = Lh + ((size_t)g * ntot + off) * M;
+    for (int e = tid; e < N * N; e += blockDim.x) {
+      const int r = e / N, c = e % N;
+      cd acc = mkc(0.0, 0.0);
+      const double* lr = Lg + (size_t)r * M;
+      const cd* tc = Th + (size_t)c * ldt;
+      for (int p = 0; p < M; ++p) cfmar(acc, tc[p], lr[p]);
+      Om[r * (N + 1) + c] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < N * N; e += blockDim.x) {
+      const int r = e / N, c = e % N;
+      const cd a = Om[r * (N + 1) + c], b = Om[c * (N + 1) + r];
+      xr += a.re * b.re - a.im * b.im;
+      xi += a.re * b.im + a.im * b.re;
+    }
+    if (tid < AFQMC_WAVE) {
+      double tr = 0.0, ti = 0.0;
+      for (int r = tid; r < N; r += AFQMC_WAVE) {
+        tr += Om[r * (N + 1) + r].re;
+        ti += Om[r * (N + 1) + r].im;
+      }
+      tr = wave_sum(tr);
+      ti = wave_sum(ti);
+      if (tid == 0) tpart[((size_t)w * 2 + s) * G + g] = mkc(tr, ti);
+    }
+    __syncthreads();
+  }
+  xr = block_sum(xr, red);
+  xi = block_sum(xi, red);
+  if (tid == 0) exch[2 * w + s] = mkc(xr, xi);
+}
+
+// ---------------------------------------------------------------------------
+// Local-energy assembly: t_g = sum_s tpart, E_L = h0 + e1 + 1/2 (sum_g t_g^2 - exch)
+// (eq:localenergy2-3 with the 1/2 of eq:bo_ham2).  One block per walker.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_energy_assemble(
+    int G, double h0, const cd* __restrict__ tpart, const cd* __restrict__ exch,
+    const cd* __restrict__ e1, const double* __restrict__ weight, int check_weight,
+    cd* __restrict__ tcur /*[nw][G]*/, cd* __restrict__ enew /*[nw]*/) {
+  __shared__ double red[8];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  if (check_weight && !(weight[w] > 0.0)) return;
+  double jr = 0.0, ji = 0.0;
+  for (int g = tid; g < G; g += blockDim.x) {
+    const cd t = cadd(tpart[((size_t)w * 2) * G + g], tpart[((size_t)w * 2 + 1) * G + g]);
+    tcur[(size_t)w * G + g] = t;
+    jr += t.re * t.re - t.im * t.im;
+    ji += 2.0 * t.re * t.im;
+  }
+  jr = block_sum(jr, red);
+  ji = block_sum(ji, red);
+  if (tid == 0) {
+    const cd x = cadd(exch[2 * w], exch[2 * w + 1]);
+    const cd e = cadd(e1[2 * w], e1[2 * w + 1]);
+    enew[w] = mkc(h0 + e.re + 0.5 * (jr - x.re), e.im + 0.5 * (ji - x.im));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Auxiliary fields and force bias (eq:hs2, eq:fb, eq:precomputing2, App. B.1):
+// x from the Philox stream (or given), xbar = -i s t capped in modulus,
+// y = x - xbar.  One thread per (walker, block of 4 fields).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fields(
+    int nw, int G, double s, double fb_cap, const cd* __restrict__ tcur,
+    const double* __restrict__ weight, const int64_t* __restrict__ walker_id, uint64_t seed,
+    uint64_t job, int64_t step, const double* __restrict__ xin, cd* __restrict__ y,
+    double* __restrict__ xout, unsigned* __restrict__ status) {
+  const int nblk = (G + 3) / 4;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)nw * nblk) return;
+  const int w = (int)(idx / nblk), b = (int)(idx % nblk);
+  double x[4];
+  if (xin) {
+    for (int j = 0; j < 4; ++j) x[j] = (4 * b + j < G) ? xin[(size_t)w * G + 4 * b + j] : 0.0;
+  } else {
+    const u64x4 r = philox4x64_10((uint64_t)b, (uint64_t)walker_id[w], (uint64_t)step, 0ull,
+                                  seed, job);
+    const double u0 = u64_unit(r.v[0]), u1 = u64_unit(r.v[1]);
+    const double u2 = u64_unit(r.v[2]), u3 = u64_unit(r.v[3]);
+    const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+    const double a1 = 2.0 * M_PI * u1, a3 = 2.0 * M_PI * u3;
+    x[0] = r0 * cos(a1);
+    x[1] = r0 * sin(a1);
+    x[2] = r1 * cos(a3);
+    x[3] = r1 * sin(a3);
+  }
+  if (xout) {
+    for (int j = 0; j < 4; ++j)
+      if (4 * b + j < G) xout[(size_t)w * G + 4 * b + j] = x[j];
+    return;
+  }
+  const bool alive = weight[w] > 0.0;
+  bool capped = false;
+  for (int j = 0; j < 4; ++j) {
+    const int g = 4 * b + j;
+    if (g >= G) break;
+    cd yv = mkc(0.0, 0.0);
+    if (alive) {
+      const cd t = tcur[(size_t)w * G + g];
+      // xbar = -i s t = (s t.im, -s t.re)
+      double br = s * t.im, bi = -s * t.re;
+      const double mod = hypot(br, bi);
+      if (mod > fb_cap) {
+        br *= fb_cap / mod;
+        bi *= fb_cap / mod;
+        capped = true;
+      }
+      yv = mkc(x[j] - br, -bi);
+    }
+    y[(size_t)w * G + g] = yv;
+  }
+  if (capped) atomicOr(status, 0x10u);
+}
+
+// ---------------------------------------------------------------------------
+// Propagator exponent A_w = i s sum_g y_wg L^g (Sec. III.D.2), FP64.
+// Thread: one matrix element for WT walkers; y staged in LDS per g-chunk.
+// ---------------------------------------------------------------------------
+template <int WT>
+__global__ void __launch_bounds__(256) k_abuild_fp64(int nw, int M, int G, double s,
+                                                     const double* __restrict__ L,
+                                                     const cd* __restrict__ y,
+                                                     cd* __restrict__ A) {
+  constexpr int GC = 64;
+  __shared__ cd ys[WT][GC];
+  const int MM = M * M;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w0 = blockIdx.y * WT;
+  double ar[WT], ai[WT];
+#pragma unroll
+  for (int k = 0; k < WT; ++k) ar[k] = ai[k] = 0.0;
+  for (int g0 = 0; g0 < G; g0 += GC) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < WT * GC; i += blockDim.x) {
+      const int k = i / GC, g = g0 + i % GC;
+      ys[k][i % GC] = (w0 + k < nw && g < G) ? y[(size_t)(w0 + k) * G + g] : mkc(0.0, 0.0);
+    }
+    __syncthreads();
+    if (e < MM) {
+      const int gn = min(GC, G - g0);
+      for (int gg = 0; gg < gn; ++gg) {
+        const double l = L[(size_t)(g0 + gg) * MM + e];
+#pragma unroll
+        for (int k = 0; k < WT; ++k) {
+          ar[k] = fma(ys[k][gg].re, l, ar[k]);
+          ai[k] = fma(ys[k][gg].im, l, ai[k]);
+        }
+      }
+    }
+  }
+  if (e < MM) {
+#pragma unroll
+    for (int k = 0; k < WT; ++k)
+      if (w0 + k < nw) A[(size_t)(w0 + k) * MM + e] = mkc(-s * ai[k], s * ar[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched complex product out^T[c][i] = scale * sum_k Mat[i][k] in^T[c][k] for one
+// walker per blockIdx.z (Theorem 1.4: applying exp(A) to the orbitals).
+// MODE 0: out = r.  MODE 1: out = r, Y = r.  MODE 2: out = r, Y += r.
+// REALMAT: Mat is one real M x M matrix shared by all walkers (exp(-dtau/2 v0)).
+// Tile: 64 rows i x 32 orbitals c per block, K chunks of 16.
+// ---------------------------------------------------------------------------
+template <int MODE, bool REALMAT>
+__global__ void __launch_bounds__(256) k_zmatmul_fp64(int M, int ntot, const void* __restrict__ Mat,
+                                                      const cd* __restrict__ in, cd* __restrict__ out,
+                                                      cd* __restrict__ Y, double scale,
+                                                      const double* __restrict__ weight) {
+  constexpr int TI = 64, TC = 32, TK = 16;
+  __shared__ cd sA[TK][TI + 1];
+  __shared__ cd sB[TK][TC + 1];
+  const int w = blockIdx.z;
+  if (!(weight[w] > 0.0)) return;
+  const int i0 = blockIdx.x * TI, c0 = blockIdx.y * TC;
+  const int tid = threadIdx.x;
+  const int ti = tid % 16, tc = tid / 16;   // thread owns rows ti + 16*a (a<4), cols tc + 16*b (b<2)
+  const cd* inw = in + (size_t)w * ntot * M;
+  const cd* Aw = REALMAT ? nullptr : reinterpret_cast<const cd*>(Mat) + (size_t)w * M * M;
+  const double* Ar = REALMAT ? reinterpret_cast<const double*>(Mat) : nullptr;
+  cd acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = mkc(0.0, 0.0);
+  for (int k0 = 0; k0 < M; k0 += TK) {
+    for (int e = tid; e < TI * TK; e += 256) {
+      const int ii = e / TK, kk = e % TK;
+      const int i = i0 + ii, k = k0 + kk;
+      cd v = mkc(0.0, 0.0);
+      if (i < M && k < M) v = REALMAT ? mkc(Ar[(size_t)i * M + k], 0.0) : Aw[(size_t)i * M + k];
+      sA[kk][ii] = v;
+    }
+    for (int e = tid; e < TC * TK; e += 256) {
+      const int cc = e / TK, kk = e % TK;
+      const int c = c0 + cc, k = k0 + kk;
+      sB[kk][cc] = (c < ntot && k < M) ? inw[(size_t)c * M + k] : mkc(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      cd av[4], bv[2];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sA[kk][ti + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = sB[kk][tc + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) cfma(acc[a][b], av[a], bv[b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + ti + 16 * a;
+    if (i >= M) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int c = c0 + tc + 16 * b;
+      if (c >= ntot) continue;
+      const size_t o = ((size_t)w * ntot + c) * M + i;
+      const cd r = cscale(acc[a][b], scale);
+      out[o] = r;
+      if (MODE == 1) Y[o] = r;
+      if (MODE == 2) Y[o] = cadd(Y[o], r);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Modified Gram-Schmidt on the orbitals of one (walker, spin) (Sec. III.D.5):
+// column k is normalized, then its projection is removed from every later
+// column.  Rows of U (orbital-major) are updated in place in global memory.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __restrict__ U,
+                                             const double* __restrict__ weight,
+                                             unsigned* __restrict__ status) {
+  __shared__ cd dots[64];
+  __shared__ double s_norm;
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s == 0 ? nup : ndn;
+  const int off = s == 0 ? 0 : nup;
+  const int ntot = nup + ndn;
+  if (N == 0 || !(weight[w] > 0.0)) return;
+  cd* Uw = U + ((size_t)w * ntot + off) * M;
+  const int tid = threadIdx.x, lane = tid % AFQMC_WAVE, wid = tid / AFQMC_WAVE;
+  const int nwave = blockDim.x / AFQMC_WAVE;
+  for (int k = 0; k < N; ++k) {
+    cd* qk = Uw + (size_t)k * M;
+    if (wid == 0) {
+      double nn = 0.0;
+      for (int p = lane; p < M; p += AFQMC_WAVE) nn += qk[p].re * qk[p].re + qk[p].im * qk[p].im;
+      nn = wave_sum(nn);
+      if (lane == 0) s_norm = sqrt(nn);
+    }
+    __syncthreads();
+    const double nrm = s_norm;
+    if (!(nrm > 0.0) && tid == 0) atomicOr(status, 0x2u);
+    const double inv = 1.0 / nrm;
+    for (int p = tid; p < M; p += blockDim.x) qk[p] = cscale(qk[p], inv);
+    __syncthreads();
+    // dots for the later columns, one wavefront per column
+    for (int j0 = k + 1; j0 < N; j0 += 64) {
+      for (int j = j0 + wid; j < min(N, j0 + 64); j += nwave) {
+        const cd* uj = Uw + (size_t)j * M;
+        double dr = 0.0, di = 0.0;
+        for (int p = lane; p < M; p += AFQMC_WAVE) {
+          const cd v = cconjmul(qk[p], uj[p]);
+          dr += v.re;
+          di += v.im;
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        if (lane == 0) dots[j - j0] = mkc(dr, di);
+      }
+      __syncthreads();
+      const int nj = min(N, j0 + 64) - j0;
+      for (int e = tid; e < nj * M; e += blockDim.x) {
+        const int j = j0 + e / M, p = e % M;
+        cfms(Uw[(size_t)j * M + p], dots[j - j0], qk[p]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phaseless weight update (eq:if_rle, eq:cap): one thread per walker.
+// ---------------------------------------------------------------------------
+__global__ void k_weights(int nw, double dtau, double e_trial, double ecap_half, double w_max,
+                          const cd* __restrict__ logdet, const unsigned* __restrict__ wflag,
+                          const cd* __restrict__ enew, double* __restrict__ weight,
+                          double* __restrict__ arg_ovlp, double* __restrict__ log_ovlp,
+                          cd* __restrict__ e_loc, unsigned* __restrict__ status) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const double W = weight[w];
+  if (!(W > 0.0)) return;
+  unsigned st = 0u;
+  const cd l0 = logdet[2 * w], l1 = logdet[2 * w + 1];
+  double a = l0.im + l1.im;
+  a = a - 2.0 * M_PI * floor((a + M_PI) / (2.0 * M_PI));   // (-pi, pi]
+  if (a <= -M_PI) a += 2.0 * M_PI;
+  const double la = l0.re + l1.re;
+  const cd en = enew[w];
+  const unsigned fl = wflag[2 * w] | wflag[2 * w + 1];
+  double Wn;
+  if (fl & WFLAG_SINGULAR) {
+    Wn = 0.0;
+    st |= 0x2u;
+  } else if (!cfinite(en) || !isfinite(a) || !isfinite(la)) {
+    Wn = 0.0;
+    st |= 0x1u;
+  } else {
+    const cd eo = e_loc[w];
+    double ec = eo.re;
+    if (ec < e_trial - ecap_half) {
+      ec = e_trial - ecap_half;
+      st |= 0x4u;
+    } else if (ec > e_trial + ecap_half) {
+      ec = e_trial + ecap_half;
+      st |= 0x4u;
+    }
+    const double proj = fmax(0.0, cos(a - arg_ovlp[w]));
+    if (!(proj > 0.0)) st |= 0x20u;
+    Wn = W * exp(-dtau * (ec - e_trial)) * proj;
+    if (Wn > w_max) {
+      Wn = w_max;
+      st |= 0x8u;
+    }
+  }
+  weight[w] = Wn;
+  arg_ovlp[w] = a;
+  log_ovlp[w] = la;
+  e_loc[w] = en;
+  if (st) atomicOr(status, st);
+}
+
+// Initialization / measurement: phase and log of the overlap, E_L, from logdet and enew.
+__global__ void k_measure_finish(int nw, const cd* __restrict__ logdet,
+                                 const unsigned* __restrict__ wflag, const cd* __restrict__ enew,
+                                 double* __restrict__ weight, double* __restrict__ arg_ovlp,
+                                 double* __restrict__ log_ovlp, cd* __restrict__ e_loc,
+                                 unsigned* __restrict__ status) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const cd l0 = logdet[2 * w], l1 = logdet[2 * w + 1];
+  double a = l0.im + l1.im;
+  a = a - 2.0 * M_PI * floor((a + M_PI) / (2.0 * M_PI));
+  if (a <= -M_PI) a += 2.0 * M_PI;
+  const unsigned fl = wflag[2 * w] | wflag[2 * w + 1];
+  arg_ovlp[w] = a;
+  log_ovlp[w] = l0.re + l1.re;
+  e_loc[w] = enew[w];
+  if ((fl & WFLAG_SINGULAR) || !cfinite(enew[w])) {
+    weight[w] = 0.0;
+    atomicOr(status, (fl & WFLAG_SINGULAR) ? 0x2u : 0x1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Comb population control (Sec. III.D.4): sequential cumulative weights in walker
+// order, positions (u + j) * (sum W / n), parent = walker whose half-open interval
+// holds the position.  One thread does the scan so the arithmetic order is fixed.
+// ---------------------------------------------------------------------------
+__global__ void k_comb_select(int nw, const double* __restrict__ weight, double u_given,
+                              uint64_t seed, uint64_t job, int64_t step, double* __restrict__ csum,
+                              int* __restrict__ parent, double* __restrict__ wnew,
+                              unsigned* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double u = u_given;
+  if (!(u > 0.0 && u < 1.0)) {
+    const u64x4 r = philox4x64_10(0ull, 0ull, (uint64_t)step, 1ull, seed, job);
+    u = u64_unit(r.v[0]);
+  }
+  double acc = 0.0;
+  int last_alive = -1;
+  for (int i = 0; i < nw; ++i) {
+    acc += weight[i];
+    csum[i] = acc;
+    if (weight[i] > 0.0) last_alive = i;
+  }
+  const double total = acc;
+  if (!(total > 0.0) || last_alive < 0) {
+    for (int j = 0; j < nw; ++j) parent[j] = j;
+    *wnew = -1.0;
+    atomicOr(status, 0x1u);
+    return;
+  }
+  const double step_w = total / (double)nw;
+  int i = 0;
+  for (int j = 0; j < nw; ++j) {
+    const double pos = (u + (double)j) * step_w;
+    while (i < nw && csum[i] <= pos) ++i;
+    parent[j] = i < last_alive ? i : last_alive;
+  }
+  *wnew = step_w;
+}
+
+// Gather walker state from a snapshot by parent index.  One block per walker.
+__global__ void __launch_bounds__(256) k_comb_gather(
+    int nw, int rowlen /*ntot*M*/, int G, const int* __restrict__ parent,
+    const double* __restrict__ wnew, const cd* __restrict__ Usnap, const cd* __restrict__ tsnap,
+    const cd* __restrict__ esnap, const double* __restrict__ asnap,
+    const double* __restrict__ lsnap, cd* __restrict__ U, cd* __restrict__ tcur,
+    cd* __restrict__ e_loc, double* __restrict__ arg_ovlp, double* __restrict__ log_ovlp,
+    double* __restrict__ weight, int64_t* __restrict__ walker_id) {
+  const int j = blockIdx.x;
+  const double wv = *wnew;
+  if (!(wv > 0.0)) return;
+  const int pj = parent[j];
+  for (int e = threadIdx.x; e < rowlen; e += blockDim.x)
+    U[(size_t)j * rowlen + e] = Usnap[(size_t)pj * rowlen + e];
+  for (int e = threadIdx.x; e < G; e += blockDim.x)
+    tcur[(size_t)j * G + e] = tsnap[(size_t)pj * G + e];
+  if (threadIdx.x == 0) {
+    e_loc[j] = esnap[pj];
+    arg_ovlp[j] = asnap[pj];
+    log_ovlp[j] = lsnap[pj];
+    weight[j] = wv;
+    walker_id[j] = j;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-estimator sums (eq:localenergy, theta = 0) in a fixed reduction order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_energy_sum(int nw, double e_trial, double ecap_half,
+                                                    const double* __restrict__ weight,
+                                                    const cd* __restrict__ e_loc,
+                                                    double* __restrict__ out) {
+  __shared__ double red[8];
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+    const double W = weight[w];
+    if (W > 0.0) {
+      const cd e = e_loc[w];
+      const double ec = fmin(fmax(e.re, e_trial - ecap_half), e_trial + ecap_half);
+      a += W * ec;
+      b += W * e.im;
+      c += W;
+      d += 1.0;
+    }
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  c = block_sum(c, red);
+  d = block_sum(d, red);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+    out[3] = d;
+  }
+}
+
+// Walkers start as the trial: U[w] = V (as complex), W = 1, id = w.
+__global__ void k_init_walkers(int nw, int rowlen, const double* __restrict__ V,
+                               cd* __restrict__ U, double* __restrict__ weight,
+                               int64_t* __restrict__ walker_id) {
+  const int w = blockIdx.x;
+  for (int e = threadIdx.x; e < rowlen; e += blockDim.x)
+    U[(size_t)w * rowlen + e] = mkc(V[e], 0.0);
+  if (threadIdx.x == 0) {
+    weight[w] = 1.0;
+    walker_id[w] = w;
+  }
+}

@@ -1,0 +1,110 @@
+"""Shared helpers of the GPU parity tests: run the HIP path (through the C ABI) and the
+CPU oracle on the same seeded inputs and compare."""
+
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+from oracle import afqmc as A
+from synthetic import comb_uniform, gaussian_fields
+
+
+def log(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_U_to_oracle(U: np.ndarray, n_up: int):
+    """[nw][ntot][M] orbital-major -> per-spin (nw, M, N_sigma)."""
+    return [np.ascontiguousarray(U[:, :n_up, :].transpose(0, 2, 1)),
+            np.ascontiguousarray(U[:, n_up:, :].transpose(0, 2, 1))]
+
+
+def oracle_U_to_gpu(Uu: np.ndarray, Ud: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(np.concatenate([Uu.transpose(0, 2, 1), Ud.transpose(0, 2, 1)], axis=1))
+
+
+def make_pair(s, nw: int, *, dtau: float, precision: str = "fp64", qr_period: int = 5,
+              pop_period: int = 5, n_taylor: int = 6, U=None):
+    import paper_1711_02242_amd as afq
+    S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, dtau)
+    P = A.Params(dtau=dtau, n_taylor=n_taylor, qr_period=qr_period, pop_period=pop_period)
+    gs = afq.System.from_synthetic(s, dtau=dtau, precision=precision, qr_period=qr_period,
+                                   pop_period=pop_period, n_taylor=n_taylor)
+    wk = gs.walkers(nw)
+    gs.init(wk)
+    if U is None:
+        wo = A.init_walkers(S, nw)
+    else:
+        import torch
+        Uu, Ud = U
+        wo = A.init_walkers(S, nw, Uu, Ud)
+        wk.U.copy_(torch.from_numpy(oracle_U_to_gpu(Uu, Ud)))
+        gs.measure(wk)
+    return S, P, wo, gs, wk
+
+
+def gpu_state(wk):
+    import torch
+    torch.cuda.synchronize()
+    return dict(U=wk.U.cpu().numpy(), W=wk.weight.cpu().numpy(), arg=wk.arg_ovlp.cpu().numpy(),
+                logabs=wk.log_ovlp.cpu().numpy(), e=wk.e_loc.cpu().numpy(),
+                ids=wk.walker_id.cpu().numpy())
+
+
+def angle_diff(a, b):
+    d = np.asarray(a) - np.asarray(b)
+    return np.abs(np.mod(d + np.pi, 2 * np.pi) - np.pi)
+
+
+def compare_state(S, wo, st, n_up: int, rtol: float, what: str = ""):
+    """Largest relative deviations of the GPU state from the oracle's (returns a dict)."""
+    Uu, Ud = gpu_U_to_oracle(st["U"], n_up)
+    alive = wo.W > 0
+    out = {}
+    scaleU = max(np.abs(wo.U[0]).max(), np.abs(wo.U[1]).max() if wo.U[1].size else 0.0)
+    dU = np.abs(Uu[alive] - wo.U[0][alive]).max(initial=0.0)
+    if wo.U[1].size:
+        dU = max(dU, np.abs(Ud[alive] - wo.U[1][alive]).max(initial=0.0))
+    out["U"] = dU / scaleU
+    out["W"] = np.abs(st["W"] - wo.W).max() / max(1.0, np.abs(wo.W).max())
+    out["e"] = (np.abs(st["e"][alive] - wo.e_loc[alive]).max(initial=0.0)
+                / max(1.0, np.abs(wo.e_loc[alive]).max(initial=1.0)))
+    out["arg"] = angle_diff(st["arg"][alive], wo.arg[alive]).max(initial=0.0)
+    out["alive_match"] = bool(np.array_equal(st["W"] > 0, alive))
+    bad = {k: v for k, v in out.items() if k != "alive_match" and not v <= rtol}
+    if bad or not out["alive_match"]:
+        raise AssertionError(f"{what}: GPU vs oracle deviation {out} (tol {rtol})")
+    return out
+
+
+def run_lockstep(s, nw: int, steps: int, *, dtau: float, precision: str = "fp64",
+                 explicit_fields: bool = True, seed: int = 0, rtol: float = 1e-10,
+                 qr_period: int = 5, pop_period: int = 5, check_every: int = 1, U=None,
+                 label: str = ""):
+    import torch
+    S, P, wo, gs, wk = make_pair(s, nw, dtau=dtau, precision=precision, qr_period=qr_period,
+                                 pop_period=pop_period, U=U)
+    compare_state(S, wo, gpu_state(wk), s.n_up, rtol, f"{label} init")
+    worst = {}
+    for k in range(steps):
+        x = gaussian_fields(seed, 0, wo.walker_id, k, s.n_chol)
+        u = comb_uniform(seed, 0, k)
+        A.step(S, P, wo, x, u)
+        if explicit_fields:
+            gs.step(wk, seed=seed, x=torch.from_numpy(x).cuda(), u_comb=u)
+        else:
+            gs.step(wk, seed=seed)
+        if (k + 1) % check_every == 0 or k == steps - 1:
+            d = compare_state(S, wo, gpu_state(wk), s.n_up, rtol, f"{label} step {k}")
+            for key, v in d.items():
+                if key != "alive_match":
+                    worst[key] = max(worst.get(key, 0.0), v)
+    e_gpu = gs.energy(wk)
+    e_or = A.mixed_energy(S, P, wo)
+    assert abs(e_gpu[0] / e_gpu[2] - e_or[0]) <= rtol * abs(e_or[0]) * 10
+    assert e_gpu[3] == e_or[4]
+    return worst, gs, wk, S, wo

@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every symbol include/afqmc.h declares, and the
+ctypes structures match the C layout (no GPU needed, no compute calls)."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1711_02242_amd as pkg
+from paper_1711_02242_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "afqmc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"AFQMC_API\s+(?:const\s+)?\w+\*?\s+(afqmc_\w+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", pkg.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT\s+(afqmc_\w+)", out))
+    assert exported == set(declared_functions())
+
+
+def test_error_strings():
+    lib = pkg.load()
+    assert lib.afqmc_error_string(0) == b"ok"
+    assert b"argument" in lib.afqmc_error_string(-1)
+    assert lib.afqmc_error_string(12345) == b"unknown error"
+
+
+def test_null_arguments_are_rejected_without_device_work():
+    lib = pkg.load()
+    assert lib.afqmc_setup(None, 0.0, None, None, None, None, None, None) == -1
+    assert lib.afqmc_destroy(None) == -1
+    b = C.c_size_t()
+    assert lib.afqmc_workspace_bytes(None, 4, C.byref(b)) == -1
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "afqmc.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("afqmc_params %zu\n", sizeof(afqmc_params));
+  printf("afqmc_walkers %zu\n", sizeof(afqmc_walkers));
+  printf("afqmc_fields %zu\n", sizeof(afqmc_fields));
+  printf("afqmc_info %zu\n", sizeof(afqmc_info));
+  P(afqmc_params, dtau) P(afqmc_params, precision) P(afqmc_params, el_cap_C) P(afqmc_params, flags)
+  P(afqmc_walkers, U) P(afqmc_walkers, workspace) P(afqmc_walkers, workspace_bytes) P(afqmc_walkers, step)
+  P(afqmc_fields, x) P(afqmc_fields, u_comb)
+  return 0;
+}
+""")
+    exe = tmp_path / "probe"
+    r = subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                        str(exe)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail(r.stderr)
+    vals = dict(line.rsplit(" ", 1) for line in
+                subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+                if line)
+    assert int(vals["afqmc_params"]) == C.sizeof(L.Params)
+    assert int(vals["afqmc_walkers"]) == C.sizeof(L.WalkersC)
+    assert int(vals["afqmc_fields"]) == C.sizeof(L.FieldsC)
+    assert int(vals["afqmc_info"]) == C.sizeof(L.InfoC)
+    for key, struct in (("afqmc_params", L.Params), ("afqmc_walkers", L.WalkersC),
+                        ("afqmc_fields", L.FieldsC)):
+        for k, v in vals.items():
+            if k.startswith(key + "."):
+                field = k.split(".", 1)[1]
+                assert getattr(struct, field).offset == int(v), k

@@ -1,0 +1,147 @@
+"""GPU (HIP, through the C ABI) against the CPU oracle on identical seeded inputs.
+
+FP64 bar: relative 1e-10 on E_L, W and U, absolute 1e-10 on the overlap phase.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import afqmc as A
+from synthetic import config_system, gaussian_fields, gen_system, random_walkers
+from tests.parity_helpers import (compare_state, gpu_state, gpu_U_to_oracle, log, make_pair,
+                                  oracle_U_to_gpu, run_lockstep)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_gpu_fields_match_counter_stream(torch_cuda):
+    """Philox4x64-10 fields drawn on the device equal the counter stream of synthetic.fields."""
+    for G in (32, 37, 800):
+        s = gen_system(8, 2, G, seed=3)
+        log(f"fields G={G}")
+        _, _, wo, gs, wk = make_pair(s, 9, dtau=0.01)
+        wk.walker_id.copy_(torch_cuda.tensor([3, 1, 4, 1, 5, 9, 2, 6, 5], dtype=torch_cuda.int64))
+        wk.step = 17
+        x_gpu = gs.fields_draw(wk, seed=12345, job_id=7).cpu().numpy()
+        x_ref = gaussian_fields(12345, 7, [3, 1, 4, 1, 5, 9, 2, 6, 5], 17, G)
+        assert np.abs(x_gpu - x_ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium", "large"])
+def test_gpu_init_energy_is_trial_energy(torch_cuda, name):
+    s = config_system(name)
+    log(f"init {name}")
+    S, P, wo, gs, wk = make_pair(s, 8, dtau=0.005)
+    st = gpu_state(wk)
+    assert abs(gs.e_hf - S.E_T) < 1e-11 * abs(S.E_T)
+    assert np.abs(st["e"] - S.E_T).max() < 1e-11 * abs(S.E_T)
+    assert np.all(st["W"] == 1.0) and np.abs(st["arg"]).max() < 1e-12
+    assert np.array_equal(st["ids"], np.arange(8))
+
+
+@pytest.mark.parametrize("case", ["tiny", "medium", "large", "ragged", "open_shell", "polarized"])
+def test_gpu_measure_random_walkers(torch_cuda, case):
+    """Overlap phase, log|overlap| and E_L of arbitrary complex walkers (Theorem 1.1-1.2,
+    eq:localenergy3) against the oracle."""
+    if case in ("tiny", "medium", "large"):
+        s = config_system(case)
+        nw = {"tiny": 16, "medium": 24, "large": 6}[case]
+    elif case == "ragged":
+        s = gen_system(13, 3, 19, seed=5)
+        nw = 7
+    elif case == "open_shell":
+        s = gen_system(24, 5, 70, seed=6, n_dn=3)
+        nw = 5
+    else:
+        s = gen_system(10, 3, 12, seed=7, n_dn=0)
+        nw = 4
+    log(f"measure {case} M={s.M} up={s.n_up} dn={s.n_dn} G={s.n_chol} nw={nw}")
+    U = random_walkers(s, nw, seed=99, amplitude=0.8)
+    S, P, wo, gs, wk = make_pair(s, nw, dtau=0.005, U=U)
+    compare_state(S, wo, gpu_state(wk), s.n_up, 1e-10, case)
+    assert np.abs(gpu_state(wk)["logabs"] - wo.logabs).max() < 1e-10
+
+
+def test_gpu_lockstep_tiny_explicit_fields(torch_cuda):
+    """Tiny molecule (M=8, N=2+2, N_g=32), 16 walkers, 200 steps, QR and comb every 5 steps."""
+    s = config_system("tiny")
+    log("lockstep tiny explicit")
+    worst, *_ = run_lockstep(s, 16, 200, dtau=0.01, label="tiny")
+    log(f"tiny worst {worst}")
+
+
+def test_gpu_lockstep_tiny_device_philox(torch_cuda):
+    """Same run with the fields drawn on the device from the counter stream."""
+    s = config_system("tiny")
+    log("lockstep tiny device philox")
+    worst, *_ = run_lockstep(s, 16, 60, dtau=0.01, explicit_fields=False, label="tiny-philox",
+                             rtol=1e-9)
+    log(f"tiny philox worst {worst}")
+
+
+@pytest.mark.parametrize("case", ["medium", "ragged", "open_shell", "polarized", "no_cholesky"])
+def test_gpu_lockstep_shapes(torch_cuda, case):
+    if case == "medium":
+        s, nw, steps, dt = config_system("medium"), 12, 10, 0.005
+    elif case == "ragged":
+        s, nw, steps, dt = gen_system(13, 3, 19, seed=5), 7, 12, 0.01
+    elif case == "open_shell":
+        s, nw, steps, dt = gen_system(24, 5, 70, seed=6, n_dn=3), 9, 10, 0.01
+    elif case == "polarized":
+        s, nw, steps, dt = gen_system(10, 3, 12, seed=7, n_dn=0), 6, 10, 0.01
+    else:
+        s, nw, steps, dt = gen_system(9, 2, 0, seed=8), 5, 10, 0.05
+    log(f"lockstep {case} M={s.M} up={s.n_up} dn={s.n_dn} G={s.n_chol} nw={nw}")
+    worst, *_ = run_lockstep(s, nw, steps, dtau=dt, label=case)
+    log(f"{case} worst {worst}")
+
+
+def test_gpu_lockstep_large_sample(torch_cuda):
+    """Full-size Hamiltonian (M=128, N=32+32, N_g=800) on a sample of 4 walkers, 5 steps
+    (QR and comb after the fifth)."""
+    s = config_system("large")
+    log("lockstep large sample")
+    worst, *_ = run_lockstep(s, 4, 5, dtau=0.005, label="large", check_every=5)
+    log(f"large worst {worst}")
+
+
+def test_gpu_phaseless_kill_and_comb_replacement(torch_cuda):
+    """A walker whose overlap phase jumps by 0.75 pi gets W = 0 (eq:if_rle), stays dead, and
+    the comb replaces it; the oracle does the same."""
+    import torch
+    s = config_system("tiny")
+    S, P, wo, gs, wk = make_pair(s, 6, dtau=0.01)
+    wo.U[0][2][:, 0] *= np.exp(0.75j * np.pi)
+    wk.U[2, 0, :] *= np.exp(0.75j * np.pi)
+    for k in range(5):
+        x = gaussian_fields(0, 0, wo.walker_id, k, s.n_chol)
+        A.step(S, P, wo, x, 0.37)
+        gs.step(wk, x=torch.from_numpy(x).cuda(), u_comb=0.37)
+        st = gpu_state(wk)
+        if k < 4:
+            assert st["W"][2] == 0.0 and wo.W[2] == 0.0
+        compare_state(S, wo, st, s.n_up, 1e-10, f"kill step {k}")
+    assert np.all(gpu_state(wk)["W"] > 0)
+    assert gs.status() & 0x20
+
+
+def test_gpu_run_is_deterministic(torch_cuda):
+    """Two identical runs give bitwise-identical walkers (fixed-order reductions, no FP atomics)."""
+    s = config_system("medium")
+    outs = []
+    for rep in range(2):
+        _, _, _, gs, wk = make_pair(s, 16, dtau=0.005)
+        for k in range(6):
+            gs.step(wk, seed=4)
+        st = gpu_state(wk)
+        outs.append(st)
+        gs.close()
+    for key in ("U", "W", "arg", "e"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
