@@ -1,0 +1,212 @@
+"""Benchmark of the phaseless-AFQMC step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3|fp64]
+
+Workload: the large synthetic molecule-shaped Hamiltonian (M = 128 orbitals,
+N = 32 + 32 electrons, N_g = 800 Cholesky vectors), 1024 walkers, dtau = 0.005,
+re-orthonormalization and comb population control every 5 steps.  A step is
+one full walker step (fields, force bias, propagator build, Taylor propagation,
+QR when due, overlap/inverse, local-energy contraction, weights, comb when
+due) for all walkers, inputs resident in HBM.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
+HBM_PEAK_GBS = 8000.0
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+
+
+def eprint(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def contraction_flops(M, nup, ndn, G, n_walkers):
+    """Algorithmic flops of the local-energy contraction Omega^g_s = Lh^g_s Theta_s:
+    real N x M by complex M x N products, 4 G N^2 M per walker and spin."""
+    return 4.0 * G * M * (nup * nup + ndn * ndn) * n_walkers
+
+
+def run_gpu(s, args, precision, steps, warmup, timed_kernels=True):
+    import torch
+
+    import paper_1711_02242_amd as afq
+    gs = afq.System.from_synthetic(s, dtau=args.dtau, precision=precision, qr_period=5,
+                                   pop_period=5)
+    wk = gs.walkers(args.walkers)
+    gs.init(wk)
+    for _ in range(warmup):
+        gs.step(wk, seed=args.seed)
+    torch.cuda.synchronize()
+    if timed_kernels:
+        gs.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gs.step(wk, seed=args.seed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = {}
+    if timed_kernels:
+        import paper_1711_02242_amd._lib as L
+        for g in L.KERNEL_GROUPS:
+            ms, n = gs.kernel_time(g)
+            kt[g] = (ms, n)
+        gs.kernel_timing(False)
+    e = gs.energy(wk)
+    return gs, wk, (t1 - t0), kt, e
+
+
+def cpu_baseline(s, args):
+    """The oracle as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+
+    from oracle import afqmc as A
+    from synthetic import comb_uniform, gaussian_fields
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, args.dtau)
+    P = A.Params(dtau=args.dtau)
+    nw, nsteps = args.cpu_walkers, args.cpu_steps
+    wk = A.init_walkers(S, nw)
+    t0 = time.perf_counter()
+    for k in range(nsteps):
+        x = gaussian_fields(args.seed, 0, wk.walker_id, k, s.n_chol)
+        A.step(S, P, wk, x, comb_uniform(args.seed, 0, k))
+    dt = time.perf_counter() - t0
+    return {"value": nw * nsteps / dt, "unit": "walker-steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{nw} walkers x {nsteps} steps of the same workload (NumPy FP64, "
+                      f"{dt:.1f} s)"}
+
+
+def el_error(s, args, gs, wk):
+    """Per-walker local-energy error of this precision on the current walkers: against the
+    GPU FP64 path on every walker, and against the FP64 oracle on a sample."""
+    import numpy as np
+    import torch
+
+    import paper_1711_02242_amd as afq
+    from oracle import afqmc as A
+    ref = afq.System.from_synthetic(s, dtau=args.dtau, precision="fp64")
+    wr = ref.walkers(wk.n)
+    ref.init(wr)
+    wr.U.copy_(wk.U)
+    wr.weight.copy_(wk.weight)
+    gs.measure(wk)
+    ref.measure(wr)
+    torch.cuda.synchronize()
+    alive = (wk.weight > 0).cpu().numpy()
+    e_lo = wk.e_loc.cpu().numpy()[alive]
+    e_64 = wr.e_loc.cpu().numpy()[alive]
+    err_gpu64 = float(np.abs(e_lo - e_64).max())
+    U = wk.U.cpu().numpy()
+    S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, args.dtau)
+    idx = np.nonzero(alive)[0][: args.oracle_sample]
+    err_or = 0.0
+    e_all = wk.e_loc.cpu().numpy()
+    for w in idx:
+        Uu = U[w, : s.n_up, :].T
+        Ud = U[w, s.n_up:, :].T
+        _, _, e, _ = A.measure(S, Uu, Ud)
+        err_or = max(err_or, abs(e_all[w] - e))
+    ref.close()
+    return err_gpu64, float(err_or), int(len(idx))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--walkers", type=int, default=1024)
+    ap.add_argument("--dtau", type=float, default=0.005)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain-FP64 GPU run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-walkers", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--oracle-sample", type=int, default=4)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only; the walker-parallel multi-GPU path "
+              "is a design (local comb per GPU, all-reduce of the estimator sums), not code. "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synthetic import config_system
+    torch.cuda.set_device(0)
+    s = config_system("large")
+    eprint(f"bench: M={s.M} N={s.n_up}+{s.n_dn} G={s.n_chol} walkers={args.walkers} "
+           f"precision={args.precision} steps={args.steps} warmup={args.warmup}")
+
+    gs, wk, dt, kt, e = run_gpu(s, args, args.precision, args.steps, args.warmup)
+    ms_step = 1e3 * dt / args.steps
+    value = args.walkers * args.steps / dt
+    ms_c, n_c = kt["contract"]
+    flops = contraction_flops(s.M, s.n_up, s.n_dn, s.n_chol, args.walkers)
+    avg_s = (ms_c / max(n_c, 1)) * 1e-3
+    achieved = flops / avg_s / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "local-energy contraction", "avg_launch_ms": round(ms_c / max(n_c, 1), 4),
+                "flops_per_launch": flops}
+    kernels_ms = {k: round(v[0] / max(args.steps, 1), 4) for k, v in kt.items()}
+    eprint(f"bench: {ms_step:.3f} ms/step, {value:.1f} walker-steps/s; per-step kernel ms {kernels_ms}")
+    eprint(f"bench: E_mix = {e[0] / e[2]:.8f}, alive {e[3]}, status {e[4]:#x}")
+
+    out = {"metric": "walker-steps/s at M=128,N=32,Ng=800 (phaseless AFQMC step)",
+           "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPE[args.precision], "data": "synthetic",
+           "config": {"workload": "synthetic molecule M=128 N_up=N_dn=32 N_g=800, 1024 walkers, "
+                                  "dtau=0.005, QR and comb every 5 steps",
+                      "M": s.M, "n_up": s.n_up, "n_dn": s.n_dn, "n_chol": s.n_chol,
+                      "n_walkers": args.walkers, "precision": args.precision},
+           "roofline": roofline, "kernel_ms_per_step": kernels_ms,
+           "e_mix": e[0] / e[2]}
+
+    if args.precision != "fp64":
+        err64, err_or, n_or = el_error(s, args, gs, wk)
+        out["el_error_ha"] = {"vs_gpu_fp64_all_walkers": err64, "vs_oracle_sample": err_or,
+                              "oracle_sample_walkers": n_or}
+        gs.close()
+        if not args.no_compare:
+            g2, w2, dt2, kt2, e2 = run_gpu(s, args, "fp64", max(4, args.steps // 4), 2,
+                                           timed_kernels=False)
+            v64 = args.walkers * max(4, args.steps // 4) / dt2
+            out["fp64_gpu"] = {"value": round(v64, 2), "unit": "walker-steps/s",
+                               "ms_per_step": round(1e3 * dt2 / max(4, args.steps // 4), 3),
+                               "speedup_vs_fp64": round(value / v64, 3)}
+            g2.close()
+    else:
+        gs.close()
+
+    if not args.no_cpu:
+        cb = cpu_baseline(s, args)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,97 @@
+"""Mixed-precision contraction (FP32 MFMA, BF16x3 MFMA) against the FP64 oracle.
+
+Bar: per-walker local energy within 1e-4 Ha of the FP64 value on identical
+walker states; the force-bias traces enter the dynamics, checked through short
+lockstep runs whose drift from the oracle is bounded.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import afqmc as A
+from synthetic import config_system, gen_system, random_walkers
+from tests.parity_helpers import gpu_state, log, make_pair, oracle_U_to_gpu, run_lockstep
+
+pytestmark = pytest.mark.gpu
+
+EL_TOL = 1e-4   # Ha, per walker
+
+
+def _static(s, nw, precision, amplitude, seed=99, oracle_sample=None):
+    import torch
+    U = random_walkers(s, nw, seed=seed, amplitude=amplitude)
+    S, P, wo, gs, wk = make_pair(s, nw, dtau=0.005, precision=precision, U=U)
+    st = gpu_state(wk)
+    n = nw if oracle_sample is None else oracle_sample
+    err = np.abs(st["e"][:n] - wo.e_loc[:n]).max()
+    arg_err = np.abs(st["arg"][:n] - wo.arg[:n]).max()
+    return err, arg_err, gs, wk
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["tiny", "medium", "ragged", "open_shell", "n16"])
+def test_static_local_energy(precision, case):
+    if case in ("tiny", "medium"):
+        s, nw = config_system(case), 24
+    elif case == "ragged":
+        s, nw = gen_system(13, 3, 19, seed=5), 7
+    elif case == "open_shell":
+        s, nw = gen_system(40, 11, 150, seed=6, n_dn=7), 9
+    else:
+        s, nw = gen_system(50, 16, 300, seed=11), 6
+    log(f"static {precision} {case} M={s.M} N={s.n_up}+{s.n_dn} G={s.n_chol}")
+    err, arg_err, gs, wk = _static(s, nw, precision, amplitude=0.5)
+    log(f"  max |dE_L| = {err:.3e} Ha")
+    assert err < EL_TOL
+    assert arg_err < 1e-12      # overlaps stay FP64 in every mode
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_static_local_energy_large_all_walkers(precision):
+    """Full workload (M=128, N=32+32, N_g=800, 1024 walkers, the launch the benchmark
+    times): every walker's E_L against the GPU FP64 path, and a sample of 3 against the
+    oracle itself."""
+    import torch
+
+    import paper_1711_02242_amd as afq
+    s = config_system("large")
+    nw = 1024
+    log(f"static large {precision} all walkers")
+    U = random_walkers(s, nw, seed=7, amplitude=0.3)
+    Ug = torch.from_numpy(oracle_U_to_gpu(*U)).cuda()
+    res = {}
+    for prec in ("fp64", precision):
+        gs = afq.System.from_synthetic(s, dtau=0.005, precision=prec)
+        wk = gs.walkers(nw)
+        gs.init(wk)
+        wk.U.copy_(Ug)
+        gs.measure(wk)
+        torch.cuda.synchronize()
+        res[prec] = wk.e_loc.cpu().numpy()
+        gs.close()
+    err = np.abs(res[precision] - res["fp64"]).max()
+    log(f"  max |dE_L| vs GPU FP64 over 1024 walkers = {err:.3e} Ha")
+    assert err < EL_TOL
+    S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, 0.005)
+    for w in (0, 511, 1023):
+        _, _, e, _ = A.measure(S, U[0][w], U[1][w])
+        assert abs(res["fp64"][w] - e) < 1e-10 * abs(e)
+        assert abs(res[precision][w] - e) < EL_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_dynamic_drift_tiny(precision):
+    """40 lockstep steps of the tiny molecule with the same fields: the mixed-precision
+    trajectory stays within the stated local-energy tolerance of the oracle's."""
+    s = config_system("tiny")
+    log(f"dynamic {precision}")
+    worst, *_ = run_lockstep(s, 16, 40, dtau=0.01, precision=precision, rtol=5e-5,
+                             label=f"tiny-{precision}")
+    log(f"  worst {worst}")
+
+
+def test_mixed_precision_refuses_unsupported_sizes():
+    import paper_1711_02242_amd as afq
+    s = gen_system(136, 34, 40, seed=1)
+    with pytest.raises(afq.AfqmcError):
+        afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
