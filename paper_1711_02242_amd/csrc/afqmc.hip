@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "kernels_fp64.hpp"
 #include "kernels_mfma.hpp"
+#include "kernels_prop.hpp"
 
 namespace {
 
@@ -26,7 +27,7 @@ struct TimedLaunch {
 
 struct WsLayout {
   size_t thetaT, tcur, tpart, exch, e1, logdet, wflag, enew, y, A, X0, X1, Y, parent, csum,
-      wnew, asnap, lsnap, esum, thetaP, total;
+      wnew, asnap, lsnap, esum, thetaP, y32, total;
 };
 
 }  // namespace
@@ -45,6 +46,9 @@ struct afqmc_sys_s {
   double* ht = nullptr;    // [ntot][M]
   unsigned* status = nullptr;
   MfmaTables mt;           // packed low-precision copies for the MFMA contraction
+  float* Lt32 = nullptr;   // [M*M][Gp] FP32 transposed Cholesky tensor (A-build operand)
+  float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
+  int Gp = 0;              // G rounded up to 32
   size_t device_bytes = 0;
   // timing
   bool timing = false;
@@ -86,6 +90,7 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.lsnap = take(nw * 8);
   L.esum = take(64);
   L.thetaP = take(mfma_theta_bytes(S->mt, nw));
+  L.y32 = take(S->mt.enabled ? nw * 2 * (size_t)S->Gp * 4 : 0);
   L.total = o;
   return L;
 }
@@ -236,6 +241,8 @@ void free_sys(afqmc_sys_s* S) {
   hipFree(S->Lh);
   hipFree(S->ht);
   hipFree(S->status);
+  hipFree(S->Lt32);
+  hipFree(S->Eh32);
   mfma_free_tables(S->mt);
   delete S;
 }
@@ -527,6 +534,16 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
       free_sys(S);
       return rc;
     }
+    S->Gp = ((G + 31) / 32) * 32;
+    std::vector<float> lt((size_t)M * M * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
+    for (int g = 0; g < G; ++g)
+      for (size_t e = 0; e < (size_t)M * M; ++e) lt[e * S->Gp + g] = (float)L_chol[(size_t)g * M * M + e];
+    for (size_t e = 0; e < eh.size(); ++e) eh[e] = (float)Eh[e];
+    if ((rc = dev_upload(S, &S->Lt32, lt.data(), lt.size())) ||
+        (rc = dev_upload(S, &S->Eh32, eh.data(), eh.size()))) {
+      free_sys(S);
+      return rc;
+    }
   }
   *out = S;
   return AFQMC_OK;
@@ -582,24 +599,39 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
   const int64_t k = w->step;
   // 1. fields and force bias
   if ((rc = launch_fields(s, w, f, L, nullptr))) return rc;
-  // 2. propagator exponent A
-  if (s->G > 0) {
-    Timer tm(s, KG_ABUILD);
-    if (s->p.precision == AFQMC_FP64 || !s->mt.enabled) {
-      constexpr int WT = 8;
-      dim3 grid((M * M + 255) / 256, (nw + WT - 1) / WT);
-      hipLaunchKernelGGL(k_abuild_fp64<WT>, grid, dim3(256), 0, s->stream, nw, M, s->G, s->s, s->L,
-                         at<cd>(ws, L.y), at<cd>(ws, L.A));
-    } else {
-      constexpr int WT = 8;
-      dim3 grid((M * M + 255) / 256, (nw + WT - 1) / WT);
-      hipLaunchKernelGGL(k_abuild_fp64<WT>, grid, dim3(256), 0, s->stream, nw, M, s->G, s->s, s->L,
-                         at<cd>(ws, L.y), at<cd>(ws, L.A));
+  // 2-3. propagator exponent A and propagation U <- E_h T_n(A) E_h U
+  if (s->mt.enabled) {
+    float* Are = at<float>(ws, L.A);
+    float* Aim = Are + (size_t)nw * M * M;
+    if (s->G > 0) {
+      Timer tm(s, KG_ABUILD);
+      const size_t ne = (size_t)nw * s->Gp;
+      hipLaunchKernelGGL(k_y_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s->stream, nw,
+                         s->G, s->Gp, at<cd>(ws, L.y), at<float>(ws, L.y32));
+      dim3 grid((2 * nw + AB_BM - 1) / AB_BM, (M * M + AB_BN - 1) / AB_BN);
+      hipLaunchKernelGGL(k_abuild_f32, grid, dim3(256), 0, s->stream, 2 * nw, M * M, s->Gp,
+                         (float)s->s, at<float>(ws, L.y32), s->Lt32, Are, Aim);
+      HIPCHK(hipGetLastError());
     }
-    HIPCHK(hipGetLastError());
-  }
-  // 3. propagation U <- E_h T_n(A) E_h U
-  {
+    {
+      Timer tm(s, KG_PROP);
+      const int Kp = ((M + 15) / 16) * 16;
+      const size_t shm = (size_t)2 * 16 * PR_RB * (Kp + 4) * 4;
+      (void)hipFuncSetAttribute((const void*)k_propagate_f32,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL(k_propagate_f32, dim3(nw), dim3(64 * (Kp / 16)), shm, s->stream, M, nt, Kp,
+                         s->G > 0 ? s->p.n_taylor : 0, s->Eh32, Are, Aim, (cd*)w->U, w->weight);
+      HIPCHK(hipGetLastError());
+    }
+  } else {
+    if (s->G > 0) {
+      Timer tm(s, KG_ABUILD);
+      constexpr int WT = 8;
+      dim3 grid((M * M + 255) / 256, (nw + WT - 1) / WT);
+      hipLaunchKernelGGL(k_abuild_fp64<WT>, grid, dim3(256), 0, s->stream, nw, M, s->G, s->s, s->L,
+                         at<cd>(ws, L.y), at<cd>(ws, L.A));
+      HIPCHK(hipGetLastError());
+    }
     Timer tm(s, KG_PROP);
     dim3 grid((M + 63) / 64, (nt + 31) / 32, nw);
     cd* U = (cd*)w->U;

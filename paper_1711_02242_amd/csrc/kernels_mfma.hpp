@@ -257,8 +257,10 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
   }
 
   double xr = 0.0, xi = 0.0;
-  AFQMC_GLOAD(0);
-  AFQMC_LSTORE(Abuf0);
+  if (G > 0) {
+    AFQMC_GLOAD(0);
+    AFQMC_LSTORE(Abuf0);
+  }
   __syncthreads();
   for (int g = 0; g < G; ++g) {
     unsigned char* Acur = (g & 1) ? Abuf1 : Abuf0;
@@ -428,7 +430,6 @@ inline hipError_t mfma_pack_theta(const MfmaTables& t, hipStream_t st, int nw, i
 
 inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int G,
                                 const void* thetaP, const double* weight, cd* tpart, cd* exch) {
-  if (G == 0) return hipSuccess;
   const size_t shm = mfma_contract_lds_bytes(t);
   dim3 grid((nw + MFMA_WAVES - 1) / MFMA_WAVES, 2);
   const bool bf = t.precision == AFQMC_BF16X3;

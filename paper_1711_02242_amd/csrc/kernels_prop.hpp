@@ -1,0 +1,312 @@
+// FP32 MFMA kernels of the propagation (arXiv:1711.02242, Sec. III.D.2, Theorem 1.4,
+// eq:primitive):
+//
+//   A_w = i s sum_g y_wg L^g                       (propagator exponent, y = x - xbar)
+//   U_w <- E_h T_n(A_w) E_h U_w,   T_n(A) = sum_{k<=n} A^k / k!,   E_h = exp(-dtau/2 v0)
+//
+// Walker orbitals are rows (U^T, orbital-major), so the propagation multiplies
+// the rows from the right: u' = u E_h T_n(A) E_h, using E_h^T = E_h and
+// A^T = A (every L^g is symmetric).  Both MFMA operands are then contiguous
+// along the contraction index.
+#pragma once
+
+#include "common.hpp"
+#include "kernels_mfma.hpp"
+
+// ---------------------------------------------------------------------------
+// A-build as a tiled MFMA GEMM:  C[r][col] = sum_k Y[r][k] Lt[col][k]
+//   r = 2w + (0: Re y, 1: Im y),  col = q*M + p,  k = g (padded to Gp, zeros).
+//   Re A_w[col] = -s C[2w+1][col],  Im A_w[col] = s C[2w][col]  (planar FP32 output).
+// Tile 128 x 128 per workgroup, K chunks of 32 double-buffered in LDS,
+// 4 wavefronts of 64 x 64 (2 x 2 blocks of v_mfma_f32_32x32x2_f32).
+// ---------------------------------------------------------------------------
+constexpr int AB_BM = 128, AB_BN = 128, AB_BK = 32, AB_LD = AB_BK + 4;
+
+__global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM, int Gp, float s,
+                                                       const float* __restrict__ Y,
+                                                       const float* __restrict__ Lt,
+                                                       float* __restrict__ Are,
+                                                       float* __restrict__ Aim) {
+  __shared__ __attribute__((aligned(16))) float As[2][AB_BM * AB_LD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][AB_BN * AB_LD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r0 = blockIdx.x * AB_BM, c0 = blockIdx.y * AB_BN;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int col = lane & 31, h = lane >> 5;
+  // each thread moves 4 float4 of A and 4 of B per K chunk
+  f32x4 pa[4], pb[4];
+#define AB_GLOAD(K0_)                                                                    \
+  do {                                                                                   \
+    _Pragma("unroll") for (int c_ = 0; c_ < 4; ++c_) {                                   \
+      const int e_ = tid + c_ * 256;                                                     \
+      const int rr_ = e_ >> 3, kk_ = (e_ & 7) * 4;                                       \
+      const int gr_ = r0 + rr_, gc_ = c0 + rr_;                                          \
+      const int sr_ = gr_ < rows ? gr_ : 0, sc_ = gc_ < MM ? gc_ : 0;                     \
+      f32x4 va_ = *reinterpret_cast<const f32x4*>(Y + (size_t)sr_ * Gp + (K0_) + kk_);   \
+      f32x4 vb_ = *reinterpret_cast<const f32x4*>(Lt + (size_t)sc_ * Gp + (K0_) + kk_);  \
+      if (gr_ >= rows) va_ = f32x4{0.f, 0.f, 0.f, 0.f};                                  \
+      if (gc_ >= MM) vb_ = f32x4{0.f, 0.f, 0.f, 0.f};                                    \
+      pa[c_] = va_;                                                                      \
+      pb[c_] = vb_;                                                                      \
+    }                                                                                    \
+  } while (0)
+#define AB_LSTORE(BUF_)                                                                  \
+  do {                                                                                   \
+    _Pragma("unroll") for (int c_ = 0; c_ < 4; ++c_) {                                   \
+      const int e_ = tid + c_ * 256;                                                     \
+      const int rr_ = e_ >> 3, kk_ = (e_ & 7) * 4;                                       \
+      *reinterpret_cast<f32x4*>(&As[BUF_][rr_ * AB_LD + kk_]) = pa[c_];                  \
+      *reinterpret_cast<f32x4*>(&Bs[BUF_][rr_ * AB_LD + kk_]) = pb[c_];                  \
+    }                                                                                    \
+  } while (0)
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
+  const int nk = Gp / AB_BK;
+  AB_GLOAD(0);
+  AB_LSTORE(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) AB_GLOAD((kc + 1) * AB_BK);
+#pragma unroll
+    for (int s8 = 0; s8 < AB_BK / 8; ++s8) {
+      f32x4 fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        fa[a] = *reinterpret_cast<const f32x4*>(&As[buf][(wr + 32 * a + col) * AB_LD + 8 * s8 + 4 * h]);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        fb[b] = *reinterpret_cast<const f32x4*>(&Bs[buf][(wc + 32 * b + col) * AB_LD + 8 * s8 + 4 * h]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[a][e], fb[b][e], acc[a][b], 0, 0, 0);
+    }
+    if (kc + 1 < nk) AB_LSTORE(buf ^ 1);
+    __syncthreads();
+  }
+#undef AB_GLOAD
+#undef AB_LSTORE
+  // epilogue: rows 8*(v/4) + 4h + v%4; v%4 in {0,1} -> walker rows (Re, Im), {2,3} next walker
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int cc = c0 + wc + 32 * b + col;
+      if (cc >= MM) continue;
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const int r = r0 + wr + 32 * a + 8 * (v / 4) + 4 * h + (v % 4);  // even
+        if (r >= rows) continue;
+        const int w = r >> 1;
+        Are[(size_t)w * MM + cc] = -s * acc[a][b][v + 1];
+        Aim[(size_t)w * MM + cc] = s * acc[a][b][v];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused propagation of one walker per workgroup: u' = u E_h T_n(A) E_h for all
+// its orbitals u (rows).  One wavefront per 16 output columns q; the wave keeps
+// its columns of A (Re, Im) and of E_h in registers as the MFMA B operand for
+// the whole Taylor series, while the current term (rows c, FP32 Re/Im planes)
+// lives in LDS as the A operand.  Sum Y of the series accumulates in registers.
+// v_mfma_f32_16x16x4_f32; output lane layout: column j = lane % 16, rows 4*(lane/16) + v.
+// Requirements: M <= 128, ntot <= 64.
+// ---------------------------------------------------------------------------
+constexpr int PR_RB = 4;  // row blocks of 16 (ntot <= 64)
+
+__global__ void __launch_bounds__(512, 1) k_propagate_f32(
+    int M, int ntot, int Kp, int n_taylor, const float* __restrict__ Eh32 /*[M][M]*/,
+    const float* __restrict__ Are, const float* __restrict__ Aim, cd* __restrict__ U,
+    const double* __restrict__ weight) {
+  extern __shared__ __attribute__((aligned(16))) float tsm[];
+  const int w = blockIdx.x;
+  if (!(weight[w] > 0.0)) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nwave = blockDim.x >> 6;
+  const int ldt = Kp + 4;
+  const int RP = 16 * PR_RB;
+  float* Tr = tsm;             // [RP][ldt]
+  float* Ti = tsm + RP * ldt;  // [RP][ldt]
+  const int j = lane & 15, q4 = lane >> 4;
+  const int qcol = 16 * wave + j;  // output column owned by the lane
+  const int MM = M * M;
+  const int nkc = Kp / 16;
+  constexpr int KCMAX = 8;  // Kp <= 128
+  const int nrb = (ntot + 15) / 16;
+
+  // load U rows (FP64 complex) into the term planes, zero padding
+  const cd* Uw = U + (size_t)w * ntot * M;
+  for (int e = tid; e < RP * Kp; e += blockDim.x) {
+    const int c = e / Kp, p = e % Kp;
+    cd v = mkc(0.0, 0.0);
+    if (c < ntot && p < M) v = Uw[(size_t)c * M + p];
+    Tr[c * ldt + p] = (float)v.re;
+    Ti[c * ldt + p] = (float)v.im;
+  }
+  // B operands: lane holds rows q = qcol, k = 16*kc + 4*q4 .. +3
+  f32x4 be[KCMAX], bar_[KCMAX], bai[KCMAX];
+  const bool colok = qcol < M;
+#pragma unroll
+  for (int kc = 0; kc < KCMAX; ++kc) {
+    be[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bar_[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bai[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (kc < nkc && colok) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int p = 16 * kc + 4 * q4 + e;
+        if (p < M) {
+          be[kc][e] = Eh32[(size_t)qcol * M + p];
+          bar_[kc][e] = Are[(size_t)w * MM + (size_t)qcol * M + p];
+          bai[kc][e] = Aim[(size_t)w * MM + (size_t)qcol * M + p];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  f32x4 yre[PR_RB], yim[PR_RB], cre[PR_RB], cim[PR_RB];
+  // X = U E_h  (real B operand)
+#pragma unroll
+  for (int rb = 0; rb < PR_RB; ++rb) {
+    cre[rb] = f32x4{};
+    cim[rb] = f32x4{};
+  }
+#pragma unroll
+  for (int kc = 0; kc < KCMAX; ++kc) {
+    if (kc >= nkc) break;
+#pragma unroll
+    for (int rb = 0; rb < PR_RB; ++rb) {
+      if (rb >= nrb) break;
+      const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+      const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], be[kc][e], cre[rb], 0, 0, 0);
+        cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], be[kc][e], cim[rb], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+  // write X back as the first term, Y = X
+#pragma unroll
+  for (int rb = 0; rb < PR_RB; ++rb) {
+    yre[rb] = cre[rb];
+    yim[rb] = cim[rb];
+    if (rb < nrb && qcol < Kp) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Tr[(16 * rb + 4 * q4 + v) * ldt + qcol] = cre[rb][v];
+        Ti[(16 * rb + 4 * q4 + v) * ldt + qcol] = cim[rb][v];
+      }
+    }
+  }
+  __syncthreads();
+  // Taylor terms: T <- T A / n, Y += T
+  for (int n = 1; n <= n_taylor; ++n) {
+#pragma unroll
+    for (int rb = 0; rb < PR_RB; ++rb) {
+      cre[rb] = f32x4{};
+      cim[rb] = f32x4{};
+    }
+#pragma unroll
+    for (int kc = 0; kc < KCMAX; ++kc) {
+      if (kc >= nkc) break;
+#pragma unroll
+      for (int rb = 0; rb < PR_RB; ++rb) {
+        if (rb >= nrb) break;
+        const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+        const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], bar_[kc][e], cre[rb], 0, 0, 0);
+          cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[e], bai[kc][e], cre[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], bai[kc][e], cim[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], bar_[kc][e], cim[rb], 0, 0, 0);
+        }
+      }
+    }
+    const float inv = 1.0f / (float)n;
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < PR_RB; ++rb) {
+      cre[rb] *= inv;
+      cim[rb] *= inv;
+      yre[rb] += cre[rb];
+      yim[rb] += cim[rb];
+      if (rb < nrb && qcol < Kp) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Tr[(16 * rb + 4 * q4 + v) * ldt + qcol] = cre[rb][v];
+          Ti[(16 * rb + 4 * q4 + v) * ldt + qcol] = cim[rb][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Y into the planes, then U' = Y E_h
+#pragma unroll
+  for (int rb = 0; rb < PR_RB; ++rb) {
+    if (rb < nrb && qcol < Kp) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Tr[(16 * rb + 4 * q4 + v) * ldt + qcol] = yre[rb][v];
+        Ti[(16 * rb + 4 * q4 + v) * ldt + qcol] = yim[rb][v];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < PR_RB; ++rb) {
+    cre[rb] = f32x4{};
+    cim[rb] = f32x4{};
+  }
+#pragma unroll
+  for (int kc = 0; kc < KCMAX; ++kc) {
+    if (kc >= nkc) break;
+#pragma unroll
+    for (int rb = 0; rb < PR_RB; ++rb) {
+      if (rb >= nrb) break;
+      const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+      const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], be[kc][e], cre[rb], 0, 0, 0);
+        cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], be[kc][e], cim[rb], 0, 0, 0);
+      }
+    }
+  }
+  cd* Uo = U + (size_t)w * ntot * M;
+#pragma unroll
+  for (int rb = 0; rb < PR_RB; ++rb) {
+    if (rb >= nrb || !colok) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = 16 * rb + 4 * q4 + v;
+      if (c < ntot) Uo[(size_t)c * M + qcol] = mkc((double)cre[rb][v], (double)cim[rb][v]);
+    }
+  }
+  (void)nwave;
+}
+
+// Fields for the FP32 A-build: Y[2w][g] = Re y, Y[2w+1][g] = Im y, zero for g >= G (< Gp).
+__global__ void __launch_bounds__(256) k_y_to_f32(int nw, int G, int Gp, const cd* __restrict__ y,
+                                                  float* __restrict__ Y) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)nw * Gp) return;
+  const int w = (int)(e / Gp), g = (int)(e % Gp);
+  cd v = mkc(0.0, 0.0);
+  if (g < G) v = y[(size_t)w * G + g];
+  Y[(size_t)(2 * w) * Gp + g] = (float)v.re;
+  Y[(size_t)(2 * w + 1) * Gp + g] = (float)v.im;
+}

@@ -90,6 +90,29 @@ def test_dynamic_drift_tiny(precision):
     log(f"  worst {worst}")
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["medium", "large", "ragged", "no_cholesky"])
+def test_dynamic_drift_shapes(precision, case):
+    """Lockstep runs through the mixed-precision A-build, propagation and contraction:
+    after every step each walker's E_L stays within 1e-4 Ha of the FP64 oracle's
+    (same fields), and weights / orbitals within 1e-4 relative."""
+    if case == "medium":
+        s, nw, steps, dt = config_system("medium"), 8, 10, 0.005
+    elif case == "large":
+        s, nw, steps, dt = config_system("large"), 3, 5, 0.005
+    elif case == "ragged":
+        s, nw, steps, dt = gen_system(13, 3, 19, seed=5), 7, 12, 0.01
+    else:
+        s, nw, steps, dt = gen_system(9, 2, 0, seed=8), 5, 10, 0.05
+    log(f"dynamic {precision} {case}")
+    worst, gs, wk, S, wo = run_lockstep(s, nw, steps, dtau=dt, precision=precision, rtol=1e-4,
+                                        label=f"{case}-{precision}", check_every=1)
+    st = gpu_state(wk)
+    alive = wo.W > 0
+    assert np.abs(st["e"][alive] - wo.e_loc[alive]).max() < EL_TOL
+    log(f"  worst {worst}")
+
+
 def test_mixed_precision_refuses_unsupported_sizes():
     import paper_1711_02242_amd as afq
     s = gen_system(136, 34, 40, seed=1)
