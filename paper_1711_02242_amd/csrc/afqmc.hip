@@ -49,6 +49,7 @@ struct afqmc_sys_s {
   float* Lt32 = nullptr;   // [M*M][Gp] FP32 transposed Cholesky tensor (A-build operand)
   float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
   int Gp = 0;              // G rounded up to 32
+  bool packed_by_overlap = false;  // the last overlap launch also wrote the MFMA operand
   size_t device_bytes = 0;
   // timing
   bool timing = false;
@@ -256,16 +257,35 @@ int check_walkers(const afqmc_sys_s* S, const afqmc_walkers* w) {
   return AFQMC_OK;
 }
 
+size_t gj_lds_bytes(const afqmc_sys_s* S) {
+  const size_t N = std::max(S->nup, S->ndn), M = S->M;
+  return N * (M + 1) * 16 + N * (2 * N + 1) * 16 + N * 16 + 64;
+}
+
 int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, int check_weight) {
   Timer tm(S, KG_OVERLAP);
   const int nmax = std::max(S->nup, S->ndn);
-  const size_t shm = (size_t)nmax * (nmax + 1) * 16 + 64 * 4 + 8 * 8;
   dim3 grid(w->n_walkers, 2);
   void* ws = w->workspace;
+  const size_t gj = gj_lds_bytes(S);
+  if (gj <= 150 * 1024) {
+    (void)hipFuncSetAttribute((const void*)k_overlap_gj, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)gj);
+    void* packed = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
+    hipLaunchKernelGGL(k_overlap_gj, grid, dim3(256), gj, S->stream, S->M, S->nup, S->ndn, S->V,
+                       S->ht, (const cd*)w->U, w->weight, check_weight, at<cd>(ws, L.thetaT),
+                       at<cd>(ws, L.logdet), at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed,
+                       S->mt.precision == AFQMC_BF16X3 ? 1 : 0, S->mt.NP, S->mt.KP);
+    S->packed_by_overlap = S->mt.enabled;
+    HIPCHK(hipGetLastError());
+    return AFQMC_OK;
+  }
+  S->packed_by_overlap = false;
+  const size_t shm = (size_t)nmax * (nmax + 1) * 16 + 64 * 4 + 8 * 8;
 #define OVL(NM)                                                                                \
   do {                                                                                         \
-    (void)hipFuncSetAttribute((const void*)k_overlap_theta<NM>,                                      \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                 \
+    (void)hipFuncSetAttribute((const void*)k_overlap_theta<NM>,                                \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
     hipLaunchKernelGGL(k_overlap_theta<NM>, grid, dim3(256), shm, S->stream, S->M, S->nup,      \
                        S->ndn, S->V, S->ht, (const cd*)w->U, w->weight, check_weight,          \
                        at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet), at<cd>(ws, L.e1),           \
@@ -297,7 +317,7 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
                        at<cd>(ws, L.tpart), at<cd>(ws, L.exch));
     HIPCHK(hipGetLastError());
   } else {
-    {
+    if (!S->packed_by_overlap) {
       Timer tm(S, KG_OVERLAP);
       HIPCHK(mfma_pack_theta(S->mt, S->stream, w->n_walkers, S->M, S->nup, S->ndn,
                              at<cd>(ws, L.thetaT), w->weight, at<void>(ws, L.thetaP)));

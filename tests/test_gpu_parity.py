@@ -145,3 +145,24 @@ def test_gpu_run_is_deterministic(torch_cuda):
         gs.close()
     for key in ("U", "W", "arg", "e"):
         assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gpu_singular_and_nonfinite_walkers_are_killed(torch_cuda, precision):
+    """A walker with a zero orbital (singular overlap) or a NaN entry gets W = 0 and sets the
+    status word; the other walkers are untouched and the estimator stays finite."""
+    s = config_system("medium")
+    _, _, wo, gs, wk = make_pair(s, 6, dtau=0.005, precision=precision)
+    e_before = gpu_state(wk)["e"].copy()
+    wk.U[1, 3, :] = 0.0
+    wk.U[4, 20, 7] = float("nan")
+    gs.measure(wk)
+    st = gpu_state(wk)
+    assert st["W"][1] == 0.0 and st["W"][4] == 0.0
+    assert np.all(st["W"][[0, 2, 3, 5]] == 1.0)
+    assert np.array_equal(st["e"][[0, 2, 3, 5]], e_before[[0, 2, 3, 5]])
+    assert gs.status() & 0x2
+    a, b, c, n, status = gs.energy(wk)
+    assert n == 4 and np.isfinite(a) and c == 4.0
+    gs.step(wk, seed=1)
+    assert gpu_state(wk)["W"][1] == 0.0
