@@ -121,7 +121,7 @@ typedef struct {
   const double* x;       /* NULL: draw the fields on the device from the counter stream
                             (block, walker_id, step, 0); else device [n_walkers][n_chol]
                             fields for this step, read as given                              */
-  double u_comb;         /* comb uniform in (0,1) if population control is due; NaN: draw it
+  double u_comb;         /* comb uniform in (0,1] if population control is due; NaN: draw it
                             from the counter stream (0, 0, step, 1)                          */
 } afqmc_fields;
 

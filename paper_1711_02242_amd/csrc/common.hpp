@@ -90,7 +90,7 @@ __device__ inline u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uin
   return o;
 }
 
-// uint64 -> double in (0, 1): ((r >> 11) + 0.5) * 2^-53.
+// uint64 -> double in (0, 1]: ((r >> 11) + 0.5) * 2^-53 (equal to 1 only where the sum rounds up).
 __device__ inline double u64_unit(uint64_t r) {
   return ((double)(r >> 11) + 0.5) * 0x1p-53;
 }

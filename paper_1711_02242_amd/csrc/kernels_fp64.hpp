@@ -573,7 +573,7 @@ __global__ void k_comb_select(int nw, const double* __restrict__ weight, double 
                               unsigned* __restrict__ status) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double u = u_given;
-  if (!(u > 0.0 && u < 1.0)) {
+  if (isnan(u)) {
     const u64x4 r = philox4x64_10(0ull, 0ull, (uint64_t)step, 1ull, seed, job);
     u = u64_unit(r.v[0]);
   }

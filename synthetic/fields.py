@@ -15,7 +15,7 @@ Conventions (shared with the HIP library's own generator):
 * counter = (block, walker_id, step, stream)   -- 4 x uint64
 * stream STREAM_FIELDS (0): block c yields fields x[4c .. 4c+3];
   stream STREAM_COMB (1): block 0, walker 0 yields the comb's uniform.
-* uint64 r -> u = ((r >> 11) + 0.5) * 2**-53, in (0, 1).
+* uint64 r -> u = ((r >> 11) + 0.5) * 2**-53, in (0, 1] (1 only for the top 2^11 values of r, where the sum rounds up; u > 0 keeps log u finite).
 * Box-Muller on (u0, u1) and (u2, u3):
   z0 = sqrt(-2 ln u0) cos(2 pi u1), z1 = sqrt(-2 ln u0) sin(2 pi u1), same for z2, z3.
 """
@@ -72,7 +72,7 @@ def philox_u64(ctr, key, rounds: int = 10) -> np.ndarray:
 
 
 def u64_to_unit(r: np.ndarray) -> np.ndarray:
-    """uint64 -> double in the open interval (0, 1): ((r >> 11) + 0.5) * 2^-53."""
+    """uint64 -> double in (0, 1]: ((r >> 11) + 0.5) * 2^-53 (rounds to 1 only at the top of the range)."""
     r = np.asarray(r, dtype=np.uint64)
     return ((r >> np.uint64(11)).astype(np.float64) + 0.5) * (2.0 ** -53)
 
@@ -101,7 +101,7 @@ def gaussian_fields(seed: int, job_id: int, walker_ids, step: int, n_chol: int) 
 
 
 def comb_uniform(seed: int, job_id: int, step: int) -> float:
-    """The single uniform in (0,1) used by the population-control comb after ``step``."""
+    """The single uniform in (0, 1] used by the population-control comb after ``step``."""
     ctr = np.array([0, 0, step, STREAM_COMB], dtype=np.uint64)
     key = np.array([seed, job_id], dtype=np.uint64)
     return float(u64_to_unit(philox_u64(ctr, key)[0]))
