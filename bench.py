@@ -38,6 +38,24 @@ def contraction_flops(M, nup, ndn, G, n_walkers):
     return 4.0 * G * M * (nup * nup + ndn * ndn) * n_walkers
 
 
+def recorded_traffic(precision):
+    """HBM bytes per launch of the contraction from the committed PMC summary, or None when
+    there is none for this precision or the kernel source changed since it was taken."""
+    import hashlib
+    if precision != "fp32":
+        return None
+    path = os.path.join(ROOT, "profiles", "contract_fp32_M128_N32_G800_W1024_traffic.md")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch", "kernel_source", "source_sha256")))
+        src = open(os.path.join(ROOT, fields["kernel_source"].strip()), "rb").read()
+        if hashlib.sha256(src).hexdigest() != fields["source_sha256"].strip():
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_gpu(s, args, precision, steps, warmup, timed_kernels=True):
     import torch
 
@@ -137,11 +155,14 @@ def main():
     ap.add_argument("--walkers", type=int, default=1024)
     ap.add_argument("--dtau", type=float, default=0.005)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-compare", action="store_true", help="skip the plain-FP64 GPU run")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain-FP64 GPU run and the local-energy error measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-walkers", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--oracle-sample", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -155,6 +176,13 @@ def main():
     from synthetic import config_system
     torch.cuda.set_device(0)
     s = config_system("large")
+    if args.copy_calibration:
+        n = 64 << 20
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        b = a.clone()
+        torch.cuda.synchronize()
+        del a, b
     eprint(f"bench: M={s.M} N={s.n_up}+{s.n_dn} G={s.n_chol} walkers={args.walkers} "
            f"precision={args.precision} steps={args.steps} warmup={args.warmup}")
 
@@ -167,7 +195,8 @@ def main():
     achieved = flops / avg_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": recorded_traffic(args.precision),
+                "traffic_unit": "bytes/launch",
                 "kernel": "local-energy contraction", "avg_launch_ms": round(ms_c / max(n_c, 1), 4),
                 "flops_per_launch": flops}
     kernels_ms = {k: round(v[0] / max(args.steps, 1), 4) for k, v in kt.items()}
@@ -186,19 +215,18 @@ def main():
            "roofline": roofline, "kernel_ms_per_step": kernels_ms,
            "e_mix": e[0] / e[2]}
 
-    if args.precision != "fp64":
+    if args.precision != "fp64" and not args.no_compare:
         err64, err_or, n_or = el_error(s, args, gs, wk)
         out["el_error_ha"] = {"vs_gpu_fp64_all_walkers": err64, "vs_oracle_sample": err_or,
                               "oracle_sample_walkers": n_or}
         gs.close()
-        if not args.no_compare:
-            g2, w2, dt2, kt2, e2 = run_gpu(s, args, "fp64", max(4, args.steps // 4), 2,
-                                           timed_kernels=False)
-            v64 = args.walkers * max(4, args.steps // 4) / dt2
-            out["fp64_gpu"] = {"value": round(v64, 2), "unit": "walker-steps/s",
-                               "ms_per_step": round(1e3 * dt2 / max(4, args.steps // 4), 3),
-                               "speedup_vs_fp64": round(value / v64, 3)}
-            g2.close()
+        n64 = max(4, args.steps // 4)
+        g2, w2, dt2, kt2, e2 = run_gpu(s, args, "fp64", n64, 2, timed_kernels=False)
+        v64 = args.walkers * n64 / dt2
+        out["fp64_gpu"] = {"value": round(v64, 2), "unit": "walker-steps/s",
+                           "ms_per_step": round(1e3 * dt2 / n64, 3),
+                           "speedup_vs_fp64": round(value / v64, 3)}
+        g2.close()
     else:
         gs.close()
 
