@@ -49,7 +49,7 @@ struct afqmc_sys_s {
   float* Lt32 = nullptr;   // [M*M][Gp] FP32 transposed Cholesky tensor (A-build operand)
   float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
   int Gp = 0;              // G rounded up to 32
-  bool packed_by_overlap = false;  // the last overlap launch also wrote the MFMA operand
+  bool f32_prop = false;   // A-build and propagation on FP32 MFMA (mixed-precision modes)
   size_t device_bytes = 0;
   // timing
   bool timing = false;
@@ -91,7 +91,7 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.lsnap = take(nw * 8);
   L.esum = take(64);
   L.thetaP = take(mfma_theta_bytes(S->mt, nw));
-  L.y32 = take(S->mt.enabled ? nw * 2 * (size_t)S->Gp * 4 : 0);
+  L.y32 = take(S->f32_prop ? nw * 2 * (size_t)S->Gp * 4 : 0);
   L.total = o;
   return L;
 }
@@ -272,15 +272,17 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
     (void)hipFuncSetAttribute((const void*)k_overlap_gj, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)gj);
     void* packed = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
+    const int kind = !S->mt.enabled ? 0
+                     : S->mt.precision == AFQMC_FP64 ? 3
+                     : S->mt.precision == AFQMC_BF16X3 ? 2 : 1;
     hipLaunchKernelGGL(k_overlap_gj, grid, dim3(256), gj, S->stream, S->M, S->nup, S->ndn, S->V,
                        S->ht, (const cd*)w->U, w->weight, check_weight, at<cd>(ws, L.thetaT),
                        at<cd>(ws, L.logdet), at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed,
-                       S->mt.precision == AFQMC_BF16X3 ? 1 : 0, S->mt.NP, S->mt.KP);
-    S->packed_by_overlap = S->mt.enabled;
+                       kind, S->mt.NP, S->mt.KP);
     HIPCHK(hipGetLastError());
     return AFQMC_OK;
   }
-  S->packed_by_overlap = false;
+  if (S->mt.enabled) return AFQMC_E_UNSUPPORTED;  // the MFMA operand is packed by k_overlap_gj only
   const size_t shm = (size_t)nmax * (nmax + 1) * 16 + 64 * 4 + 8 * 8;
 #define OVL(NM)                                                                                \
   do {                                                                                         \
@@ -306,22 +308,26 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
 
 int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
   void* ws = w->workspace;
-  if (S->p.precision == AFQMC_FP64 || !S->mt.enabled) {
+  if (!S->mt.enabled) {
     Timer tm(S, KG_CONTRACT);
-    const int nmax = std::max(S->nup, S->ndn);
-    const size_t shm = (size_t)nmax * (S->M + 1) * 16 + (size_t)nmax * (nmax + 1) * 16 + 64;
-    (void)hipFuncSetAttribute((const void*)k_contract_fp64, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm);
-    hipLaunchKernelGGL(k_contract_fp64, dim3(w->n_walkers, 2), dim3(256), shm, S->stream, S->M,
-                       S->nup, S->ndn, S->G, S->Lh, at<cd>(ws, L.thetaT), w->weight,
-                       at<cd>(ws, L.tpart), at<cd>(ws, L.exch));
+    const size_t nmax = std::max(S->nup, S->ndn);
+    const size_t om = nmax * (nmax + 1) * 16 + 64;
+    const size_t staged = nmax * (S->M + 1) * 16 + om;
+    if (staged <= 150 * 1024) {
+      (void)hipFuncSetAttribute((const void*)k_contract_fp64<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)staged);
+      hipLaunchKernelGGL(k_contract_fp64<true>, dim3(w->n_walkers, 2), dim3(256), staged, S->stream,
+                         S->M, S->nup, S->ndn, S->G, S->Lh, at<cd>(ws, L.thetaT), w->weight,
+                         at<cd>(ws, L.tpart), at<cd>(ws, L.exch));
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_contract_fp64<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)om);
+      hipLaunchKernelGGL(k_contract_fp64<false>, dim3(w->n_walkers, 2), dim3(256), om, S->stream,
+                         S->M, S->nup, S->ndn, S->G, S->Lh, at<cd>(ws, L.thetaT), w->weight,
+                         at<cd>(ws, L.tpart), at<cd>(ws, L.exch));
+    }
     HIPCHK(hipGetLastError());
   } else {
-    if (!S->packed_by_overlap) {
-      Timer tm(S, KG_OVERLAP);
-      HIPCHK(mfma_pack_theta(S->mt, S->stream, w->n_walkers, S->M, S->nup, S->ndn,
-                             at<cd>(ws, L.thetaT), w->weight, at<void>(ws, L.thetaP)));
-    }
     Timer tm(S, KG_CONTRACT);
     HIPCHK(mfma_contract(S->mt, S->stream, w->n_walkers, S->G, at<void>(ws, L.thetaP), w->weight,
                          at<cd>(ws, L.tpart), at<cd>(ws, L.exch)));
@@ -547,13 +553,23 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
     free_sys(S);
     return AFQMC_E_HIP;
   }
-  if (p->precision != AFQMC_FP64) {
-    rc = mfma_build_tables(S->mt, p->precision, M, nup, ndn, G, Lh.data());
-    if (rc == AFQMC_OK) S->device_bytes += S->mt.bytes;
-    if (rc != AFQMC_OK) {
+  {
+    const bool fits = std::max(nup, ndn) <= 32 && M <= MFMA_KMAX && gj_lds_bytes(S) <= 150 * 1024;
+    if (!fits && p->precision != AFQMC_FP64) {
       free_sys(S);
-      return rc;
+      return AFQMC_E_UNSUPPORTED;
     }
+    if (fits) {
+      rc = mfma_build_tables(S->mt, p->precision, M, nup, ndn, G, Lh.data());
+      if (rc != AFQMC_OK) {
+        free_sys(S);
+        return rc;
+      }
+      S->device_bytes += S->mt.bytes;
+    }
+  }
+  if (p->precision != AFQMC_FP64) {
+    S->f32_prop = true;
     S->Gp = ((G + 31) / 32) * 32;
     std::vector<float> lt((size_t)M * M * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
     for (int g = 0; g < G; ++g)
@@ -620,7 +636,7 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
   // 1. fields and force bias
   if ((rc = launch_fields(s, w, f, L, nullptr))) return rc;
   // 2-3. propagator exponent A and propagation U <- E_h T_n(A) E_h U
-  if (s->mt.enabled) {
+  if (s->f32_prop) {
     float* Are = at<float>(ws, L.A);
     float* Aim = Are + (size_t)nw * M * M;
     if (s->G > 0) {

@@ -173,6 +173,7 @@ __global__ void __launch_bounds__(256) k_overlap_theta(
 // Omega = Lh^g_s Theta_s (N x N), tpart[w][s][g] = tr Omega and
 // exch[w][s] = sum_g tr(Omega Omega).  One block per (walker, spin).
 // ---------------------------------------------------------------------------
+template <bool THETA_IN_LDS>
 __global__ void __launch_bounds__(256) k_contract_fp64(
     int M, int nup, int ndn, int G, const double* __restrict__ Lh, const cd* __restrict__ thetaT,
     const double* __restrict__ weight, cd* __restrict__ tpart /*[nw][2][G]*/,
@@ -189,12 +190,15 @@ __global__ void __launch_bounds__(256) k_contract_fp64(
     return;
   }
   if (!(weight[w] > 0.0)) return;
-  const int ldt = M + 1;
-  cd* Th = reinterpret_cast<cd*>(smem_raw);        // [N][M+1]
-  cd* Om = Th + (size_t)N * ldt;                    // [N][N+1]
+  // Theta rows staged in LDS when they fit ([N][M+1]); otherwise read from global memory.
+  const int ldt = THETA_IN_LDS ? M + 1 : M;
+  cd* Ts = reinterpret_cast<cd*>(smem_raw);
+  cd* Om = THETA_IN_LDS ? Ts + (size_t)N * ldt : Ts;   // [N][N+1]
   double* red = reinterpret_cast<double*>(Om + (size_t)N * (N + 1));
   const cd* Tw = thetaT + ((size_t)w * ntot + off) * M;
-  for (int e = tid; e < N * M; e += blockDim.x) Th[(e / M) * ldt + e % M] = Tw[e];
+  if (THETA_IN_LDS)
+    for (int e = tid; e < N * M; e += blockDim.x) Ts[(e / M) * ldt + e % M] = Tw[e];
+  const cd* Th = THETA_IN_LDS ? Ts : Tw;
   __syncthreads();
   double xr = 0.0, xi = 0.0;
   for (int g = 0; g < G; ++g) {
@@ -684,7 +688,7 @@ __global__ void __launch_bounds__(256) k_overlap_gj(
     int M, int nup, int ndn, const double* __restrict__ V, const double* __restrict__ ht,
     const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
     cd* __restrict__ thetaT, cd* __restrict__ logdet, cd* __restrict__ e1,
-    unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_bf16, int NP, int KP) {
+    unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int w = blockIdx.x, s = blockIdx.y;
   const int N = s == 0 ? nup : ndn;
@@ -806,16 +810,17 @@ __global__ void __launch_bounds__(256) k_overlap_gj(
     const double hv = hts[(size_t)c * M + p];
     e1re = fma(hv, acc.re, e1re);
     e1im = fma(hv, acc.im, e1im);
-    if (packed && !packed_bf16) {
+    if (packed_kind == 3) {
+      double* o = reinterpret_cast<double*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
+      o[0] = acc.re;
+      o[per] = acc.im;
+    } else if (packed_kind == 1) {
       float* o = reinterpret_cast<float*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
       o[0] = (float)acc.re;
       o[per] = (float)acc.im;
-    } else if (packed) {
+    } else if (packed_kind == 2) {
       uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)w * 2 + s) * 4 * per + (size_t)c * KP + p;
       const float xr = (float)acc.re, xi = (float)acc.im;
-      uint32_t ur, ui;
-      memcpy(&ur, &xr, 4);
-      memcpy(&ui, &xi, 4);
       // round-to-nearest-even to bf16, then the residual likewise
       auto bf = [](float f) -> uint16_t {
         uint32_t u;
@@ -838,16 +843,16 @@ __global__ void __launch_bounds__(256) k_overlap_gj(
     }
   }
   // zero padding of the packed operand (rows N..NP-1, columns M..KP-1)
-  if (packed) {
-    const int planes = packed_bf16 ? 4 : 2;
+  if (packed_kind) {
+    const int planes = packed_kind == 2 ? 4 : 2;
     for (size_t e = tid; e < (size_t)planes * per; e += blockDim.x) {
       const int pl = (int)(e / per);
       const int c = (int)((e % per) / KP), p = (int)(e % KP);
       if (c < N && p < M) continue;
-      if (packed_bf16)
-        reinterpret_cast<uint16_t*>(packed)[((size_t)w * 2 + s) * 4 * per + (size_t)pl * per + (size_t)c * KP + p] = 0;
-      else
-        reinterpret_cast<float*>(packed)[((size_t)w * 2 + s) * 2 * per + (size_t)pl * per + (size_t)c * KP + p] = 0.f;
+      const size_t o = ((size_t)w * 2 + s) * planes * per + (size_t)pl * per + (size_t)c * KP + p;
+      if (packed_kind == 3) reinterpret_cast<double*>(packed)[o] = 0.0;
+      else if (packed_kind == 1) reinterpret_cast<float*>(packed)[o] = 0.f;
+      else reinterpret_cast<uint16_t*>(packed)[o] = 0;
     }
   }
   e1re = block_sum(e1re, red);

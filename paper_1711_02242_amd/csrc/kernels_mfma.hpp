@@ -40,9 +40,9 @@ constexpr int MFMA_WAVES = 4;
 
 struct MfmaTables {
   bool enabled = false;
-  int precision = 0;  // AFQMC_FP32 or AFQMC_BF16X3
+  int precision = 0;  // AFQMC_FP64, AFQMC_FP32 or AFQMC_BF16X3
   int NP = 0, KP = 0, M = 0, G = 0, nup = 0, ndn = 0;
-  void* Lp = nullptr;  // fp32: [2][G][NP][KP]; bf16x3: [2][G][2 (hi, lo)][NP][KP] bf16 bits
+  void* Lp = nullptr;  // fp64 / fp32: [2][G][NP][KP]; bf16x3: [2][G][2 (hi, lo)][NP][KP] bf16 bits
   size_t bytes = 0;
 };
 
@@ -63,7 +63,8 @@ __host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
 
 inline size_t mfma_theta_bytes(const MfmaTables& t, size_t nw) {
   if (!t.enabled) return 0;
-  return nw * 2 * 2 * (size_t)t.NP * t.KP * 4;  // fp32 re/im, or bf16 re/im x hi/lo
+  // fp32 re/im, or bf16 re/im x hi/lo (same bytes); fp64 re/im
+  return nw * 2 * 2 * (size_t)t.NP * t.KP * (t.precision == AFQMC_FP64 ? 8 : 4);
 }
 
 inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int ndn, int G,
@@ -79,7 +80,19 @@ inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int n
   t.ndn = ndn;
   const int nt = nup + ndn;
   const size_t per = (size_t)t.NP * t.KP;
-  if (precision == AFQMC_FP32) {
+  if (precision == AFQMC_FP64) {
+    std::vector<double> h((size_t)2 * G * per + 2, 0.0);
+    for (int s = 0; s < 2; ++s) {
+      const int N = s ? ndn : nup, off = s ? nup : 0;
+      for (int g = 0; g < G; ++g)
+        for (int r = 0; r < N; ++r)
+          for (int p = 0; p < M; ++p)
+            h[((size_t)s * G + g) * per + (size_t)r * t.KP + p] = Lh[((size_t)g * nt + off + r) * M + p];
+    }
+    t.bytes = h.size() * sizeof(double);
+    if (hipMalloc(&t.Lp, t.bytes) != hipSuccess) return AFQMC_E_NOMEM;
+    if (hipMemcpy(t.Lp, h.data(), t.bytes, hipMemcpyHostToDevice) != hipSuccess) return AFQMC_E_HIP;
+  } else if (precision == AFQMC_FP32) {
     std::vector<float> h((size_t)2 * G * per + 1, 0.0f);
     for (int s = 0; s < 2; ++s) {
       const int N = s ? ndn : nup, off = s ? nup : 0;
@@ -121,45 +134,6 @@ inline void mfma_free_tables(MfmaTables& t) {
   if (t.Lp) (void)hipFree(t.Lp);
   t.Lp = nullptr;
   t.enabled = false;
-}
-
-// ---------------------------------------------------------------------------
-// Theta (FP64, rows of Theta^T) -> packed operand of the contraction.
-// fp32:   [w][s][re/im][NP][KP] float
-// bf16x3: [w][s][re/im][hi/lo][NP][KP] bf16 bits
-// ---------------------------------------------------------------------------
-template <bool BF16>
-__global__ void __launch_bounds__(256) k_pack_theta(int nw, int M, int nup, int ndn, int NP, int KP,
-                                                    const cd* __restrict__ thetaT,
-                                                    const double* __restrict__ weight,
-                                                    void* __restrict__ out) {
-  const int ntot = nup + ndn;
-  const size_t per = (size_t)NP * KP;
-  const size_t total = (size_t)nw * 2 * per;
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  const int p = (int)(e % KP);
-  const int j = (int)((e / KP) % NP);
-  const int s = (int)((e / per) % 2);
-  const int w = (int)(e / (2 * per));
-  if (!(weight[w] > 0.0)) return;
-  const int N = s ? ndn : nup, off = s ? nup : 0;
-  cd v = mkc(0.0, 0.0);
-  if (j < N && p < M) v = thetaT[((size_t)w * ntot + off + j) * M + p];
-  const size_t base = ((size_t)w * 2 + s) * 2 * (BF16 ? 2 : 1) * per + (size_t)j * KP + p;
-  if (!BF16) {
-    float* o = reinterpret_cast<float*>(out);
-    o[base] = (float)v.re;
-    o[base + per] = (float)v.im;
-  } else {
-    uint16_t* o = reinterpret_cast<uint16_t*>(out);
-    const float xr = (float)v.re, xi = (float)v.im;
-    const uint16_t hr = f32_to_bf16_bits(xr), hi = f32_to_bf16_bits(xi);
-    o[base] = hr;
-    o[base + per] = f32_to_bf16_bits(xr - bf16_bits_to_f32(hr));
-    o[base + 2 * per] = hi;
-    o[base + 3 * per] = f32_to_bf16_bits(xi - bf16_bits_to_f32(hi));
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -415,21 +389,189 @@ inline size_t mfma_contract_lds_bytes(const MfmaTables& t) {
   return 2 * tile + (size_t)MFMA_WAVES * 2 * t.NP * (t.NP + 4) * 4;
 }
 
-inline hipError_t mfma_pack_theta(const MfmaTables& t, hipStream_t st, int nw, int M, int nup,
-                                  int ndn, const cd* thetaT, const double* weight, void* out) {
-  const size_t total = (size_t)nw * 2 * t.NP * t.KP;
-  const unsigned blocks = (unsigned)((total + 255) / 256);
-  if (t.precision == AFQMC_BF16X3)
-    hipLaunchKernelGGL(k_pack_theta<true>, dim3(blocks), dim3(256), 0, st, nw, M, nup, ndn, t.NP,
-                       t.KP, thetaT, weight, out);
-  else
-    hipLaunchKernelGGL(k_pack_theta<false>, dim3(blocks), dim3(256), 0, st, nw, M, nup, ndn, t.NP,
-                       t.KP, thetaT, weight, out);
-  return hipGetLastError();
+// ---------------------------------------------------------------------------
+// FP64 form of the contraction on v_mfma_f64_16x16x4_f64.
+// Operand lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k.  Output: lane l,
+// item v holds D[l/16 + 4v][l%16] (rows strided by 4 -- not the FP32 16x16 layout).
+// Two wavefronts share one walker-spin: one holds Re Theta, the other Im Theta
+// (M x N each, 128 VGPRs at M = 128) as the B operand for the whole kernel.  A
+// workgroup of 4 waves covers two walkers of one spin.  The Lh^g tile is single-
+// buffered in LDS with a register prefetch two g ahead, which keeps two
+// workgroups per CU.  Per g each wave writes its Omega plane (Re or Im) to LDS;
+// the Re wave then accumulates sum_ij (R_ij R_ji - I_ij I_ji) and the Im wave
+// 2 sum_ij I_ij R_ji, both in FP64.
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <int NP>
+__global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
+    int nw, int G, int nup, int ndn, int KP, const double* __restrict__ Lp,
+    const double* __restrict__ thp, const double* __restrict__ weight, cd* __restrict__ tpart,
+    cd* __restrict__ exch) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  constexpr int NB = NP / 16;
+  constexpr int KMAX = MFMA_KMAX;
+  constexpr int NCH = KMAX / 8;               // K chunks of 8 held per lane as 4 x f64x2
+  constexpr int LDE = NP + 1;
+  const int s = blockIdx.y;
+  const int N = s ? ndn : nup;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int pair = wave >> 1, part = wave & 1;  // part 0: Re Theta, 1: Im Theta
+  const int w = blockIdx.x * 2 + pair;
+  if (N == 0) {
+    if (w < nw && part == 0) {
+      for (int g = lane; g < G; g += 64) tpart[((size_t)w * 2 + s) * G + g] = mkc(0.0, 0.0);
+      if (lane == 0) exch[2 * w + s] = mkc(0.0, 0.0);
+    }
+    return;
+  }
+  const bool active = (w < nw) && (weight[w] > 0.0);
+  const int lda = KP + 2;
+  double* At = reinterpret_cast<double*>(smem);                       // [NP][KP + 2]
+  double* ep = At + (size_t)NP * lda + (size_t)pair * 2 * NP * LDE;   // this pair's planes
+  double* epR = ep;
+  double* epI = ep + NP * LDE;
+  const int nk = KP / 8;
+  const int j16 = lane & 15, q = lane >> 4;
+
+  // B operand: lane holds Theta_part[16 b + j16][8 c + 2 q + {0, 1}]
+  f64x2 breg[NB][NCH];
+  if (active) {
+    const double* tb = thp + (((size_t)w * 2 + s) * 2 + part) * NP * KP;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+        if (c < nk)
+          breg[b][c] = *reinterpret_cast<const f64x2*>(tb + (size_t)(16 * b + j16) * KP + 8 * c + 2 * q);
+  }
+
+  // tile staging: NP * KP doubles as 16-byte chunks
+  const int chunks_per_row = KP / 2;
+  const int nchunks = NP * chunks_per_row;
+  constexpr int MAXCH = (32 * KMAX / 2 + 255) / 256;  // 8
+  u32x4 pre[MAXCH];
+  const double* Lbase = Lp + (size_t)s * G * NP * KP;
+#define F64_GLOAD(G_)                                                                          \
+  do {                                                                                         \
+    const u32x4* src_ = reinterpret_cast<const u32x4*>(Lbase + (size_t)(G_) * NP * KP);        \
+    _Pragma("unroll") for (int c_ = 0; c_ < MAXCH; ++c_) {                                     \
+      const int ch_ = tid + c_ * 256;                                                          \
+      pre[c_] = src_[ch_ < nchunks ? ch_ : 0];                                                 \
+    }                                                                                          \
+  } while (0)
+#define F64_LSTORE()                                                                           \
+  do {                                                                                         \
+    _Pragma("unroll") for (int c_ = 0; c_ < MAXCH; ++c_) {                                     \
+      const int ch_ = tid + c_ * 256;                                                          \
+      if (ch_ < nchunks) {                                                                     \
+        const int row_ = ch_ / chunks_per_row, col_ = (ch_ % chunks_per_row) * 2;              \
+        *reinterpret_cast<u32x4*>(At + (size_t)row_ * lda + col_) = pre[c_];                   \
+      }                                                                                        \
+    }                                                                                          \
+  } while (0)
+
+  double xacc = 0.0;
+  if (G > 0) {
+    F64_GLOAD(0);
+    F64_LSTORE();
+  }
+  __syncthreads();
+  if (G > 1) F64_GLOAD(1);
+  for (int g = 0; g < G; ++g) {
+    f64x4 acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        if (c < nk) {
+          f64x2 af[NB];
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+            af[a] = *reinterpret_cast<const f64x2*>(At + (size_t)(16 * a + j16) * lda + 8 * c + 2 * q);
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+              for (int b = 0; b < NB; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][e], breg[b][c][e], acc[a][b], 0, 0, 0);
+        }
+      }
+      // this wave's plane, column-major: element (row r, col c) at [c * LDE + r]
+      double* pl = part ? epI : epR;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            pl[(16 * b + j16) * LDE + 16 * a + q + 4 * v] = acc[a][b][v];
+    }
+    __syncthreads();
+    if (g + 1 < G) F64_LSTORE();
+    if (active) {
+      double pr = 0.0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * a + q + 4 * v, j = 16 * b + j16;
+            const double mine = acc[a][b][v];
+            const double Rji = epR[i * LDE + j];
+            if (part == 0) {
+              const double Iij = epI[j * LDE + i], Iji = epI[i * LDE + j];
+              pr += mine * Rji - Iij * Iji;
+            } else {
+              pr += 2.0 * mine * Rji;
+            }
+          }
+      xacc += pr;
+      double d = 0.0;
+      if (lane < NP) d = part ? epI[lane * LDE + lane] : epR[lane * LDE + lane];
+      d = wave_sum(d);
+      if (lane == 0) reinterpret_cast<double*>(tpart + ((size_t)w * 2 + s) * G + g)[part] = d;
+    }
+    if (g + 2 < G) F64_GLOAD(g + 2);
+    __syncthreads();
+  }
+#undef F64_GLOAD
+#undef F64_LSTORE
+  if (active) {
+    xacc = wave_sum(xacc);
+    if (lane == 0) reinterpret_cast<double*>(exch + 2 * w + s)[part] = xacc;
+  }
+}
+
+inline size_t mfma_f64_contract_lds_bytes(const MfmaTables& t) {
+  return ((size_t)t.NP * (t.KP + 2) + (size_t)2 * 2 * t.NP * (t.NP + 1)) * 8;
 }
 
 inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int G,
                                 const void* thetaP, const double* weight, cd* tpart, cd* exch) {
+  if (t.precision == AFQMC_FP64) {
+    const size_t shm = mfma_f64_contract_lds_bytes(t);
+    dim3 grid((nw + 1) / 2, 2);
+    if (t.NP == 32) {
+      (void)hipFuncSetAttribute((const void*)k_contract_f64mfma<32>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL(k_contract_f64mfma<32>, grid, dim3(256), shm, st, nw, G, t.nup, t.ndn, t.KP,
+                         (const double*)t.Lp, (const double*)thetaP, weight, tpart, exch);
+    } else {
+      (void)hipFuncSetAttribute((const void*)k_contract_f64mfma<16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipLaunchKernelGGL(k_contract_f64mfma<16>, grid, dim3(256), shm, st, nw, G, t.nup, t.ndn, t.KP,
+                         (const double*)t.Lp, (const double*)thetaP, weight, tpart, exch);
+    }
+    return hipGetLastError();
+  }
   const size_t shm = mfma_contract_lds_bytes(t);
   dim3 grid((nw + MFMA_WAVES - 1) / MFMA_WAVES, 2);
   const bool bf = t.precision == AFQMC_BF16X3;

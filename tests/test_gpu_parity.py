@@ -166,3 +166,16 @@ def test_gpu_singular_and_nonfinite_walkers_are_killed(torch_cuda, precision):
     assert n == 4 and np.isfinite(a) and c == 4.0
     gs.step(wk, seed=1)
     assert gpu_state(wk)["W"][1] == 0.0
+
+
+@pytest.mark.parametrize("case", ["n34_m136", "n48_m200"])
+def test_gpu_fp64_beyond_mfma_tile_limits(torch_cuda, case):
+    """FP64 sizes outside the MFMA tiles (N > 32 or M > 128) run on the FP64 VALU kernels;
+    M=200, N=48 also exceeds the LDS of the staged inverse and uses the LU kernel."""
+    if case == "n34_m136":
+        s, nw, steps = gen_system(136, 34, 40, seed=21, n_dn=30), 3, 5
+    else:
+        s, nw, steps = gen_system(200, 48, 24, seed=22, n_dn=40), 2, 5
+    log(f"fp64 large shape {case}")
+    worst, *_ = run_lockstep(s, nw, steps, dtau=0.005, label=case)
+    log(f"{case} worst {worst}")
