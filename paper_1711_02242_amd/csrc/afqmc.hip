@@ -267,6 +267,25 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
   const int nmax = std::max(S->nup, S->ndn);
   dim3 grid(w->n_walkers, 2);
   void* ws = w->workspace;
+  void* packed0 = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
+  const int kind0 = !S->mt.enabled ? 0
+                    : S->mt.precision == AFQMC_FP64 ? 3
+                    : S->mt.precision == AFQMC_BF16X3 ? 2 : 1;
+  if (nmax <= 32) {
+    const size_t shm = (size_t)nmax * (2 * nmax + 1) * 16 + (size_t)nmax * 16 + 64;
+    if (nmax <= 16)
+      hipLaunchKernelGGL(k_overlap_mfma<16>, grid, dim3(256), shm, S->stream, S->M, S->nup, S->ndn,
+                         S->V, S->ht, (const cd*)w->U, w->weight, check_weight, at<cd>(ws, L.thetaT),
+                         at<cd>(ws, L.logdet), at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed0,
+                         kind0, S->mt.NP, S->mt.KP);
+    else
+      hipLaunchKernelGGL(k_overlap_mfma<32>, grid, dim3(256), shm, S->stream, S->M, S->nup, S->ndn,
+                         S->V, S->ht, (const cd*)w->U, w->weight, check_weight, at<cd>(ws, L.thetaT),
+                         at<cd>(ws, L.logdet), at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed0,
+                         kind0, S->mt.NP, S->mt.KP);
+    HIPCHK(hipGetLastError());
+    return AFQMC_OK;
+  }
   const size_t gj = gj_lds_bytes(S);
   if (gj <= 150 * 1024) {
     (void)hipFuncSetAttribute((const void*)k_overlap_gj, hipFuncAttributeMaxDynamicSharedMemorySize,

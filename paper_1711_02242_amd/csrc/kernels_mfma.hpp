@@ -592,3 +592,210 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
 #undef LAUNCH_CONTRACT
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Overlap, determinant and Theta with the two small products on FP64 MFMA
+// (Theorem 1.1-1.2, eq:precomputing), for N <= 32.  One block (4 waves) per
+// (walker, spin); only the Gauss-Jordan matrix [T | I] lives in LDS, which keeps
+// several blocks per CU.
+//   T = V^T U             (16x16 blocks, K = M, U read from global as complex)
+//   [T | I] -> [I | T^-1] (Gauss-Jordan, partial pivoting, log det from the pivots)
+//   Theta^T = (T^-1)^T U^T  (16x16 blocks, K = N, complex product as four real ones)
+// The outputs are those of k_overlap_gj: Theta^T (FP64), e1 = tr(ht Theta), logdet,
+// flags, and optionally the packed MFMA operand of the contraction.
+// ---------------------------------------------------------------------------
+template <int NPAD>
+__global__ void __launch_bounds__(256) k_overlap_mfma(
+    int M, int nup, int ndn, const double* __restrict__ V, const double* __restrict__ ht,
+    const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
+    cd* __restrict__ thetaT, cd* __restrict__ logdet, cd* __restrict__ e1,
+    unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  constexpr int NB = NPAD / 16;
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s == 0 ? nup : ndn;
+  const int off = s == 0 ? 0 : nup;
+  const int ntot = nup + ndn;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (N == 0) {
+    if (tid == 0) {
+      logdet[2 * w + s] = mkc(0.0, 0.0);
+      e1[2 * w + s] = mkc(0.0, 0.0);
+      wflag[2 * w + s] = 0u;
+    }
+    return;
+  }
+  if (check_weight && !(weight[w] > 0.0)) return;
+  const int lda = 2 * N + 1;
+  cd* Ag = reinterpret_cast<cd*>(smem_raw);          // [N][2N+1]
+  cd* fac = Ag + (size_t)N * lda;                     // [N]
+  double* red = reinterpret_cast<double*>(fac + N);  // [8]
+  __shared__ int s_piv, s_sing, s_nswap;
+  __shared__ double s_la, s_ar;
+  const int l16 = lane & 15, q = lane >> 4;
+  const cd* Uw = U + ((size_t)w * ntot + off) * M;
+  const double* Vs = V + (size_t)off * M;
+
+  // ---- T = V^T U on MFMA: wave t handles block (t / NB, t % NB)
+  for (int t = wave; t < NB * NB; t += 4) {
+    const int a = t / NB, b = t % NB;
+    f64x4 tr = {0.0, 0.0, 0.0, 0.0}, ti = {0.0, 0.0, 0.0, 0.0};
+    const int ri = 16 * a + l16, cj = 16 * b + l16;
+    const bool rok = ri < N, cok = cj < N;
+#pragma unroll 8
+    for (int k0 = 0; k0 < M; k0 += 4) {
+      const int k = k0 + q;
+      const double va = (rok && k < M) ? Vs[(size_t)ri * M + k] : 0.0;
+      const cd ub = (cok && k < M) ? Uw[(size_t)cj * M + k] : mkc(0.0, 0.0);
+      tr = __builtin_amdgcn_mfma_f64_16x16x4f64(va, ub.re, tr, 0, 0, 0);
+      ti = __builtin_amdgcn_mfma_f64_16x16x4f64(va, ub.im, ti, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * a + q + 4 * v, c = 16 * b + l16;
+      if (r < N && c < N) Ag[r * lda + c] = mkc(tr[v], ti[v]);
+    }
+  }
+  for (int e = tid; e < N * N; e += blockDim.x) {
+    const int i = e / N, j = e % N;
+    Ag[i * lda + N + j] = mkc(i == j ? 1.0 : 0.0, 0.0);
+  }
+  if (tid == 0) {
+    s_sing = 0;
+    s_nswap = 0;
+    s_la = 0.0;
+    s_ar = 0.0;
+  }
+  __syncthreads();
+  // ---- Gauss-Jordan with partial pivoting
+  for (int k = 0; k < N; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + lane; i < N; i += 64) {
+        const cd v = Ag[i * lda + k];
+        const double m = v.re * v.re + v.im * v.im;
+        if (m > best) {
+          best = m;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_piv = bi;
+        if (!(best > 0.0)) s_sing = 1;
+        if (bi != k) s_nswap += 1;
+      }
+    }
+    __syncthreads();
+    if (s_sing) break;
+    const int piv = s_piv;
+    if (piv != k) {
+      for (int j = tid; j < 2 * N; j += blockDim.x) {
+        const cd tmp = Ag[k * lda + j];
+        Ag[k * lda + j] = Ag[piv * lda + j];
+        Ag[piv * lda + j] = tmp;
+      }
+    }
+    __syncthreads();
+    const cd pk = Ag[k * lda + k];
+    if (tid < N) fac[tid] = Ag[tid * lda + k];
+    if (tid == 0) {
+      s_la += log(hypot(pk.re, pk.im));
+      s_ar += atan2(pk.im, pk.re);
+    }
+    __syncthreads();
+    for (int j = tid; j < 2 * N; j += blockDim.x) Ag[k * lda + j] = cdiv(Ag[k * lda + j], pk);
+    __syncthreads();
+    for (int e = tid; e < N * 2 * N; e += blockDim.x) {
+      const int i = e / (2 * N), j = e % (2 * N);
+      if (i != k) cfms(Ag[i * lda + j], fac[i], Ag[k * lda + j]);
+    }
+    __syncthreads();
+  }
+  if (s_sing) {
+    if (tid == 0) {
+      wflag[2 * w + s] = WFLAG_SINGULAR;
+      logdet[2 * w + s] = mkc(-INFINITY, 0.0);
+      e1[2 * w + s] = mkc(0.0, 0.0);
+    }
+    return;
+  }
+  if (tid == 0) {
+    logdet[2 * w + s] = mkc(s_la, s_ar + M_PI * (double)(s_nswap & 1));
+    wflag[2 * w + s] = 0u;
+  }
+  // ---- Theta^T[c][p] = sum_j Tinv[j][c] U^T[j][p] on MFMA (K = j, padded to NPAD)
+  const int CB = (M + 15) / 16;
+  const size_t per = (size_t)NP * KP;
+  cd* Tw = thetaT + ((size_t)w * ntot + off) * M;
+  const double* hts = ht + (size_t)off * M;
+  double e1re = 0.0, e1im = 0.0;
+  for (int t = wave; t < NB * CB; t += 4) {
+    const int a = t / CB, b = t % CB;
+    f64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    const int c_in = 16 * a + l16;   // A row (output row c)
+    const int p_in = 16 * b + l16;   // B column (output column p)
+#pragma unroll
+    for (int k0 = 0; k0 < NPAD; k0 += 4) {
+      const int j = k0 + q;
+      const cd tv = (j < N && c_in < N) ? Ag[j * lda + N + c_in] : mkc(0.0, 0.0);
+      const cd uv = (j < N && p_in < M) ? Uw[(size_t)j * M + p_in] : mkc(0.0, 0.0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uv.re, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-tv.im, uv.im, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uv.im, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.im, uv.re, ci, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = 16 * a + q + 4 * v, p = 16 * b + l16;
+      if (c >= N || p >= M) continue;
+      const cd th = mkc(cr[v], ci[v]);
+      Tw[(size_t)c * M + p] = th;
+      const double hv = hts[(size_t)c * M + p];
+      e1re = fma(hv, th.re, e1re);
+      e1im = fma(hv, th.im, e1im);
+      if (packed_kind == 3) {
+        double* o = reinterpret_cast<double*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
+        o[0] = th.re;
+        o[per] = th.im;
+      } else if (packed_kind == 1) {
+        float* o = reinterpret_cast<float*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
+        o[0] = (float)th.re;
+        o[per] = (float)th.im;
+      } else if (packed_kind == 2) {
+        uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)w * 2 + s) * 4 * per + (size_t)c * KP + p;
+        const float xr = (float)th.re, xi = (float)th.im;
+        const uint16_t hr = f32_to_bf16_bits(xr), hi = f32_to_bf16_bits(xi);
+        o[0] = hr;
+        o[per] = f32_to_bf16_bits(xr - bf16_bits_to_f32(hr));
+        o[2 * per] = hi;
+        o[3 * per] = f32_to_bf16_bits(xi - bf16_bits_to_f32(hi));
+      }
+    }
+  }
+  if (packed_kind) {
+    const int planes = packed_kind == 2 ? 4 : 2;
+    for (size_t e = tid; e < (size_t)planes * per; e += blockDim.x) {
+      const int pl = (int)(e / per);
+      const int c = (int)((e % per) / KP), p = (int)(e % KP);
+      if (c < N && p < M) continue;
+      const size_t o = ((size_t)w * 2 + s) * planes * per + (size_t)pl * per + (size_t)c * KP + p;
+      if (packed_kind == 3) reinterpret_cast<double*>(packed)[o] = 0.0;
+      else if (packed_kind == 1) reinterpret_cast<float*>(packed)[o] = 0.f;
+      else reinterpret_cast<uint16_t*>(packed)[o] = 0;
+    }
+  }
+  e1re = block_sum(e1re, red);
+  e1im = block_sum(e1im, red);
+  if (tid == 0) e1[2 * w + s] = mkc(e1re, e1im);
+}
