@@ -82,6 +82,18 @@ typedef enum {
 #define AFQMC_STATUS_FBCAP     0x10u   /* the force-bias cap was applied (App. B.1)    */
 #define AFQMC_STATUS_PHASE     0x20u   /* cos(dtheta) <= 0 killed a walker (eq:if_rle) */
 
+/* Weight update (afqmc_params.flags; at most one of the two bits):
+ *   0                        phaseless, local-energy importance function (eq:if_rle):
+ *                            W <- W exp(-dtau (Re E_L^cap(Psi) - E_T)) max(0, cos dtheta)
+ *   AFQMC_FLAG_HYBRID        phaseless with the hybrid importance function (eq:hybrid-wt):
+ *                            W <- W |I(x, xbar; Psi)| max(0, cos dtheta), capped at w_max
+ *   AFQMC_FLAG_FREE_PROJECTION  free projection (Sec. II.C, eq:weight_update) with the hybrid
+ *                            importance function: W e^{i theta} <- W e^{i theta} I(x, xbar; Psi),
+ *                            no projection and no caps on W or E_L; needs walkers.phase.
+ * I(x, xbar; Psi) = [<Psi_T|Psi'>/<Psi_T|Psi>] e^{-dtau (H0 - E_T)} e^{x.xbar - xbar.xbar/2}. */
+#define AFQMC_FLAG_HYBRID            0x1u
+#define AFQMC_FLAG_FREE_PROJECTION   0x2u
+
 typedef struct afqmc_sys_s* afqmc_sys;   /* opaque, library-owned */
 
 typedef struct {
@@ -97,7 +109,7 @@ typedef struct {
   double el_cap_C;      /* local-energy cap |Re E_L - E_T| <= sqrt(C/dtau), > 0 (eq:cap) */
   double w_max;         /* weight cap; NaN -> max(100, n_walkers/10) (App. B.1)       */
   double fb_cap;        /* cap on |xbar_g|, > 0 (App. B.1)                            */
-  uint32_t flags;       /* reserved, must be 0                                        */
+  uint32_t flags;       /* AFQMC_FLAG_* weight-update mode, 0 = phaseless local energy */
   uint32_t reserved;
 } afqmc_params;
 
@@ -109,6 +121,8 @@ typedef struct {
   double* arg_ovlp;      /* device, [n_walkers]   arg <Phi_T|Psi> in (-pi, pi]               */
   double* log_ovlp;      /* device, [n_walkers]   log |<Phi_T|Psi>| (diagnostic)            */
   double* e_loc;         /* device, [n_walkers][2] complex E_L of the current determinant    */
+  double* phase;         /* device, [n_walkers]   walker phase theta (free projection; may be
+                            NULL in the phaseless modes, where theta is identically 0)      */
   int64_t* walker_id;    /* device, [n_walkers]   ids that select the field stream           */
   void* workspace;       /* device, afqmc_workspace_bytes() bytes, 256-byte aligned          */
   size_t workspace_bytes;
@@ -170,15 +184,18 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
  * [n_walkers][n_chol] doubles.  Asynchronous. */
 AFQMC_API int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc_fields* f, double* x_out);
 
-/* Mixed-estimator sums over the walkers (eq:localenergy, theta = 0), reduced on the device
- * in a fixed order, copied to the host, synchronizing the stream:
- *   out[0] = sum_w W_w Re E_L^cap(Psi_w)   (eq:cap applied to Re E_L)
- *   out[1] = sum_w W_w Im E_L(Psi_w)
- *   out[2] = sum_w W_w
+/* Mixed-estimator sums over the walkers (eq:localenergy), reduced on the device in a fixed
+ * order, copied to the host, synchronizing the stream.  With c_w = W_w e^{i theta_w}
+ * (theta = 0 in the phaseless modes) and E_w = E_L(Psi_w), capped (eq:cap) in the phaseless
+ * modes and uncapped in free projection:
+ *   out[0] = Re sum_w c_w E_w      out[1] = Im sum_w c_w E_w
+ *   out[2] = Re sum_w c_w          out[5] = Im sum_w c_w
  *   out[3] = number of walkers with W > 0
  *   out[4] = status word (AFQMC_STATUS_* bits accumulated since setup or the last clear)
+ * The phaseless mixed estimate is out[0] / out[2]; the free-projection one is
+ * (out[0] + i out[1]) / (out[2] + i out[5]).
  * Returns AFQMC_E_NUMERIC if no walker is alive or a sum is not finite. */
-AFQMC_API int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[5]);
+AFQMC_API int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[6]);
 
 /* Read and clear the sticky status word (synchronizes the stream). */
 AFQMC_API int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear);

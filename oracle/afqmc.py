@@ -217,6 +217,14 @@ def phaseless_weight(W, e_loc_old, arg_old, arg_new, dtau, E_T, C, w_max):
     return np.minimum(Wn, w_max)
 
 
+def hybrid_log_importance(S, x, xbar, log_ovlp_old: complex, log_ovlp_new: complex) -> complex:
+    """log I(x, xbar; Psi) of eq:hybrid-wt:
+    log[<Psi_T|B(x - xbar)|Psi>/<Psi_T|Psi>] + x.xbar - xbar.xbar/2, where the overlap ratio is
+    that of the propagated and the old determinant and B carries exp(-dtau (H0 - E_T))."""
+    return (log_ovlp_new - log_ovlp_old - S.dtau * (S.h0 - S.E_T)
+            + complex(np.sum(x * xbar) - 0.5 * np.sum(xbar * xbar)))
+
+
 # --------------------------------------------------------------------------
 # Population control (Sec. III.D.4): comb / systematic resampling
 # --------------------------------------------------------------------------
@@ -245,6 +253,11 @@ def comb(W: np.ndarray, u: float):
 # Walker population and the step (Sec. III.E)
 # --------------------------------------------------------------------------
 
+WEIGHT_PHASELESS = "phaseless"      # eq:if_rle: local-energy importance function, cos projection
+WEIGHT_HYBRID = "hybrid"            # eq:hybrid-wt magnitude with the cos projection
+WEIGHT_FREE = "free"                # free projection (Sec. II.C) with the hybrid importance function
+
+
 @dataclass
 class Params:
     dtau: float
@@ -254,6 +267,7 @@ class Params:
     el_cap_C: float = 2.0
     w_max: float | None = None
     fb_cap: float = 1.0
+    weight_mode: str = WEIGHT_PHASELESS
 
     def wmax(self, n_walkers: int) -> float:
         return self.w_max if self.w_max is not None else max(100.0, n_walkers / 10.0)
@@ -269,6 +283,7 @@ class Walkers:
     t: np.ndarray         # (n_w, N_g) complex traces of the current walker
     walker_id: np.ndarray  # (n_w,) int64
     step: int = 0
+    theta: np.ndarray | None = None   # (n_w,) walker phase; stays 0 except in free projection
 
     @property
     def n(self):
@@ -301,7 +316,7 @@ def init_walkers(S: Setup, n_walkers: int, U_up=None, U_dn=None) -> Walkers:
     for w in range(n):
         arg[w], logabs[w], e[w], t[w] = measure(S, U_up[w], U_dn[w])
     return Walkers(U=[U_up, U_dn], W=np.ones(n), arg=arg, logabs=logabs, e_loc=e, t=t,
-                   walker_id=np.arange(n, dtype=np.int64), step=0)
+                   walker_id=np.arange(n, dtype=np.int64), step=0, theta=np.zeros(n))
 
 
 def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
@@ -324,12 +339,25 @@ def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None =
         A = propagator_exponent(S, x[w], xbar)
         U_up = propagate(S, A, wk.U[0][w], P.n_taylor)
         U_dn = propagate(S, A, wk.U[1][w], P.n_taylor)
+        # log|<Phi_T|Psi'>| before any re-orthonormalization: QR divides the overlap by det R.
+        log_r = 0.0
         if do_qr:
-            U_up = modified_gram_schmidt(U_up)[0]
-            U_dn = modified_gram_schmidt(U_dn)[0]
+            U_up, r_up = modified_gram_schmidt(U_up)
+            U_dn, r_dn = modified_gram_schmidt(U_dn)
+            log_r = float(np.sum(np.log(r_up)) + np.sum(np.log(r_dn)))
         arg_new, logabs_new, e_new, t_new = measure(S, U_up, U_dn)
-        wk.W[w] = phaseless_weight(wk.W[w], wk.e_loc[w], wk.arg[w], arg_new, P.dtau, S.E_T,
-                                   P.el_cap_C, wmax)
+        if P.weight_mode == WEIGHT_PHASELESS:
+            wk.W[w] = phaseless_weight(wk.W[w], wk.e_loc[w], wk.arg[w], arg_new, P.dtau, S.E_T,
+                                       P.el_cap_C, wmax)
+        else:
+            logI = hybrid_log_importance(S, x[w], xbar, complex(wk.logabs[w], wk.arg[w]),
+                                         complex(logabs_new + log_r, arg_new))
+            if P.weight_mode == WEIGHT_HYBRID:
+                proj = max(0.0, math.cos(arg_new - wk.arg[w]))
+                wk.W[w] = min(wmax, wk.W[w] * math.exp(logI.real) * proj)
+            else:   # free projection: complex weight W e^{i theta} times I (eq:weight_update)
+                wk.W[w] = wk.W[w] * math.exp(logI.real)
+                wk.theta[w] = float(wrap_angle(wk.theta[w] + logI.imag))
         wk.U[0][w] = U_up
         wk.U[1][w] = U_dn
         wk.arg[w] = arg_new
@@ -348,10 +376,17 @@ def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None =
         wk.logabs = wk.logabs[parent]
         wk.e_loc = wk.e_loc[parent]
         wk.t = wk.t[parent]
+        wk.theta = wk.theta[parent]
         wk.W = Wn
         wk.walker_id = np.arange(n, dtype=np.int64)
     wk.step = k + 1
     return wk
+
+
+def free_projection_energy(wk: Walkers) -> complex:
+    """sum_w W e^{i theta} E_L / sum_w W e^{i theta} (eq:freep, eq:localenergy), uncapped."""
+    c = wk.W * np.exp(1j * wk.theta)
+    return complex(np.sum(c * wk.e_loc) / np.sum(c))
 
 
 def mixed_energy(S: Setup, P: Params, wk: Walkers):

@@ -9,6 +9,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 
 AFQMC_FP64, AFQMC_FP32, AFQMC_BF16X3 = 0, 1, 2
+FLAG_HYBRID, FLAG_FREE_PROJECTION = 0x1, 0x2
+WEIGHT_MODES = {"phaseless": 0, "hybrid": FLAG_HYBRID, "free": FLAG_FREE_PROJECTION}
 PRECISIONS = {"fp64": AFQMC_FP64, "fp32": AFQMC_FP32, "bf16x3": AFQMC_BF16X3}
 
 STATUS_BITS = {0x1: "nonfinite", 0x2: "singular", 0x4: "ecap", 0x8: "wcap", 0x10: "fbcap",
@@ -33,7 +35,8 @@ class Params(C.Structure):
 class WalkersC(C.Structure):
     _fields_ = [("n_walkers", C.c_int32), ("reserved", C.c_int32), ("U", C.c_void_p),
                 ("weight", C.c_void_p), ("arg_ovlp", C.c_void_p), ("log_ovlp", C.c_void_p),
-                ("e_loc", C.c_void_p), ("walker_id", C.c_void_p), ("workspace", C.c_void_p),
+                ("e_loc", C.c_void_p), ("phase", C.c_void_p), ("walker_id", C.c_void_p),
+                ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("step", C.c_int64)]
 
 

@@ -35,7 +35,7 @@ class System:
     def __init__(self, h0, h1, L_chol, phi_up, phi_dn, *, dtau: float, precision: str = "fp64",
                  n_taylor: int = 6, qr_period: int = 5, pop_period: int = 5, el_cap_C: float = 2.0,
                  w_max: float | None = None, fb_cap: float = 1.0, e_trial: float | None = None,
-                 stream=None):
+                 weight_mode: str = "phaseless", stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise L.AfqmcError("no GPU visible: the AFQMC library runs on the GPU only")
@@ -53,8 +53,9 @@ class System:
                      e_trial=math.nan if e_trial is None else float(e_trial), n_taylor=n_taylor,
                      qr_period=qr_period, pop_period=pop_period,
                      precision=L.PRECISIONS[precision], el_cap_C=el_cap_C,
-                     w_max=math.nan if w_max is None else float(w_max), fb_cap=fb_cap, flags=0,
-                     reserved=0)
+                     w_max=math.nan if w_max is None else float(w_max), fb_cap=fb_cap,
+                     flags=L.WEIGHT_MODES[weight_mode], reserved=0)
+        self.weight_mode = weight_mode
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
@@ -127,12 +128,21 @@ class System:
         return out
 
     def energy(self, wk: "Walkers", check: bool = True):
-        """(sum W Re E_cap, sum W Im E, sum W, n_alive, status) -- synchronizes the stream."""
-        out = (C.c_double * 5)()
+        """(Re sum c E, Im sum c E, Re sum c, n_alive, status) with c = W e^{i theta}
+        -- synchronizes the stream.  ``energy_sums`` also returns Im sum c."""
+        o = self.energy_sums(wk, check)
+        return o[0], o[1], o[2], int(o[3]), int(o[4])
+
+    def energy_sums(self, wk: "Walkers", check: bool = True):
+        out = (C.c_double * 6)()
         rc = self.lib.afqmc_energy(self.handle, wk.c_ref(), out)
         if check:
             L.check(rc, "afqmc_energy")
-        return out[0], out[1], out[2], int(out[3]), int(out[4])
+        return tuple(out)
+
+    def free_projection_energy(self, wk: "Walkers") -> complex:
+        o = self.energy_sums(wk)
+        return complex(o[0], o[1]) / complex(o[2], o[5])
 
     def mixed_energy(self, wk: "Walkers") -> float:
         a, _, c, _, _ = self.energy(wk)
@@ -170,6 +180,7 @@ class Walkers:
         self.arg_ovlp = torch.zeros(n, dtype=torch.float64, device=dev)
         self.log_ovlp = torch.zeros(n, dtype=torch.float64, device=dev)
         self.e_loc = torch.zeros(n, dtype=torch.complex128, device=dev)
+        self.phase = torch.zeros(n, dtype=torch.float64, device=dev)
         self.walker_id = torch.arange(n, dtype=torch.int64, device=dev)
         nb = system.workspace_bytes(n)
         self._ws_raw = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
@@ -187,6 +198,7 @@ class Walkers:
         c.arg_ovlp = int(self.arg_ovlp.data_ptr())
         c.log_ovlp = int(self.log_ovlp.data_ptr())
         c.e_loc = int(self.e_loc.data_ptr())
+        c.phase = int(self.phase.data_ptr())
         c.walker_id = int(self.walker_id.data_ptr())
         c.workspace = int(self.workspace.data_ptr())
         c.workspace_bytes = int(self.workspace.numel())

@@ -27,7 +27,7 @@ struct TimedLaunch {
 
 struct WsLayout {
   size_t thetaT, tcur, tpart, exch, e1, logdet, wflag, enew, y, A, X0, X1, Y, parent, csum,
-      wnew, asnap, lsnap, esum, thetaP, y32, total;
+      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, logR, psnap, total;
 };
 
 }  // namespace
@@ -92,6 +92,9 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.esum = take(64);
   L.thetaP = take(mfma_theta_bytes(S->mt, nw));
   L.y32 = take(S->f32_prop ? nw * 2 * (size_t)S->Gp * 4 : 0);
+  L.fbterm = take(S->p.flags ? nw * (size_t)((S->G + 3) / 4) * 16 : 0);
+  L.logR = take(nw * 2 * 8);
+  L.psnap = take(nw * 8);
   L.total = o;
   return L;
 }
@@ -253,6 +256,7 @@ int check_walkers(const afqmc_sys_s* S, const afqmc_walkers* w) {
       !w->e_loc || !w->walker_id || !w->workspace)
     return AFQMC_E_ARG;
   if ((reinterpret_cast<uintptr_t>(w->workspace) & 255u) != 0) return AFQMC_E_ARG;
+  if ((S->p.flags & AFQMC_FLAG_FREE_PROJECTION) && !w->phase) return AFQMC_E_ARG;
   if (w->workspace_bytes < layout(S, (size_t)w->n_walkers).total) return AFQMC_E_NOMEM;
   return AFQMC_OK;
 }
@@ -386,7 +390,7 @@ int launch_fields(afqmc_sys_s* S, const afqmc_walkers* w, const afqmc_fields* f,
   hipLaunchKernelGGL(k_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S->stream,
                      w->n_walkers, S->G, S->s, S->p.fb_cap, at<cd>(ws, L.tcur), w->weight,
                      w->walker_id, f->seed, f->job_id, w->step, f->x, at<cd>(ws, L.y), xout,
-                     S->status);
+                     S->status, (S->p.flags && !xout) ? at<cd>(ws, L.fbterm) : nullptr);
   HIPCHK(hipGetLastError());
   return AFQMC_OK;
 }
@@ -417,7 +421,10 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
   if (M < 1 || nup < 0 || ndn < 0 || nup > M || ndn > M || nup + ndn < 1 || G < 0)
     return AFQMC_E_ARG;
   if (!(p->dtau > 0.0) || p->n_taylor < 1 || p->n_taylor > 20 || p->qr_period < 0 ||
-      p->pop_period < 0 || !(p->el_cap_C > 0.0) || !(p->fb_cap > 0.0) || p->flags != 0)
+      p->pop_period < 0 || !(p->el_cap_C > 0.0) || !(p->fb_cap > 0.0))
+    return AFQMC_E_ARG;
+  if ((p->flags & ~(AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION)) != 0 ||
+      p->flags == (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION))
     return AFQMC_E_ARG;
   if ((G > 0 && !L_chol) || (nup > 0 && !phi_up) || (ndn > 0 && !phi_dn)) return AFQMC_E_ARG;
   if (p->precision < AFQMC_FP64 || p->precision > AFQMC_BF16X3) return AFQMC_E_UNSUPPORTED;
@@ -623,7 +630,7 @@ int afqmc_walkers_init(afqmc_sys s, afqmc_walkers* w) {
   int rc = check_walkers(s, w);
   if (rc) return rc;
   hipLaunchKernelGGL(k_init_walkers, dim3(w->n_walkers), dim3(256), 0, s->stream, w->n_walkers,
-                     s->ntot * s->M, s->V, (cd*)w->U, w->weight, w->walker_id);
+                     s->ntot * s->M, s->V, (cd*)w->U, w->weight, w->walker_id, w->phase);
   HIPCHK(hipGetLastError());
   w->step = 0;
   return do_measure(s, w);
@@ -708,10 +715,11 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
     HIPCHK(hipGetLastError());
   }
   // 4. periodic re-orthonormalization
-  if (s->p.qr_period > 0 && (k + 1) % s->p.qr_period == 0) {
+  const bool qr_due = s->p.qr_period > 0 && (k + 1) % s->p.qr_period == 0;
+  if (qr_due) {
     Timer tm(s, KG_QR);
     hipLaunchKernelGGL(k_mgs, dim3(nw, 2), dim3(256), 0, s->stream, M, s->nup, s->ndn, (cd*)w->U,
-                       w->weight, s->status);
+                       w->weight, s->status, at<double>(ws, L.logR));
     HIPCHK(hipGetLastError());
   }
   // 5-6. overlap, Theta, local energy of the new determinants
@@ -721,17 +729,22 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
   {
     Timer tm(s, KG_WEIGHT);
     const double wmax = std::isnan(s->p.w_max) ? std::max(100.0, nw / 10.0) : s->p.w_max;
-    hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, s->stream, nw, s->p.dtau,
-                       s->e_trial, sqrt(s->p.el_cap_C / s->p.dtau), wmax, at<cd>(ws, L.logdet),
-                       at<unsigned>(ws, L.wflag), at<cd>(ws, L.enew), w->weight, w->arg_ovlp,
-                       w->log_ovlp, (cd*)w->e_loc, s->status);
+    const int mode = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 2
+                     : (s->p.flags & AFQMC_FLAG_HYBRID) ? 1 : 0;
+    hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, s->stream, nw, mode,
+                       s->p.dtau, s->h0, s->e_trial, sqrt(s->p.el_cap_C / s->p.dtau), wmax,
+                       at<cd>(ws, L.logdet), at<unsigned>(ws, L.wflag), at<cd>(ws, L.enew),
+                       mode ? at<cd>(ws, L.fbterm) : nullptr, (s->G + 3) / 4,
+                       qr_due ? at<double>(ws, L.logR) : nullptr, w->weight, w->arg_ovlp,
+                       w->log_ovlp, (cd*)w->e_loc, w->phase, s->status);
     HIPCHK(hipGetLastError());
   }
   // 8. population control
   if (s->p.pop_period > 0 && (k + 1) % s->p.pop_period == 0) {
     Timer tm(s, KG_COMB);
     const double u = f->u_comb;
-    hipLaunchKernelGGL(k_comb_select, dim3(1), dim3(64), 0, s->stream, nw, w->weight, u, f->seed,
+    const size_t cshm = nw <= 8192 ? (size_t)nw * 8 : 0;
+    hipLaunchKernelGGL(k_comb_select, dim3(1), dim3(1024), cshm, s->stream, nw, w->weight, u, f->seed,
                        f->job_id, k, at<double>(ws, L.csum), at<int>(ws, L.parent),
                        at<double>(ws, L.wnew), s->status);
     const size_t rowb = (size_t)nt * M * 16;
@@ -745,35 +758,42 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
                           hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(at<void>(ws, L.lsnap), w->log_ovlp, (size_t)nw * 8,
                           hipMemcpyDeviceToDevice, s->stream));
+    if (w->phase)
+      HIPCHK(hipMemcpyAsync(at<void>(ws, L.psnap), w->phase, (size_t)nw * 8,
+                            hipMemcpyDeviceToDevice, s->stream));
     hipLaunchKernelGGL(k_comb_gather, dim3(nw), dim3(256), 0, s->stream, nw, nt * M, s->G,
                        at<int>(ws, L.parent), at<double>(ws, L.wnew), at<cd>(ws, L.X0),
                        at<cd>(ws, L.y), at<cd>(ws, L.enew), at<double>(ws, L.asnap),
-                       at<double>(ws, L.lsnap), (cd*)w->U, at<cd>(ws, L.tcur), (cd*)w->e_loc,
-                       w->arg_ovlp, w->log_ovlp, w->weight, w->walker_id);
+                       at<double>(ws, L.lsnap), at<double>(ws, L.psnap), (cd*)w->U,
+                       at<cd>(ws, L.tcur), (cd*)w->e_loc, w->arg_ovlp, w->log_ovlp, w->phase,
+                       w->weight, w->walker_id);
     HIPCHK(hipGetLastError());
   }
   w->step = k + 1;
   return AFQMC_OK;
 }
 
-int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[5]) {
+int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[6]) {
   if (!s || !out) return AFQMC_E_ARG;
   int rc = check_walkers(s, w);
   if (rc) return rc;
   const WsLayout L = layout(s, (size_t)w->n_walkers);
   double* d = at<double>(w->workspace, L.esum);
   const double half = sqrt(s->p.el_cap_C / s->p.dtau);
-  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, s->e_trial, half,
-                     w->weight, (const cd*)w->e_loc, d);
+  const int fp = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 1 : 0;
+  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, fp, s->e_trial,
+                     half, w->weight, w->phase, (const cd*)w->e_loc, d);
   HIPCHK(hipGetLastError());
-  double h[4];
+  double h[6];
   unsigned st = 0;
   HIPCHK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipMemcpyAsync(&st, s->status, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   for (int i = 0; i < 4; ++i) out[i] = h[i];
   out[4] = (double)st;
-  if (!(h[3] > 0.0) || !std::isfinite(h[0]) || !std::isfinite(h[1]) || !(h[2] > 0.0))
+  out[5] = h[5];
+  if (!(h[3] > 0.0) || !std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2]) ||
+      !std::isfinite(h[5]) || (!fp && !(h[2] > 0.0)))
     return AFQMC_E_NUMERIC;
   return AFQMC_OK;
 }

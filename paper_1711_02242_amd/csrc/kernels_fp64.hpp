@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(256) k_fields(
     int nw, int G, double s, double fb_cap, const cd* __restrict__ tcur,
     const double* __restrict__ weight, const int64_t* __restrict__ walker_id, uint64_t seed,
     uint64_t job, int64_t step, const double* __restrict__ xin, cd* __restrict__ y,
-    double* __restrict__ xout, unsigned* __restrict__ status) {
+    double* __restrict__ xout, unsigned* __restrict__ status, cd* __restrict__ fbterm) {
   const int nblk = (G + 3) / 4;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)nw * nblk) return;
@@ -298,6 +298,7 @@ __global__ void __launch_bounds__(256) k_fields(
   }
   const bool alive = weight[w] > 0.0;
   bool capped = false;
+  double fr = 0.0, fi = 0.0;  // sum over the block of x xbar - xbar^2 / 2 (eq:hybrid-wt)
   for (int j = 0; j < 4; ++j) {
     const int g = 4 * b + j;
     if (g >= G) break;
@@ -313,9 +314,12 @@ __global__ void __launch_bounds__(256) k_fields(
         capped = true;
       }
       yv = mkc(x[j] - br, -bi);
+      fr += x[j] * br - 0.5 * (br * br - bi * bi);
+      fi += x[j] * bi - br * bi;
     }
     y[(size_t)w * G + g] = yv;
   }
+  if (fbterm) fbterm[(size_t)w * nblk + b] = mkc(fr, fi);
   if (capped) atomicOr(status, 0x10u);
 }
 
@@ -442,16 +446,22 @@ __global__ void __launch_bounds__(256) k_zmatmul_fp64(int M, int ntot, const voi
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __restrict__ U,
                                              const double* __restrict__ weight,
-                                             unsigned* __restrict__ status) {
+                                             unsigned* __restrict__ status,
+                                             double* __restrict__ logR /*[nw][2]*/) {
   __shared__ cd dots[64];
   __shared__ double s_norm;
   const int w = blockIdx.x, s = blockIdx.y;
   const int N = s == 0 ? nup : ndn;
   const int off = s == 0 ? 0 : nup;
   const int ntot = nup + ndn;
-  if (N == 0 || !(weight[w] > 0.0)) return;
+  if (N == 0) {
+    if (threadIdx.x == 0) logR[2 * w + s] = 0.0;
+    return;
+  }
+  if (!(weight[w] > 0.0)) return;
   cd* Uw = U + ((size_t)w * ntot + off) * M;
   const int tid = threadIdx.x, lane = tid % AFQMC_WAVE, wid = tid / AFQMC_WAVE;
+  double lr = 0.0;  // sum_k log r_kk: QR divides <Phi_T|Psi> by det R (Theorem 1.5)
   const int nwave = blockDim.x / AFQMC_WAVE;
   for (int k = 0; k < N; ++k) {
     cd* qk = Uw + (size_t)k * M;
@@ -464,6 +474,7 @@ __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __rest
     __syncthreads();
     const double nrm = s_norm;
     if (!(nrm > 0.0) && tid == 0) atomicOr(status, 0x2u);
+    lr += log(nrm);
     const double inv = 1.0 / nrm;
     for (int p = tid; p < M; p += blockDim.x) qk[p] = cscale(qk[p], inv);
     __syncthreads();
@@ -490,16 +501,25 @@ __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __rest
       __syncthreads();
     }
   }
+  if (tid == 0) logR[2 * w + s] = lr;
 }
 
 // ---------------------------------------------------------------------------
-// Phaseless weight update (eq:if_rle, eq:cap): one thread per walker.
+// Weight update, one thread per walker.
+//   mode 0 phaseless local energy (eq:if_rle, eq:cap):
+//          W <- min(w_max, W exp(-dtau (Re E_L^cap(old) - E_T)) max(0, cos dtheta))
+//   mode 1 phaseless hybrid (eq:hybrid-wt): W <- min(w_max, W |I| max(0, cos dtheta))
+//   mode 2 free projection (Sec. II.C): W e^{i theta} <- W e^{i theta} I
+// with log I = log(<Phi_T|Psi'>/<Phi_T|Psi>) - dtau (h0 - E_T) + sum_g (x xbar - xbar^2/2),
+// where <Phi_T|Psi'> is taken before this step's QR (log det R added back).
 // ---------------------------------------------------------------------------
-__global__ void k_weights(int nw, double dtau, double e_trial, double ecap_half, double w_max,
-                          const cd* __restrict__ logdet, const unsigned* __restrict__ wflag,
-                          const cd* __restrict__ enew, double* __restrict__ weight,
-                          double* __restrict__ arg_ovlp, double* __restrict__ log_ovlp,
-                          cd* __restrict__ e_loc, unsigned* __restrict__ status) {
+__global__ void k_weights(int nw, int mode, double dtau, double h0, double e_trial,
+                          double ecap_half, double w_max, const cd* __restrict__ logdet,
+                          const unsigned* __restrict__ wflag, const cd* __restrict__ enew,
+                          const cd* __restrict__ fbterm, int nblk, const double* __restrict__ logR,
+                          double* __restrict__ weight, double* __restrict__ arg_ovlp,
+                          double* __restrict__ log_ovlp, cd* __restrict__ e_loc,
+                          double* __restrict__ phase, unsigned* __restrict__ status) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
   const double W = weight[w];
@@ -519,7 +539,7 @@ __global__ void k_weights(int nw, double dtau, double e_trial, double ecap_half,
   } else if (!cfinite(en) || !isfinite(a) || !isfinite(la)) {
     Wn = 0.0;
     st |= 0x1u;
-  } else {
+  } else if (mode == 0) {
     const cd eo = e_loc[w];
     double ec = eo.re;
     if (ec < e_trial - ecap_half) {
@@ -535,6 +555,35 @@ __global__ void k_weights(int nw, double dtau, double e_trial, double ecap_half,
     if (Wn > w_max) {
       Wn = w_max;
       st |= 0x8u;
+    }
+  } else {
+    double fr = 0.0, fi = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      const cd f = fbterm[(size_t)w * nblk + b];
+      fr += f.re;
+      fi += f.im;
+    }
+    const double lr = logR ? logR[2 * w] + logR[2 * w + 1] : 0.0;
+    const double lre = (la + lr - log_ovlp[w]) - dtau * (h0 - e_trial) + fr;
+    const double lim = (a - arg_ovlp[w]) + fi;
+    if (mode == 1) {
+      const double proj = fmax(0.0, cos(a - arg_ovlp[w]));
+      if (!(proj > 0.0)) st |= 0x20u;
+      Wn = W * exp(lre) * proj;
+      if (Wn > w_max) {
+        Wn = w_max;
+        st |= 0x8u;
+      }
+    } else {
+      Wn = W * exp(lre);
+      double th = phase[w] + lim;
+      th = th - 2.0 * M_PI * floor((th + M_PI) / (2.0 * M_PI));
+      if (th <= -M_PI) th += 2.0 * M_PI;
+      phase[w] = th;
+      if (!isfinite(Wn)) {
+        Wn = 0.0;
+        st |= 0x1u;
+      }
     }
   }
   weight[w] = Wn;
@@ -571,38 +620,65 @@ __global__ void k_measure_finish(int nw, const cd* __restrict__ logdet,
 // order, positions (u + j) * (sum W / n), parent = walker whose half-open interval
 // holds the position.  One thread does the scan so the arithmetic order is fixed.
 // ---------------------------------------------------------------------------
-__global__ void k_comb_select(int nw, const double* __restrict__ weight, double u_given,
-                              uint64_t seed, uint64_t job, int64_t step, double* __restrict__ csum,
-                              int* __restrict__ parent, double* __restrict__ wnew,
-                              unsigned* __restrict__ status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double u = u_given;
-  if (isnan(u)) {
-    const u64x4 r = philox4x64_10(0ull, 0ull, (uint64_t)step, 1ull, seed, job);
-    u = u64_unit(r.v[0]);
+__global__ void __launch_bounds__(1024) k_comb_select(int nw, const double* __restrict__ weight,
+                                                      double u_given, uint64_t seed, uint64_t job,
+                                                      int64_t step, double* __restrict__ csum,
+                                                      int* __restrict__ parent,
+                                                      double* __restrict__ wnew,
+                                                      unsigned* __restrict__ status) {
+  // Cumulative weights are summed by one thread in walker order (the arithmetic order of a
+  // sequential cumulative sum); the weights are staged in LDS first when they fit.  The
+  // parent of each position is then found by an independent binary search.
+  extern __shared__ double cs[];
+  __shared__ double s_total, s_u;
+  __shared__ int s_last;
+  const bool in_lds = nw <= 8192;
+  double* C = in_lds ? cs : csum;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) C[i] = weight[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = u_given;
+    if (isnan(u)) {
+      const u64x4 r = philox4x64_10(0ull, 0ull, (uint64_t)step, 1ull, seed, job);
+      u = u64_unit(r.v[0]);
+    }
+    double acc = 0.0;
+    int last_alive = -1;
+    for (int i = 0; i < nw; ++i) {
+      const double wi = C[i];
+      acc += wi;
+      C[i] = acc;
+      if (wi > 0.0) last_alive = i;
+    }
+    s_total = acc;
+    s_u = u;
+    s_last = last_alive;
   }
-  double acc = 0.0;
-  int last_alive = -1;
-  for (int i = 0; i < nw; ++i) {
-    acc += weight[i];
-    csum[i] = acc;
-    if (weight[i] > 0.0) last_alive = i;
-  }
-  const double total = acc;
+  __syncthreads();
+  const double total = s_total;
+  const int last_alive = s_last;
   if (!(total > 0.0) || last_alive < 0) {
-    for (int j = 0; j < nw; ++j) parent[j] = j;
-    *wnew = -1.0;
-    atomicOr(status, 0x1u);
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) parent[j] = j;
+    if (threadIdx.x == 0) {
+      *wnew = -1.0;
+      atomicOr(status, 0x1u);
+    }
     return;
   }
   const double step_w = total / (double)nw;
-  int i = 0;
-  for (int j = 0; j < nw; ++j) {
+  const double u = s_u;
+  for (int j = threadIdx.x; j < nw; j += blockDim.x) {
     const double pos = (u + (double)j) * step_w;
-    while (i < nw && csum[i] <= pos) ++i;
-    parent[j] = i < last_alive ? i : last_alive;
+    // first i with C[i] > pos (half-open intervals [C_{i-1}, C_i))
+    int lo = 0, hi = nw;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (C[mid] <= pos) lo = mid + 1;
+      else hi = mid;
+    }
+    parent[j] = lo < last_alive ? lo : last_alive;
   }
-  *wnew = step_w;
+  if (threadIdx.x == 0) *wnew = step_w;
 }
 
 // Gather walker state from a snapshot by parent index.  One block per walker.
@@ -610,9 +686,10 @@ __global__ void __launch_bounds__(256) k_comb_gather(
     int nw, int rowlen /*ntot*M*/, int G, const int* __restrict__ parent,
     const double* __restrict__ wnew, const cd* __restrict__ Usnap, const cd* __restrict__ tsnap,
     const cd* __restrict__ esnap, const double* __restrict__ asnap,
-    const double* __restrict__ lsnap, cd* __restrict__ U, cd* __restrict__ tcur,
-    cd* __restrict__ e_loc, double* __restrict__ arg_ovlp, double* __restrict__ log_ovlp,
-    double* __restrict__ weight, int64_t* __restrict__ walker_id) {
+    const double* __restrict__ lsnap, const double* __restrict__ psnap, cd* __restrict__ U,
+    cd* __restrict__ tcur, cd* __restrict__ e_loc, double* __restrict__ arg_ovlp,
+    double* __restrict__ log_ovlp, double* __restrict__ phase, double* __restrict__ weight,
+    int64_t* __restrict__ walker_id) {
   const int j = blockIdx.x;
   const double wv = *wnew;
   if (!(wv > 0.0)) return;
@@ -625,6 +702,7 @@ __global__ void __launch_bounds__(256) k_comb_gather(
     e_loc[j] = esnap[pj];
     arg_ovlp[j] = asnap[pj];
     log_ovlp[j] = lsnap[pj];
+    if (phase) phase[j] = psnap[pj];
     weight[j] = wv;
     walker_id[j] = j;
   }
@@ -633,20 +711,32 @@ __global__ void __launch_bounds__(256) k_comb_gather(
 // ---------------------------------------------------------------------------
 // Mixed-estimator sums (eq:localenergy, theta = 0) in a fixed reduction order.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_energy_sum(int nw, double e_trial, double ecap_half,
+__global__ void __launch_bounds__(256) k_energy_sum(int nw, int free_proj, double e_trial,
+                                                    double ecap_half,
                                                     const double* __restrict__ weight,
+                                                    const double* __restrict__ phase,
                                                     const cd* __restrict__ e_loc,
                                                     double* __restrict__ out) {
+  // c = W e^{i theta}: sums of c E (Re, Im), of c (Re, Im) and the live count.  The local
+  // energy is capped (eq:cap) in the phaseless modes and taken as is in free projection.
   __shared__ double red[8];
-  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0, f = 0.0;
   for (int w = threadIdx.x; w < nw; w += blockDim.x) {
     const double W = weight[w];
     if (W > 0.0) {
       const cd e = e_loc[w];
-      const double ec = fmin(fmax(e.re, e_trial - ecap_half), e_trial + ecap_half);
-      a += W * ec;
-      b += W * e.im;
-      c += W;
+      double cr = W, ci = 0.0;
+      double er = e.re;
+      if (free_proj) {
+        cr = W * cos(phase[w]);
+        ci = W * sin(phase[w]);
+      } else {
+        er = fmin(fmax(e.re, e_trial - ecap_half), e_trial + ecap_half);
+      }
+      a += cr * er - ci * e.im;
+      b += cr * e.im + ci * er;
+      c += cr;
+      f += ci;
       d += 1.0;
     }
   }
@@ -654,24 +744,27 @@ __global__ void __launch_bounds__(256) k_energy_sum(int nw, double e_trial, doub
   b = block_sum(b, red);
   c = block_sum(c, red);
   d = block_sum(d, red);
+  f = block_sum(f, red);
   if (threadIdx.x == 0) {
     out[0] = a;
     out[1] = b;
     out[2] = c;
     out[3] = d;
+    out[5] = f;
   }
 }
 
 // Walkers start as the trial: U[w] = V (as complex), W = 1, id = w.
 __global__ void k_init_walkers(int nw, int rowlen, const double* __restrict__ V,
                                cd* __restrict__ U, double* __restrict__ weight,
-                               int64_t* __restrict__ walker_id) {
+                               int64_t* __restrict__ walker_id, double* __restrict__ phase) {
   const int w = blockIdx.x;
   for (int e = threadIdx.x; e < rowlen; e += blockDim.x)
     U[(size_t)w * rowlen + e] = mkc(V[e], 0.0);
   if (threadIdx.x == 0) {
     weight[w] = 1.0;
     walker_id[w] = w;
+    if (phase) phase[w] = 0.0;
   }
 }
 

@@ -28,12 +28,14 @@ def oracle_U_to_gpu(Uu: np.ndarray, Ud: np.ndarray) -> np.ndarray:
 
 
 def make_pair(s, nw: int, *, dtau: float, precision: str = "fp64", qr_period: int = 5,
-              pop_period: int = 5, n_taylor: int = 6, U=None):
+              pop_period: int = 5, n_taylor: int = 6, U=None, weight_mode: str = "phaseless"):
     import paper_1711_02242_amd as afq
     S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, dtau)
-    P = A.Params(dtau=dtau, n_taylor=n_taylor, qr_period=qr_period, pop_period=pop_period)
+    P = A.Params(dtau=dtau, n_taylor=n_taylor, qr_period=qr_period, pop_period=pop_period,
+                 weight_mode=weight_mode)
     gs = afq.System.from_synthetic(s, dtau=dtau, precision=precision, qr_period=qr_period,
-                                   pop_period=pop_period, n_taylor=n_taylor)
+                                   pop_period=pop_period, n_taylor=n_taylor,
+                                   weight_mode=weight_mode)
     wk = gs.walkers(nw)
     gs.init(wk)
     if U is None:
@@ -52,7 +54,7 @@ def gpu_state(wk):
     torch.cuda.synchronize()
     return dict(U=wk.U.cpu().numpy(), W=wk.weight.cpu().numpy(), arg=wk.arg_ovlp.cpu().numpy(),
                 logabs=wk.log_ovlp.cpu().numpy(), e=wk.e_loc.cpu().numpy(),
-                ids=wk.walker_id.cpu().numpy())
+                ids=wk.walker_id.cpu().numpy(), theta=wk.phase.cpu().numpy())
 
 
 def angle_diff(a, b):
@@ -74,6 +76,8 @@ def compare_state(S, wo, st, n_up: int, rtol: float, what: str = ""):
     out["e"] = (np.abs(st["e"][alive] - wo.e_loc[alive]).max(initial=0.0)
                 / max(1.0, np.abs(wo.e_loc[alive]).max(initial=1.0)))
     out["arg"] = angle_diff(st["arg"][alive], wo.arg[alive]).max(initial=0.0)
+    if wo.theta is not None:
+        out["theta"] = angle_diff(st["theta"][alive], wo.theta[alive]).max(initial=0.0)
     out["alive_match"] = bool(np.array_equal(st["W"] > 0, alive))
     bad = {k: v for k, v in out.items() if k != "alive_match" and not v <= rtol}
     if bad or not out["alive_match"]:
@@ -84,10 +88,10 @@ def compare_state(S, wo, st, n_up: int, rtol: float, what: str = ""):
 def run_lockstep(s, nw: int, steps: int, *, dtau: float, precision: str = "fp64",
                  explicit_fields: bool = True, seed: int = 0, rtol: float = 1e-10,
                  qr_period: int = 5, pop_period: int = 5, check_every: int = 1, U=None,
-                 label: str = ""):
+                 label: str = "", weight_mode: str = "phaseless"):
     import torch
     S, P, wo, gs, wk = make_pair(s, nw, dtau=dtau, precision=precision, qr_period=qr_period,
-                                 pop_period=pop_period, U=U)
+                                 pop_period=pop_period, U=U, weight_mode=weight_mode)
     compare_state(S, wo, gpu_state(wk), s.n_up, rtol, f"{label} init")
     worst = {}
     for k in range(steps):
@@ -103,8 +107,13 @@ def run_lockstep(s, nw: int, steps: int, *, dtau: float, precision: str = "fp64"
             for key, v in d.items():
                 if key != "alive_match":
                     worst[key] = max(worst.get(key, 0.0), v)
-    e_gpu = gs.energy(wk)
-    e_or = A.mixed_energy(S, P, wo)
-    assert abs(e_gpu[0] / e_gpu[2] - e_or[0]) <= rtol * abs(e_or[0]) * 10
-    assert e_gpu[3] == e_or[4]
+    if weight_mode == "free":
+        e_fp = gs.free_projection_energy(wk)
+        e_ofp = A.free_projection_energy(wo)
+        assert abs(e_fp - e_ofp) <= rtol * abs(e_ofp) * 10
+    else:
+        e_gpu = gs.energy(wk)
+        e_or = A.mixed_energy(S, P, wo)
+        assert abs(e_gpu[0] / e_gpu[2] - e_or[0]) <= rtol * abs(e_or[0]) * 10
+        assert e_gpu[3] == e_or[4]
     return worst, gs, wk, S, wo

@@ -1,0 +1,79 @@
+"""Hybrid (eq:hybrid-wt) and free-projection (Sec. II.C) weight updates on the GPU against the
+oracle, and the GPU free-projection estimate against exact diagonalization."""
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import afqmc as A
+from oracle import fock as F
+from synthetic import config_system, gen_system
+from tests.parity_helpers import log, run_lockstep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mode", ["hybrid", "free"])
+@pytest.mark.parametrize("case", ["tiny", "medium", "ragged"])
+def test_weight_modes_lockstep_fp64(mode, case):
+    if case == "tiny":
+        s, nw, steps, dt = config_system("tiny"), 16, 40, 0.01
+    elif case == "medium":
+        s, nw, steps, dt = config_system("medium"), 8, 10, 0.005
+    else:
+        s, nw, steps, dt = gen_system(13, 3, 19, seed=5, n_dn=2), 7, 12, 0.01
+    log(f"weight mode {mode} {case}")
+    worst, *_ = run_lockstep(s, nw, steps, dtau=dt, label=f"{mode}-{case}", weight_mode=mode)
+    log(f"  worst {worst}")
+
+
+@pytest.mark.parametrize("mode", ["hybrid", "free"])
+def test_weight_modes_lockstep_fp32(mode):
+    s = config_system("tiny")
+    log(f"weight mode {mode} fp32")
+    worst, *_ = run_lockstep(s, 16, 30, dtau=0.01, precision="fp32", rtol=1e-4,
+                             label=f"{mode}-fp32", weight_mode=mode)
+    log(f"  worst {worst}")
+
+
+def test_gpu_free_projection_matches_exact_finite_beta():
+    """With one Cholesky vector the HS integral is exact: free projection on the GPU (device
+    Philox fields) reproduces the finite-beta mixed estimate of the Trotter-split propagator."""
+    import paper_1711_02242_amd as afq
+    s = gen_system(8, 2, 1, seed=41)
+    L = s.L * 3.0
+    dt, nsteps, nw = 0.02, 25, 20000
+    S = A.setup(0.0, s.h1, L, s.phi_up, s.phi_dn, dt)
+    fs = F.FockSpace(8, 2, 2)
+    H = fs.hamiltonian(0.0, s.h1, F.eri_from_cholesky(L))
+    half = scipy.linalg.expm(-0.5 * dt * fs.one_body(S.v0))
+    Lhat = fs.one_body(L[0])
+    P = half @ scipy.linalg.expm(-0.5 * dt * Lhat @ Lhat) @ half
+    phiT = fs.slater(s.phi_up.astype(complex), s.phi_dn.astype(complex))
+    psi = phiT.copy()
+    ref = []
+    for k in range(nsteps):
+        psi = P @ psi
+        ref.append((np.vdot(phiT, H @ psi) / np.vdot(phiT, psi)).real)
+    gs = afq.System(0.0, s.h1, L, s.phi_up, s.phi_dn, dtau=dt, qr_period=5, pop_period=0,
+                    weight_mode="free")
+    wk = gs.walkers(nw)
+    gs.init(wk)
+    for k in range(nsteps):
+        gs.step(wk, seed=11)
+        if k in (9, 24):
+            W = wk.weight.cpu().numpy()
+            th = wk.phase.cpu().numpy()
+            e = wk.e_loc.cpu().numpy()
+            c = W * np.exp(1j * th)
+            num = c * e
+            g = 40
+            idx = np.arange(nw) % g
+            full = (num.sum() / c.sum()).real
+            assert abs(full - gs.free_projection_energy(wk).real) < 1e-9 * abs(full)
+            jk = np.array([((num.sum() - num[idx == i].sum()) / (c.sum() - c[idx == i].sum())).real
+                           for i in range(g)])
+            err = np.sqrt((g - 1) / g * np.sum((jk - jk.mean()) ** 2))
+            log(f"  beta={dt * (k + 1):.2f}: {full:.5f} +- {err:.5f}, exact {ref[k]:.5f}")
+            assert err < 0.01
+            assert abs(full - ref[k]) < 4 * err
