@@ -93,6 +93,17 @@ typedef enum {
  * I(x, xbar; Psi) = [<Psi_T|Psi'>/<Psi_T|Psi>] e^{-dtau (H0 - E_T)} e^{x.xbar - xbar.xbar/2}. */
 #define AFQMC_FLAG_HYBRID            0x1u
 #define AFQMC_FLAG_FREE_PROJECTION   0x2u
+/* Mean-field background subtraction (Sec. II.B.3): v_g -> v_g - <v_g>_T.  The one-body
+ * operator becomes v0 + sum_g lbar_g L^g (lbar_g = <L_g>_T), the force bias
+ * -i sqrt(dtau) (t_g - lbar_g), and every step multiplies the walker's overlap by the
+ * c-number exp(-i sqrt(dtau) sum_g (x_g - xbar_g) lbar_g), which enters the phase and the
+ * hybrid weight.  Combines with any weight mode. */
+#define AFQMC_FLAG_MEAN_FIELD        0x4u
+/* Closed-shell walkers: requires n_up == n_dn and phi_up == phi_dn.  Identical fields act
+ * identically on both spins, so U_up == U_dn for every walker at every step; the library
+ * then stores and propagates only the up block -- walkers.U is [n_walkers][n_up][M] -- and
+ * counts each spin-summed quantity (log overlap, traces, exchange, one-body energy) twice. */
+#define AFQMC_FLAG_CLOSED_SHELL      0x8u
 
 typedef struct afqmc_sys_s* afqmc_sys;   /* opaque, library-owned */
 
@@ -109,14 +120,15 @@ typedef struct {
   double el_cap_C;      /* local-energy cap |Re E_L - E_T| <= sqrt(C/dtau), > 0 (eq:cap) */
   double w_max;         /* weight cap; NaN -> max(100, n_walkers/10) (App. B.1)       */
   double fb_cap;        /* cap on |xbar_g|, > 0 (App. B.1)                            */
-  uint32_t flags;       /* AFQMC_FLAG_* weight-update mode, 0 = phaseless local energy */
+  uint32_t flags;       /* AFQMC_FLAG_* bits; weight mode 0 = phaseless local energy  */
   uint32_t reserved;
 } afqmc_params;
 
 typedef struct {
   int32_t n_walkers;     /* >= 1 */
   int32_t reserved;
-  void* U;               /* device, [n_walkers][n_up+n_dn][M] complex128 (see Conventions) */
+  void* U;               /* device, [n_walkers][n_up+n_dn][M] complex128 (see Conventions);
+                            [n_walkers][n_up][M] with AFQMC_FLAG_CLOSED_SHELL               */
   double* weight;        /* device, [n_walkers]   W >= 0; W == 0 marks a dead walker         */
   double* arg_ovlp;      /* device, [n_walkers]   arg <Phi_T|Psi> in (-pi, pi]               */
   double* log_ovlp;      /* device, [n_walkers]   log |<Phi_T|Psi>| (diagnostic)            */

@@ -48,6 +48,8 @@ class Setup:
     Lh: list              # per spin, (N_g, N_sigma, M) half-rotated Cholesky V^T L_g
     ht: list              # per spin, (N_sigma, M) half-rotated one-body V^T h1
     E_T: float            # trial energy E_L(Phi_T, Phi_T)
+    lbar: np.ndarray | None = None   # (N_g,) mean-field shifts <L_g>_T (zeros: no subtraction)
+    h0_prop: float = 0.0  # constant of the propagated Hamiltonian (H0, or H0 - 1/2 sum lbar^2)
 
     @property
     def M(self):
@@ -69,21 +71,31 @@ def sym_expm(A: np.ndarray, c: float) -> np.ndarray:
     return (Q * np.exp(c * w)) @ Q.T
 
 
-def setup(h0, h1, L, phi_up, phi_dn, dtau, e_trial=None) -> Setup:
+def setup(h0, h1, L, phi_up, phi_dn, dtau, e_trial=None, mean_field: bool = False) -> Setup:
+    """Precompute everything that does not depend on the walkers.
+
+    With ``mean_field`` the mean-field background is subtracted (Sec. II.B.3): with
+    v_g = i L_g and vbar_g = <Psi_T|v_g|Psi_T> = i lbar_g, lbar_g = <L_g>_T real,
+    H = H0' + v0' - 1/2 sum_g (v_g - vbar_g)^2 where
+    H0' = H0 + 1/2 sum vbar^2 = H0 - 1/2 sum lbar^2 and v0' = v0 - sum vbar_g v_g = v0 + sum lbar_g L_g.
+    """
     h1 = np.asarray(h1, dtype=np.float64)
     L = np.asarray(L, dtype=np.float64)
     V = [np.asarray(phi_up, dtype=np.float64), np.asarray(phi_dn, dtype=np.float64)]
     v0 = one_body_v0(h1, L)
-    Eh = sym_expm(v0, -0.5 * dtau)
     # Half rotation: (Lh_g)_rq = sum_p (V^dagger)_rp L^g_pq, V real (eq:precomputing2).
     Lh = [np.einsum("pr,gpq->grq", Vs, L) for Vs in V]
     ht = [Vs.T @ h1 for Vs in V]
-    S = Setup(h0=float(h0), h1=h1, L=L, V=V, dtau=float(dtau), v0=v0, Eh=Eh, Lh=Lh, ht=ht,
-              E_T=0.0)
-    if e_trial is None:
-        th = [overlap_theta(V[s], V[s].astype(np.complex128))[1] for s in range(2)]
-        e_trial = local_energy(S, th)[0].real
-    S.E_T = float(e_trial)
+    S = Setup(h0=float(h0), h1=h1, L=L, V=V, dtau=float(dtau), v0=v0, Eh=None, Lh=Lh, ht=ht,
+              E_T=0.0, lbar=np.zeros(L.shape[0]), h0_prop=float(h0))
+    th = [overlap_theta(V[s], V[s].astype(np.complex128))[1] for s in range(2)]
+    e_hf, t_trial = local_energy(S, th)
+    if mean_field:
+        S.lbar = t_trial.real.copy()
+        S.v0 = v0 + np.einsum("g,gpq->pq", S.lbar, L)
+        S.h0_prop = float(h0) - 0.5 * float(np.sum(S.lbar ** 2))
+    S.Eh = sym_expm(S.v0, -0.5 * dtau)
+    S.E_T = float(e_hf.real if e_trial is None else e_trial)
     return S
 
 
@@ -217,11 +229,19 @@ def phaseless_weight(W, e_loc_old, arg_old, arg_new, dtau, E_T, C, w_max):
     return np.minimum(Wn, w_max)
 
 
+def mean_field_log_factor(S, x, xbar) -> complex:
+    """log of the c-number exp(sqrt(dtau) sum_g (x - xbar)_g (-vbar_g)) = exp(-i s sum (x - xbar) lbar)
+    that the mean-field-subtracted propagator puts on every walker (zero without subtraction)."""
+    return complex(-1j * math.sqrt(S.dtau) * np.sum((x - xbar) * S.lbar))
+
+
 def hybrid_log_importance(S, x, xbar, log_ovlp_old: complex, log_ovlp_new: complex) -> complex:
     """log I(x, xbar; Psi) of eq:hybrid-wt:
     log[<Psi_T|B(x - xbar)|Psi>/<Psi_T|Psi>] + x.xbar - xbar.xbar/2, where the overlap ratio is
-    that of the propagated and the old determinant and B carries exp(-dtau (H0 - E_T))."""
-    return (log_ovlp_new - log_ovlp_old - S.dtau * (S.h0 - S.E_T)
+    that of the propagated and the old determinant (times the mean-field c-number) and B
+    carries exp(-dtau (H0' - E_T))."""
+    return (log_ovlp_new - log_ovlp_old + mean_field_log_factor(S, x, xbar)
+            - S.dtau * (S.h0_prop - S.E_T)
             + complex(np.sum(x * xbar) - 0.5 * np.sum(xbar * xbar)))
 
 
@@ -335,7 +355,7 @@ def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None =
     for w in range(n):
         if not wk.W[w] > 0.0:
             continue
-        xbar = force_bias(wk.t[w], P.dtau, P.fb_cap)
+        xbar = force_bias(wk.t[w] - S.lbar, P.dtau, P.fb_cap)
         A = propagator_exponent(S, x[w], xbar)
         U_up = propagate(S, A, wk.U[0][w], P.n_taylor)
         U_dn = propagate(S, A, wk.U[1][w], P.n_taylor)
@@ -347,13 +367,15 @@ def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None =
             log_r = float(np.sum(np.log(r_up)) + np.sum(np.log(r_dn)))
         arg_new, logabs_new, e_new, t_new = measure(S, U_up, U_dn)
         if P.weight_mode == WEIGHT_PHASELESS:
-            wk.W[w] = phaseless_weight(wk.W[w], wk.e_loc[w], wk.arg[w], arg_new, P.dtau, S.E_T,
-                                       P.el_cap_C, wmax)
+            dphase = mean_field_log_factor(S, x[w], xbar).imag
+            wk.W[w] = phaseless_weight(wk.W[w], wk.e_loc[w], wk.arg[w], arg_new + dphase, P.dtau,
+                                       S.E_T, P.el_cap_C, wmax)
         else:
             logI = hybrid_log_importance(S, x[w], xbar, complex(wk.logabs[w], wk.arg[w]),
                                          complex(logabs_new + log_r, arg_new))
             if P.weight_mode == WEIGHT_HYBRID:
-                proj = max(0.0, math.cos(arg_new - wk.arg[w]))
+                proj = max(0.0, math.cos(arg_new - wk.arg[w]
+                                         + mean_field_log_factor(S, x[w], xbar).imag))
                 wk.W[w] = min(wmax, wk.W[w] * math.exp(logI.real) * proj)
             else:   # free projection: complex weight W e^{i theta} times I (eq:weight_update)
                 wk.W[w] = wk.W[w] * math.exp(logI.real)

@@ -9,7 +9,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 
 AFQMC_FP64, AFQMC_FP32, AFQMC_BF16X3 = 0, 1, 2
-FLAG_HYBRID, FLAG_FREE_PROJECTION = 0x1, 0x2
+FLAG_HYBRID, FLAG_FREE_PROJECTION, FLAG_MEAN_FIELD, FLAG_CLOSED_SHELL = 0x1, 0x2, 0x4, 0x8
 WEIGHT_MODES = {"phaseless": 0, "hybrid": FLAG_HYBRID, "free": FLAG_FREE_PROJECTION}
 PRECISIONS = {"fp64": AFQMC_FP64, "fp32": AFQMC_FP32, "bf16x3": AFQMC_BF16X3}
 

@@ -35,7 +35,8 @@ class System:
     def __init__(self, h0, h1, L_chol, phi_up, phi_dn, *, dtau: float, precision: str = "fp64",
                  n_taylor: int = 6, qr_period: int = 5, pop_period: int = 5, el_cap_C: float = 2.0,
                  w_max: float | None = None, fb_cap: float = 1.0, e_trial: float | None = None,
-                 weight_mode: str = "phaseless", stream=None):
+                 weight_mode: str = "phaseless", mean_field: bool = False,
+                 closed_shell: bool = False, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise L.AfqmcError("no GPU visible: the AFQMC library runs on the GPU only")
@@ -46,7 +47,8 @@ class System:
         phi_up = np.ascontiguousarray(phi_up, dtype=np.float64).reshape(M, -1)
         phi_dn = np.ascontiguousarray(phi_dn, dtype=np.float64).reshape(M, -1)
         self.M, self.n_up, self.n_dn, self.n_chol = M, phi_up.shape[1], phi_dn.shape[1], L_chol.shape[0]
-        self.ntot = self.n_up + self.n_dn
+        self.closed_shell = bool(closed_shell)
+        self.ntot = self.n_up if self.closed_shell else self.n_up + self.n_dn
         self.dtau = float(dtau)
         self.precision = precision
         p = L.Params(M=M, n_up=self.n_up, n_dn=self.n_dn, n_chol=self.n_chol, dtau=self.dtau,
@@ -54,7 +56,9 @@ class System:
                      qr_period=qr_period, pop_period=pop_period,
                      precision=L.PRECISIONS[precision], el_cap_C=el_cap_C,
                      w_max=math.nan if w_max is None else float(w_max), fb_cap=fb_cap,
-                     flags=L.WEIGHT_MODES[weight_mode], reserved=0)
+                     flags=L.WEIGHT_MODES[weight_mode]
+                     | (L.FLAG_MEAN_FIELD if mean_field else 0)
+                     | (L.FLAG_CLOSED_SHELL if closed_shell else 0), reserved=0)
         self.weight_mode = weight_mode
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()

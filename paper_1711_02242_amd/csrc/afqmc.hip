@@ -27,7 +27,7 @@ struct TimedLaunch {
 
 struct WsLayout {
   size_t thetaT, tcur, tpart, exch, e1, logdet, wflag, enew, y, A, X0, X1, Y, parent, csum,
-      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, logR, psnap, total;
+      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, mfterm, logR, psnap, total;
 };
 
 }  // namespace
@@ -50,6 +50,9 @@ struct afqmc_sys_s {
   float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
   int Gp = 0;              // G rounded up to 32
   bool f32_prop = false;   // A-build and propagation on FP32 MFMA (mixed-precision modes)
+  int sf = 1;              // spin factor: 2 in closed-shell mode (only the up block is stored)
+  double h0p = 0.0;        // constant of the propagated Hamiltonian (H0 - 1/2 sum lbar^2)
+  double* lbar = nullptr;  // [G] mean-field shifts <L_g>_T (zeros without subtraction)
   size_t device_bytes = 0;
   // timing
   bool timing = false;
@@ -92,7 +95,9 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.esum = take(64);
   L.thetaP = take(mfma_theta_bytes(S->mt, nw));
   L.y32 = take(S->f32_prop ? nw * 2 * (size_t)S->Gp * 4 : 0);
-  L.fbterm = take(S->p.flags ? nw * (size_t)((S->G + 3) / 4) * 16 : 0);
+  const size_t nblk = (size_t)((S->G + 3) / 4);
+  L.fbterm = take((S->p.flags & (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION)) ? nw * nblk * 16 : 0);
+  L.mfterm = take((S->p.flags & AFQMC_FLAG_MEAN_FIELD) ? nw * nblk * 16 : 0);
   L.logR = take(nw * 2 * 8);
   L.psnap = take(nw * 8);
   L.total = o;
@@ -246,6 +251,7 @@ void free_sys(afqmc_sys_s* S) {
   hipFree(S->ht);
   hipFree(S->status);
   hipFree(S->Lt32);
+  hipFree(S->lbar);
   hipFree(S->Eh32);
   mfma_free_tables(S->mt);
   delete S;
@@ -358,6 +364,7 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
   {
     Timer tm(S, KG_ASSEMBLE);
     hipLaunchKernelGGL(k_energy_assemble, dim3(w->n_walkers), dim3(256), 0, S->stream, S->G, S->h0,
+                       (double)S->sf,
                        at<cd>(ws, L.tpart), at<cd>(ws, L.exch), at<cd>(ws, L.e1), w->weight, 1,
                        at<cd>(ws, L.tcur), at<cd>(ws, L.enew));
     HIPCHK(hipGetLastError());
@@ -373,7 +380,7 @@ int do_measure(afqmc_sys_s* S, afqmc_walkers* w) {
   rc = launch_contract(S, w, L);
   if (rc) return rc;
   hipLaunchKernelGGL(k_measure_finish, dim3((w->n_walkers + 255) / 256), dim3(256), 0, S->stream,
-                     w->n_walkers, at<cd>(ws, L.logdet), at<unsigned>(ws, L.wflag),
+                     w->n_walkers, (double)S->sf, at<cd>(ws, L.logdet), at<unsigned>(ws, L.wflag),
                      at<cd>(ws, L.enew), w->weight, w->arg_ovlp, w->log_ovlp, (cd*)w->e_loc,
                      S->status);
   HIPCHK(hipGetLastError());
@@ -390,7 +397,11 @@ int launch_fields(afqmc_sys_s* S, const afqmc_walkers* w, const afqmc_fields* f,
   hipLaunchKernelGGL(k_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S->stream,
                      w->n_walkers, S->G, S->s, S->p.fb_cap, at<cd>(ws, L.tcur), w->weight,
                      w->walker_id, f->seed, f->job_id, w->step, f->x, at<cd>(ws, L.y), xout,
-                     S->status, (S->p.flags && !xout) ? at<cd>(ws, L.fbterm) : nullptr);
+                     S->status,
+                     ((S->p.flags & (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION)) && !xout)
+                         ? at<cd>(ws, L.fbterm) : nullptr,
+                     S->lbar,
+                     ((S->p.flags & AFQMC_FLAG_MEAN_FIELD) && !xout) ? at<cd>(ws, L.mfterm) : nullptr);
   HIPCHK(hipGetLastError());
   return AFQMC_OK;
 }
@@ -423,9 +434,16 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
   if (!(p->dtau > 0.0) || p->n_taylor < 1 || p->n_taylor > 20 || p->qr_period < 0 ||
       p->pop_period < 0 || !(p->el_cap_C > 0.0) || !(p->fb_cap > 0.0))
     return AFQMC_E_ARG;
-  if ((p->flags & ~(AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION)) != 0 ||
-      p->flags == (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION))
+  const uint32_t known = AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION | AFQMC_FLAG_MEAN_FIELD |
+                         AFQMC_FLAG_CLOSED_SHELL;
+  if ((p->flags & ~known) != 0 ||
+      (p->flags & (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION)) ==
+          (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION))
     return AFQMC_E_ARG;
+  if (p->flags & AFQMC_FLAG_CLOSED_SHELL) {
+    if (nup != ndn || nup == 0) return AFQMC_E_ARG;
+    if (memcmp(phi_up, phi_dn, sizeof(double) * (size_t)M * nup) != 0) return AFQMC_E_ARG;
+  }
   if ((G > 0 && !L_chol) || (nup > 0 && !phi_up) || (ndn > 0 && !phi_dn)) return AFQMC_E_ARG;
   if (p->precision < AFQMC_FP64 || p->precision > AFQMC_BF16X3) return AFQMC_E_UNSUPPORTED;
   if (std::max(nup, ndn) > 64) return AFQMC_E_UNSUPPORTED;
@@ -482,8 +500,6 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
       const double v = 0.5 * (v0[(size_t)i * M + j] + v0[(size_t)j * M + i]);
       v0[(size_t)i * M + j] = v0[(size_t)j * M + i] = v;
     }
-  std::vector<double> Eh;
-  host_expm_sym(v0, M, -0.5 * p->dtau, Eh);
 
   // Trial orbitals as rows: V[c][p] = (V_s)_{p, c'}
   std::vector<double> Vr((size_t)nt * M);
@@ -512,7 +528,9 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
       for (int j = 0; j < M; ++j) ht[(size_t)c * M + j] += a * h1[(size_t)q * M + j];
     }
 
-  // E_HF = E_L(Phi_T, Phi_T): Theta_s = V_s (V_s^T V_s)^{-1} (real), then eq:localenergy3.
+  // E_HF = E_L(Phi_T, Phi_T): Theta_s = V_s (V_s^T V_s)^{-1} (real), then eq:localenergy3;
+  // tvec[g] = <L_g>_T are the trial's traces.
+  std::vector<double> tvec;
   {
     std::vector<double> th((size_t)nt * M, 0.0);  // rows of Theta^T
     for (int s = 0; s < 2; ++s) {
@@ -541,6 +559,7 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
     for (int c = 0; c < nt; ++c)
       for (int q = 0; q < M; ++q) e1 += ht[(size_t)c * M + q] * th[(size_t)c * M + q];
     std::vector<double> om;
+    tvec.assign((size_t)G, 0.0);
     for (int g = 0; g < G; ++g) {
       double t = 0.0;
       for (int s = 0; s < 2; ++s) {
@@ -560,15 +579,55 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
         }
       }
       jsum += t * t;
+      tvec[g] = t;
     }
     S->e_hf = h0 + e1 + 0.5 * (jsum - xsum);
   }
   S->e_trial = std::isnan(p->e_trial) ? S->e_hf : p->e_trial;
 
+  // Mean-field subtraction (Sec. II.B.3): v0' = v0 + sum_g lbar_g L^g, H0' = H0 - 1/2 sum lbar^2.
+  std::vector<double> lb((size_t)(G > 0 ? G : 1), 0.0);
+  S->h0p = h0;
+  if (p->flags & AFQMC_FLAG_MEAN_FIELD) {
+    for (int g = 0; g < G; ++g) {
+      lb[g] = tvec[g];
+      S->h0p -= 0.5 * tvec[g] * tvec[g];
+      const double* Lg = L_chol + (size_t)g * M * M;
+      for (size_t e = 0; e < (size_t)M * M; ++e) v0[e] += tvec[g] * Lg[e];
+    }
+    for (int i = 0; i < M; ++i)
+      for (int j = i + 1; j < M; ++j) {
+        const double v = 0.5 * (v0[(size_t)i * M + j] + v0[(size_t)j * M + i]);
+        v0[(size_t)i * M + j] = v0[(size_t)j * M + i] = v;
+      }
+  }
+  std::vector<double> Eh;
+  host_expm_sym(v0, M, -0.5 * p->dtau, Eh);
+
+  // Closed shell: keep only the up block; spin-summed quantities are counted twice.
+  int nup_i = nup, ndn_i = ndn;
+  if (p->flags & AFQMC_FLAG_CLOSED_SHELL) {
+    std::vector<double> Lh1((size_t)G * nup * M), ht1((size_t)nup * M), V1((size_t)nup * M);
+    for (int g = 0; g < G; ++g)
+      memcpy(Lh1.data() + (size_t)g * nup * M, Lh.data() + (size_t)g * nt * M,
+             sizeof(double) * (size_t)nup * M);
+    memcpy(ht1.data(), ht.data(), sizeof(double) * (size_t)nup * M);
+    memcpy(V1.data(), Vr.data(), sizeof(double) * (size_t)nup * M);
+    Lh.swap(Lh1);
+    ht.swap(ht1);
+    Vr.swap(V1);
+    ndn_i = 0;
+    S->ndn = 0;
+    S->ntot = nup;
+    S->sf = 2;
+  }
+  const int nt_i = S->ntot;
+
   int rc;
   if ((rc = dev_upload(S, &S->L, G ? L_chol : nullptr, (size_t)G * M * M)) ||
       (rc = dev_upload(S, &S->Eh, Eh.data(), (size_t)M * M)) ||
-      (rc = dev_upload(S, &S->V, Vr.data(), (size_t)nt * M)) ||
+      (rc = dev_upload(S, &S->V, Vr.data(), (size_t)nt_i * M)) ||
+      (rc = dev_upload(S, &S->lbar, lb.data(), lb.size())) ||
       (rc = dev_upload(S, &S->Lh, Lh.data(), Lh.size())) ||
       (rc = dev_upload(S, &S->ht, ht.data(), ht.size())) ||
       (rc = dev_upload<unsigned>(S, &S->status, nullptr, 1))) {
@@ -580,13 +639,13 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
     return AFQMC_E_HIP;
   }
   {
-    const bool fits = std::max(nup, ndn) <= 32 && M <= MFMA_KMAX && gj_lds_bytes(S) <= 150 * 1024;
+    const bool fits = std::max(nup_i, ndn_i) <= 32 && M <= MFMA_KMAX && gj_lds_bytes(S) <= 150 * 1024;
     if (!fits && p->precision != AFQMC_FP64) {
       free_sys(S);
       return AFQMC_E_UNSUPPORTED;
     }
     if (fits) {
-      rc = mfma_build_tables(S->mt, p->precision, M, nup, ndn, G, Lh.data());
+      rc = mfma_build_tables(S->mt, p->precision, M, nup_i, ndn_i, G, Lh.data());
       if (rc != AFQMC_OK) {
         free_sys(S);
         return rc;
@@ -732,9 +791,12 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
     const int mode = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 2
                      : (s->p.flags & AFQMC_FLAG_HYBRID) ? 1 : 0;
     hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, s->stream, nw, mode,
-                       s->p.dtau, s->h0, s->e_trial, sqrt(s->p.el_cap_C / s->p.dtau), wmax,
-                       at<cd>(ws, L.logdet), at<unsigned>(ws, L.wflag), at<cd>(ws, L.enew),
-                       mode ? at<cd>(ws, L.fbterm) : nullptr, (s->G + 3) / 4,
+                       (double)s->sf, s->p.dtau, s->h0p, s->e_trial,
+                       sqrt(s->p.el_cap_C / s->p.dtau), wmax, at<cd>(ws, L.logdet),
+                       at<unsigned>(ws, L.wflag), at<cd>(ws, L.enew),
+                       mode ? at<cd>(ws, L.fbterm) : nullptr,
+                       (s->p.flags & AFQMC_FLAG_MEAN_FIELD) ? at<cd>(ws, L.mfterm) : nullptr,
+                       (s->G + 3) / 4,
                        qr_due ? at<double>(ws, L.logR) : nullptr, w->weight, w->arg_ovlp,
                        w->log_ovlp, (cd*)w->e_loc, w->phase, s->status);
     HIPCHK(hipGetLastError());

@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(256) k_contract_fp64(
 // (eq:localenergy2-3 with the 1/2 of eq:bo_ham2).  One block per walker.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_energy_assemble(
-    int G, double h0, const cd* __restrict__ tpart, const cd* __restrict__ exch,
+    int G, double h0, double sf, const cd* __restrict__ tpart, const cd* __restrict__ exch,
     const cd* __restrict__ e1, const double* __restrict__ weight, int check_weight,
     cd* __restrict__ tcur /*[nw][G]*/, cd* __restrict__ enew /*[nw]*/) {
   __shared__ double red[8];
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) k_energy_assemble(
   if (check_weight && !(weight[w] > 0.0)) return;
   double jr = 0.0, ji = 0.0;
   for (int g = tid; g < G; g += blockDim.x) {
-    const cd t = cadd(tpart[((size_t)w * 2) * G + g], tpart[((size_t)w * 2 + 1) * G + g]);
+    const cd t = cadd(cscale(tpart[((size_t)w * 2) * G + g], sf), tpart[((size_t)w * 2 + 1) * G + g]);
     tcur[(size_t)w * G + g] = t;
     jr += t.re * t.re - t.im * t.im;
     ji += 2.0 * t.re * t.im;
@@ -256,8 +256,8 @@ __global__ void __launch_bounds__(256) k_energy_assemble(
   jr = block_sum(jr, red);
   ji = block_sum(ji, red);
   if (tid == 0) {
-    const cd x = cadd(exch[2 * w], exch[2 * w + 1]);
-    const cd e = cadd(e1[2 * w], e1[2 * w + 1]);
+    const cd x = cadd(cscale(exch[2 * w], sf), exch[2 * w + 1]);
+    const cd e = cadd(cscale(e1[2 * w], sf), e1[2 * w + 1]);
     enew[w] = mkc(h0 + e.re + 0.5 * (jr - x.re), e.im + 0.5 * (ji - x.im));
   }
 }
@@ -271,7 +271,8 @@ __global__ void __launch_bounds__(256) k_fields(
     int nw, int G, double s, double fb_cap, const cd* __restrict__ tcur,
     const double* __restrict__ weight, const int64_t* __restrict__ walker_id, uint64_t seed,
     uint64_t job, int64_t step, const double* __restrict__ xin, cd* __restrict__ y,
-    double* __restrict__ xout, unsigned* __restrict__ status, cd* __restrict__ fbterm) {
+    double* __restrict__ xout, unsigned* __restrict__ status, cd* __restrict__ fbterm,
+    const double* __restrict__ lbar, cd* __restrict__ mfterm) {
   const int nblk = (G + 3) / 4;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)nw * nblk) return;
@@ -299,14 +300,16 @@ __global__ void __launch_bounds__(256) k_fields(
   const bool alive = weight[w] > 0.0;
   bool capped = false;
   double fr = 0.0, fi = 0.0;  // sum over the block of x xbar - xbar^2 / 2 (eq:hybrid-wt)
+  double mr = 0.0, mi = 0.0;  // sum over the block of y_g lbar_g (mean-field c-number)
   for (int j = 0; j < 4; ++j) {
     const int g = 4 * b + j;
     if (g >= G) break;
     cd yv = mkc(0.0, 0.0);
     if (alive) {
       const cd t = tcur[(size_t)w * G + g];
-      // xbar = -i s t = (s t.im, -s t.re)
-      double br = s * t.im, bi = -s * t.re;
+      const double lb = lbar[g];
+      // xbar = -i s (t - lbar) = (s t.im, -s (t.re - lbar))
+      double br = s * t.im, bi = -s * (t.re - lb);
       const double mod = hypot(br, bi);
       if (mod > fb_cap) {
         br *= fb_cap / mod;
@@ -316,10 +319,14 @@ __global__ void __launch_bounds__(256) k_fields(
       yv = mkc(x[j] - br, -bi);
       fr += x[j] * br - 0.5 * (br * br - bi * bi);
       fi += x[j] * bi - br * bi;
+      mr += yv.re * lb;
+      mi += yv.im * lb;
     }
     y[(size_t)w * G + g] = yv;
   }
   if (fbterm) fbterm[(size_t)w * nblk + b] = mkc(fr, fi);
+  // log of exp(-i s sum y lbar) = (s Im(sum y lbar), -s Re(sum y lbar))
+  if (mfterm) mfterm[(size_t)w * nblk + b] = mkc(s * mi, -s * mr);
   if (capped) atomicOr(status, 0x10u);
 }
 
@@ -513,10 +520,11 @@ __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __rest
 // with log I = log(<Phi_T|Psi'>/<Phi_T|Psi>) - dtau (h0 - E_T) + sum_g (x xbar - xbar^2/2),
 // where <Phi_T|Psi'> is taken before this step's QR (log det R added back).
 // ---------------------------------------------------------------------------
-__global__ void k_weights(int nw, int mode, double dtau, double h0, double e_trial,
+__global__ void k_weights(int nw, int mode, double sf, double dtau, double h0, double e_trial,
                           double ecap_half, double w_max, const cd* __restrict__ logdet,
                           const unsigned* __restrict__ wflag, const cd* __restrict__ enew,
-                          const cd* __restrict__ fbterm, int nblk, const double* __restrict__ logR,
+                          const cd* __restrict__ fbterm, const cd* __restrict__ mfterm, int nblk,
+                          const double* __restrict__ logR,
                           double* __restrict__ weight, double* __restrict__ arg_ovlp,
                           double* __restrict__ log_ovlp, cd* __restrict__ e_loc,
                           double* __restrict__ phase, unsigned* __restrict__ status) {
@@ -526,12 +534,20 @@ __global__ void k_weights(int nw, int mode, double dtau, double h0, double e_tri
   if (!(W > 0.0)) return;
   unsigned st = 0u;
   const cd l0 = logdet[2 * w], l1 = logdet[2 * w + 1];
-  double a = l0.im + l1.im;
+  double a = sf * l0.im + l1.im;
   a = a - 2.0 * M_PI * floor((a + M_PI) / (2.0 * M_PI));   // (-pi, pi]
   if (a <= -M_PI) a += 2.0 * M_PI;
-  const double la = l0.re + l1.re;
+  const double la = sf * l0.re + l1.re;
   const cd en = enew[w];
   const unsigned fl = wflag[2 * w] | wflag[2 * w + 1];
+  // mean-field c-number on the overlap ratio (zero without subtraction)
+  double mre = 0.0, mim = 0.0;
+  if (mfterm)
+    for (int b = 0; b < nblk; ++b) {
+      const cd f = mfterm[(size_t)w * nblk + b];
+      mre += f.re;
+      mim += f.im;
+    }
   double Wn;
   if (fl & WFLAG_SINGULAR) {
     Wn = 0.0;
@@ -549,7 +565,7 @@ __global__ void k_weights(int nw, int mode, double dtau, double h0, double e_tri
       ec = e_trial + ecap_half;
       st |= 0x4u;
     }
-    const double proj = fmax(0.0, cos(a - arg_ovlp[w]));
+    const double proj = fmax(0.0, cos(a - arg_ovlp[w] + mim));
     if (!(proj > 0.0)) st |= 0x20u;
     Wn = W * exp(-dtau * (ec - e_trial)) * proj;
     if (Wn > w_max) {
@@ -563,11 +579,11 @@ __global__ void k_weights(int nw, int mode, double dtau, double h0, double e_tri
       fr += f.re;
       fi += f.im;
     }
-    const double lr = logR ? logR[2 * w] + logR[2 * w + 1] : 0.0;
-    const double lre = (la + lr - log_ovlp[w]) - dtau * (h0 - e_trial) + fr;
-    const double lim = (a - arg_ovlp[w]) + fi;
+    const double lr = logR ? sf * logR[2 * w] + logR[2 * w + 1] : 0.0;
+    const double lre = (la + lr - log_ovlp[w]) + mre - dtau * (h0 - e_trial) + fr;
+    const double lim = (a - arg_ovlp[w]) + mim + fi;
     if (mode == 1) {
-      const double proj = fmax(0.0, cos(a - arg_ovlp[w]));
+      const double proj = fmax(0.0, cos(a - arg_ovlp[w] + mim));
       if (!(proj > 0.0)) st |= 0x20u;
       Wn = W * exp(lre) * proj;
       if (Wn > w_max) {
@@ -594,7 +610,7 @@ __global__ void k_weights(int nw, int mode, double dtau, double h0, double e_tri
 }
 
 // Initialization / measurement: phase and log of the overlap, E_L, from logdet and enew.
-__global__ void k_measure_finish(int nw, const cd* __restrict__ logdet,
+__global__ void k_measure_finish(int nw, double sf, const cd* __restrict__ logdet,
                                  const unsigned* __restrict__ wflag, const cd* __restrict__ enew,
                                  double* __restrict__ weight, double* __restrict__ arg_ovlp,
                                  double* __restrict__ log_ovlp, cd* __restrict__ e_loc,
@@ -602,12 +618,12 @@ __global__ void k_measure_finish(int nw, const cd* __restrict__ logdet,
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
   const cd l0 = logdet[2 * w], l1 = logdet[2 * w + 1];
-  double a = l0.im + l1.im;
+  double a = sf * l0.im + l1.im;
   a = a - 2.0 * M_PI * floor((a + M_PI) / (2.0 * M_PI));
   if (a <= -M_PI) a += 2.0 * M_PI;
   const unsigned fl = wflag[2 * w] | wflag[2 * w + 1];
   arg_ovlp[w] = a;
-  log_ovlp[w] = l0.re + l1.re;
+  log_ovlp[w] = sf * l0.re + l1.re;
   e_loc[w] = enew[w];
   if ((fl & WFLAG_SINGULAR) || !cfinite(enew[w])) {
     weight[w] = 0.0;

@@ -28,14 +28,16 @@ def oracle_U_to_gpu(Uu: np.ndarray, Ud: np.ndarray) -> np.ndarray:
 
 
 def make_pair(s, nw: int, *, dtau: float, precision: str = "fp64", qr_period: int = 5,
-              pop_period: int = 5, n_taylor: int = 6, U=None, weight_mode: str = "phaseless"):
+              pop_period: int = 5, n_taylor: int = 6, U=None, weight_mode: str = "phaseless",
+              mean_field: bool = False, closed_shell: bool = False):
     import paper_1711_02242_amd as afq
-    S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, dtau)
+    S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, dtau, mean_field=mean_field)
     P = A.Params(dtau=dtau, n_taylor=n_taylor, qr_period=qr_period, pop_period=pop_period,
                  weight_mode=weight_mode)
     gs = afq.System.from_synthetic(s, dtau=dtau, precision=precision, qr_period=qr_period,
                                    pop_period=pop_period, n_taylor=n_taylor,
-                                   weight_mode=weight_mode)
+                                   weight_mode=weight_mode, mean_field=mean_field,
+                                   closed_shell=closed_shell)
     wk = gs.walkers(nw)
     gs.init(wk)
     if U is None:
@@ -44,7 +46,8 @@ def make_pair(s, nw: int, *, dtau: float, precision: str = "fp64", qr_period: in
         import torch
         Uu, Ud = U
         wo = A.init_walkers(S, nw, Uu, Ud)
-        wk.U.copy_(torch.from_numpy(oracle_U_to_gpu(Uu, Ud)))
+        Ug = oracle_U_to_gpu(Uu, Ud)
+        wk.U.copy_(torch.from_numpy(Ug[:, : gs.ntot]))
         gs.measure(wk)
     return S, P, wo, gs, wk
 
@@ -65,6 +68,10 @@ def angle_diff(a, b):
 def compare_state(S, wo, st, n_up: int, rtol: float, what: str = ""):
     """Largest relative deviations of the GPU state from the oracle's (returns a dict)."""
     Uu, Ud = gpu_U_to_oracle(st["U"], n_up)
+    if Ud.shape[2] == 0 and wo.U[1].shape[2] == n_up and n_up > 0:
+        # closed-shell storage: the up block stands for both spins
+        assert np.array_equal(wo.U[0], wo.U[1])
+        Ud = Uu
     alive = wo.W > 0
     out = {}
     scaleU = max(np.abs(wo.U[0]).max(), np.abs(wo.U[1]).max() if wo.U[1].size else 0.0)
@@ -88,10 +95,12 @@ def compare_state(S, wo, st, n_up: int, rtol: float, what: str = ""):
 def run_lockstep(s, nw: int, steps: int, *, dtau: float, precision: str = "fp64",
                  explicit_fields: bool = True, seed: int = 0, rtol: float = 1e-10,
                  qr_period: int = 5, pop_period: int = 5, check_every: int = 1, U=None,
-                 label: str = "", weight_mode: str = "phaseless"):
+                 label: str = "", weight_mode: str = "phaseless", mean_field: bool = False,
+                 closed_shell: bool = False):
     import torch
     S, P, wo, gs, wk = make_pair(s, nw, dtau=dtau, precision=precision, qr_period=qr_period,
-                                 pop_period=pop_period, U=U, weight_mode=weight_mode)
+                                 pop_period=pop_period, U=U, weight_mode=weight_mode,
+                                 mean_field=mean_field, closed_shell=closed_shell)
     compare_state(S, wo, gpu_state(wk), s.n_up, rtol, f"{label} init")
     worst = {}
     for k in range(steps):

@@ -1,0 +1,68 @@
+"""Mean-field subtraction (Sec. II.B.3) and the closed-shell one-spin path on the GPU against
+the general two-spin FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from synthetic import config_system, gen_system, random_walkers
+from tests.parity_helpers import gpu_state, log, make_pair, run_lockstep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mode", ["phaseless", "hybrid", "free"])
+@pytest.mark.parametrize("case", ["tiny", "medium"])
+def test_mean_field_lockstep(mode, case):
+    if case == "tiny":
+        s, nw, steps, dt = config_system("tiny"), 16, 40, 0.01
+    else:
+        s, nw, steps, dt = config_system("medium"), 8, 10, 0.005
+    log(f"mean field {mode} {case}")
+    worst, *_ = run_lockstep(s, nw, steps, dtau=dt, label=f"mf-{mode}-{case}", weight_mode=mode,
+                             mean_field=True)
+    log(f"  worst {worst}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("mean_field", [False, True])
+def test_closed_shell_matches_two_spin_oracle(precision, mean_field):
+    s = config_system("medium") if precision == "fp64" else config_system("tiny")
+    nw, steps, dt = (8, 10, 0.005) if precision == "fp64" else (16, 30, 0.01)
+    rtol = 1e-10 if precision == "fp64" else 1e-4
+    log(f"closed shell {precision} mf={mean_field}")
+    worst, gs, wk, S, wo = run_lockstep(s, nw, steps, dtau=dt, precision=precision, rtol=rtol,
+                                        label=f"cs-{precision}", mean_field=mean_field,
+                                        closed_shell=True)
+    assert gs.ntot == s.n_up and tuple(wk.U.shape) == (nw, s.n_up, s.M)
+    log(f"  worst {worst}")
+
+
+def test_closed_shell_large_static_energy():
+    """Full-size closed-shell measure: E_L of random closed-shell walkers equals the two-spin
+    GPU FP64 path's."""
+    import torch
+
+    import paper_1711_02242_amd as afq
+    s = config_system("large")
+    nw = 64
+    Uu, _ = random_walkers(s, nw, seed=3, amplitude=0.3)
+    Ut = torch.from_numpy(np.ascontiguousarray(Uu.transpose(0, 2, 1))).cuda()
+    out = {}
+    for cs in (False, True):
+        gs = afq.System.from_synthetic(s, dtau=0.005, precision="fp64", closed_shell=cs)
+        wk = gs.walkers(nw)
+        gs.init(wk)
+        wk.U.copy_(torch.cat([Ut, Ut], dim=1) if not cs else Ut)
+        gs.measure(wk)
+        torch.cuda.synchronize()
+        out[cs] = (wk.e_loc.cpu().numpy(), wk.arg_ovlp.cpu().numpy(), wk.log_ovlp.cpu().numpy())
+        gs.close()
+    for a, b in zip(out[False], out[True]):
+        assert np.abs(a - b).max() < 1e-10 * max(1.0, np.abs(a).max())
+
+
+def test_closed_shell_rejects_open_shell_input():
+    import paper_1711_02242_amd as afq
+    s = gen_system(10, 3, 12, seed=7, n_dn=2)
+    with pytest.raises(afq.AfqmcError):
+        afq.System.from_synthetic(s, dtau=0.01, closed_shell=True)
