@@ -56,12 +56,12 @@ def recorded_traffic(precision):
         return None
 
 
-def run_gpu(s, args, precision, steps, warmup, timed_kernels=True):
+def run_gpu(s, args, precision, steps, warmup, timed_kernels=True, closed_shell=False):
     import torch
 
     import paper_1711_02242_amd as afq
     gs = afq.System.from_synthetic(s, dtau=args.dtau, precision=precision, qr_period=5,
-                                   pop_period=5)
+                                   pop_period=5, closed_shell=closed_shell)
     wk = gs.walkers(args.walkers)
     gs.init(wk)
     for _ in range(warmup):
@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--cpu-walkers", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--oracle-sample", type=int, default=4)
+    ap.add_argument("--no-closed-shell", action="store_true",
+                    help="skip the closed-shell one-spin measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -229,6 +231,16 @@ def main():
         g2.close()
     else:
         gs.close()
+
+    if not args.no_closed_shell and not args.no_compare:
+        # the same workload on the closed-shell path (U_up = U_dn stored once; identical results)
+        g3, w3, dt3, kt3, e3 = run_gpu(s, args, args.precision, args.steps, 2,
+                                       timed_kernels=False, closed_shell=True)
+        out["closed_shell"] = {"value": round(args.walkers * args.steps / dt3, 2),
+                               "unit": "walker-steps/s",
+                               "ms_per_step": round(1e3 * dt3 / args.steps, 3),
+                               "e_mix": e3[0] / e3[2]}
+        g3.close()
 
     if not args.no_cpu:
         cb = cpu_baseline(s, args)
