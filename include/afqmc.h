@@ -221,6 +221,25 @@ AFQMC_API int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear);
 AFQMC_API int afqmc_kernel_timing(afqmc_sys s, int enable);
 AFQMC_API int afqmc_kernel_time(afqmc_sys s, int kernel, double* ms, int64_t* launches);
 
+/* Modified Cholesky decomposition of the two-electron tensor (Sec. II.B.2, eq:chol, eq:chol2):
+ * with V_{(p r),(q s)} = v_pqrs, find vectors L^g (each M x M) with V ~ sum_g L^g L^g^T.  Each
+ * step takes the largest residual diagonal Dmax (first index on ties), stops when Dmax < delta,
+ * zeroes the entries with sqrt(|D_mu| Dmax) <= min(1e-9, delta) (damped prescreening) and appends
+ * the residual pivot column / sqrt(Dmax).  On convergence every residual element is <= delta.
+ * eri       device, [M][M][M][M] doubles, eri[p][q][r][s] = v_pqrs (real orbitals, so
+ *           v_pqrs = v_rqps = v_psrq); read only
+ * L_out     device, [max_vectors][M][M] doubles (caller-owned); vector g is L_out[g]
+ * n_vectors host out: number of vectors written
+ * converged host out (may be NULL): 1 if Dmax < delta was reached within max_vectors
+ * workspace device, afqmc_mcd_workspace_bytes(M) bytes, 256-byte aligned
+ * stream    hipStream_t for the work; the call synchronizes it.
+ * Returns AFQMC_E_ARG / AFQMC_E_NOMEM on bad arguments, AFQMC_E_HIP on launch errors. */
+AFQMC_API int afqmc_mcd_workspace_bytes(int32_t M, size_t* bytes);
+AFQMC_API int afqmc_modified_cholesky(const double* eri, int32_t M, double delta,
+                                      int32_t max_vectors, double* L_out, int32_t* n_vectors,
+                                      int32_t* converged, void* workspace,
+                                      size_t workspace_bytes, void* stream);
+
 /* Free the device memory owned by the system. */
 AFQMC_API int afqmc_destroy(afqmc_sys s);
 

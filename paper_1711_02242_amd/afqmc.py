@@ -211,3 +211,26 @@ class Walkers:
 
     def sync_from_c(self):
         self.step = int(self._c.step)
+
+
+def modified_cholesky(eri, delta: float, max_vectors: int | None = None, stream=None):
+    """Modified Cholesky decomposition of a device tensor eri[p, q, r, s] = v_pqrs (float64,
+    (M, M, M, M)) on the GPU.  Returns (L, converged) with L a device tensor (n, M, M)."""
+    torch = _torch()
+    lib = L.load()
+    assert eri.is_cuda and eri.dtype == torch.float64 and eri.is_contiguous() and eri.dim() == 4
+    M = int(eri.shape[0])
+    nmax = M * M if max_vectors is None else int(max_vectors)
+    out = torch.empty((max(nmax, 1), M, M), dtype=torch.float64, device=eri.device)
+    wb = C.c_size_t()
+    L.check(lib.afqmc_mcd_workspace_bytes(M, C.byref(wb)), "afqmc_mcd_workspace_bytes")
+    raw = torch.empty(wb.value + 256, dtype=torch.uint8, device=eri.device)
+    off = (-int(raw.data_ptr())) % 256
+    n = C.c_int32()
+    conv = C.c_int32()
+    L.check(lib.afqmc_modified_cholesky(C.c_void_p(int(eri.data_ptr())), M, float(delta), nmax,
+                                        C.c_void_p(int(out.data_ptr())), C.byref(n), C.byref(conv),
+                                        C.c_void_p(int(raw.data_ptr()) + off), wb.value,
+                                        C.c_void_p(_stream_handle(stream))),
+            "afqmc_modified_cholesky")
+    return out[: n.value], bool(conv.value)

@@ -14,6 +14,7 @@
 #include "kernels_fp64.hpp"
 #include "kernels_mfma.hpp"
 #include "kernels_prop.hpp"
+#include "kernels_mcd.hpp"
 
 namespace {
 
@@ -891,6 +892,54 @@ int afqmc_kernel_time(afqmc_sys s, int kernel, double* ms, int64_t* launches) {
   flush_timing(s);
   *ms = s->acc_ms[kernel];
   *launches = s->acc_n[kernel];
+  return AFQMC_OK;
+}
+
+int afqmc_mcd_workspace_bytes(int32_t M, size_t* bytes) {
+  if (M < 1 || !bytes) return AFQMC_E_ARG;
+  const size_t MM = (size_t)M * M;
+  *bytes = al256(MM * 8) + al256(MM) + al256(sizeof(McdState));
+  return AFQMC_OK;
+}
+
+int afqmc_modified_cholesky(const double* eri, int32_t M, double delta, int32_t max_vectors,
+                            double* L_out, int32_t* n_vectors, int32_t* converged,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  if (!eri || M < 1 || !(delta > 0.0) || max_vectors < 0 || (max_vectors > 0 && !L_out) ||
+      !n_vectors || !workspace)
+    return AFQMC_E_ARG;
+  size_t need = 0;
+  afqmc_mcd_workspace_bytes(M, &need);
+  if (workspace_bytes < need) return AFQMC_E_NOMEM;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return AFQMC_E_ARG;
+  const size_t MM = (size_t)M * M;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  double* D = at<double>(workspace, 0);
+  unsigned char* dead = at<unsigned char>(workspace, al256(MM * 8));
+  McdState* state = at<McdState>(workspace, al256(MM * 8) + al256(MM));
+  hipLaunchKernelGGL(k_mcd_init, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, st, M, eri, D,
+                     dead, state);
+  HIPCHK(hipGetLastError());
+  McdState h{};
+  int n = 0;
+  for (; n <= max_vectors; ++n) {
+    hipLaunchKernelGGL(k_mcd_pivot, dim3(1), dim3(1024), 0, st, (int)MM, delta, n, max_vectors, D,
+                       dead, state);
+    if (n < max_vectors)
+      hipLaunchKernelGGL(k_mcd_column, dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, st, M, n,
+                         eri, L_out, D, dead, state);
+    HIPCHK(hipGetLastError());
+    if ((n & 31) == 31 || n == max_vectors) {
+      HIPCHK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (h.done) break;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (!h.done) return AFQMC_E_STATE;
+  *n_vectors = h.count;
+  if (converged) *converged = h.count < max_vectors || h.dmax < delta ? 1 : 0;
   return AFQMC_OK;
 }
 
