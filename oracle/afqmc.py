@@ -319,27 +319,38 @@ def measure(S: Setup, U_up: np.ndarray, U_dn: np.ndarray):
     return float(wrap_angle(lg.imag)), float(lg.real), e, t
 
 
-def init_walkers(S: Setup, n_walkers: int, U_up=None, U_dn=None) -> Walkers:
-    """Every walker starts as {Psi_I = Phi_T, W = 1, theta = 0} (Sec. II.C, Sec. III.E)
-    unless explicit determinants are given."""
+def _measure_any(S, U_up, U_dn):
+    return measure_multi(S, U_up, U_dn) if isinstance(S, MultiSetup) else measure(S, U_up, U_dn)
+
+
+def _first(S):
+    """The single-determinant Setup that carries h, L, E_h and the trial's first determinant."""
+    return S.dets[0] if isinstance(S, MultiSetup) else S
+
+
+def init_walkers(S, n_walkers: int, U_up=None, U_dn=None) -> Walkers:
+    """Every walker starts as {Psi_I, W = 1, theta = 0} (Sec. II.C, Sec. III.E) with Psi_I the
+    (first) trial determinant unless explicit determinants are given."""
+    S = S if isinstance(S, MultiSetup) else S
+    S0 = _first(S)
     if U_up is None:
-        U_up = np.repeat(S.V[0][None].astype(np.complex128), n_walkers, axis=0)
+        U_up = np.repeat(S0.V[0][None].astype(np.complex128), n_walkers, axis=0)
     if U_dn is None:
-        U_dn = np.repeat(S.V[1][None].astype(np.complex128), n_walkers, axis=0)
+        U_dn = np.repeat(S0.V[1][None].astype(np.complex128), n_walkers, axis=0)
     U_up = np.array(U_up, dtype=np.complex128)
     U_dn = np.array(U_dn, dtype=np.complex128)
     n = U_up.shape[0]
     arg = np.zeros(n)
     logabs = np.zeros(n)
     e = np.zeros(n, dtype=np.complex128)
-    t = np.zeros((n, S.n_chol), dtype=np.complex128)
+    t = np.zeros((n, S0.n_chol), dtype=np.complex128)
     for w in range(n):
-        arg[w], logabs[w], e[w], t[w] = measure(S, U_up[w], U_dn[w])
+        arg[w], logabs[w], e[w], t[w] = _measure_any(S, U_up[w], U_dn[w])
     return Walkers(U=[U_up, U_dn], W=np.ones(n), arg=arg, logabs=logabs, e_loc=e, t=t,
                    walker_id=np.arange(n, dtype=np.int64), step=0, theta=np.zeros(n))
 
 
-def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
+def step(S, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
          info: dict | None = None) -> Walkers:
     """One step of the random walk for every walker (Sec. III.E), in place.
 
@@ -347,6 +358,7 @@ def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None =
     is the comb's uniform, needed when population control is due after it.
     Walkers with zero weight are skipped until population control replaces them.
     """
+    Sm, S = S, _first(S)      # Sm measures (single or multi-determinant), S propagates
     k = wk.step
     n = wk.n
     wmax = P.wmax(n)
@@ -365,7 +377,7 @@ def step(S: Setup, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None =
             U_up, r_up = modified_gram_schmidt(U_up)
             U_dn, r_dn = modified_gram_schmidt(U_dn)
             log_r = float(np.sum(np.log(r_up)) + np.sum(np.log(r_dn)))
-        arg_new, logabs_new, e_new, t_new = measure(S, U_up, U_dn)
+        arg_new, logabs_new, e_new, t_new = _measure_any(Sm, U_up, U_dn)
         if P.weight_mode == WEIGHT_PHASELESS:
             dphase = mean_field_log_factor(S, x[w], xbar).imag
             wk.W[w] = phaseless_weight(wk.W[w], wk.e_loc[w], wk.arg[w], arg_new + dphase, P.dtau,
@@ -420,3 +432,89 @@ def mixed_energy(S: Setup, P: Params, wk: Walkers):
     swi = float(np.sum(wk.W * wk.e_loc.imag))
     alive = int(np.count_nonzero(wk.W > 0))
     return swe / sw, swe, swi, sw, alive
+
+
+# --------------------------------------------------------------------------
+# Multi-determinant trial (Sec. III.D.1, eq:usesherman, eq:precomputing2, eq:localenergy2)
+# --------------------------------------------------------------------------
+
+@dataclass
+class MultiSetup:
+    """Psi_T = sum_d A_d |Psi_d>; one single-determinant Setup per determinant (sharing h, L)."""
+    dets: list            # list of Setup, one per determinant
+    coeffs: np.ndarray    # (N_d,) complex A_d
+    E_T: float
+    dtau: float
+    lbar: np.ndarray
+    h0_prop: float
+
+    @property
+    def n_chol(self):
+        return self.dets[0].n_chol
+
+
+def measure_multi(MS: MultiSetup, U_up: np.ndarray, U_dn: np.ndarray):
+    """Overlap, local energy and force-bias traces of one walker against a multi-determinant
+    trial.  With r_d = A_d^* <Psi_d|Psi>:
+      <Psi_T|Psi> = sum_d r_d;   E_L = sum_d r_d E_L^d / sum_d r_d   (linearity of eq:localenergy2);
+      t_g = sum_d r_d t^d_g / sum_d r_d                           (eq:precomputing2),
+    where E_L^d, t^d are the single-determinant quantities against Psi_d (eq:localenergy3).
+    Returns (arg <Psi_T|Psi>, log|<Psi_T|Psi>|, E_L, t)."""
+    logs, es, ts, keep = [], [], [], []
+    for d, S in enumerate(MS.dets):
+        # An exactly singular V_d^T U gives r_d = 0; its energy term A_d^* <Psi_d|H|Psi> is then
+        # dropped, which is exact only for walkers non-orthogonal to every determinant
+        # (propagated walkers are, with probability one).
+        if any(np.linalg.slogdet(S.V[k].T @ U)[0] == 0 for k, U in ((0, U_up), (1, U_dn))
+               if U.shape[1] > 0):
+            continue
+        lg_u, th_u = overlap_theta(S.V[0], U_up)
+        lg_d, th_d = overlap_theta(S.V[1], U_dn)
+        e, t = local_energy(S, [th_u, th_d])
+        logs.append(lg_u + lg_d)
+        es.append(e)
+        ts.append(t)
+        keep.append(d)
+    logs = np.array(logs)
+    ref = np.max(logs.real)
+    r = np.conj(MS.coeffs[keep]) * np.exp(logs - ref)
+    R = np.sum(r)
+    e = complex(np.sum(r * np.array(es)) / R)
+    t = np.sum(r[:, None] * np.array(ts), axis=0) / R
+    lg = np.log(R) + ref
+    return float(wrap_angle(lg.imag)), float(lg.real), e, t
+
+
+def setup_multi(h0, h1, L, coeffs, phis_up, phis_dn, dtau, e_trial=None,
+                mean_field: bool = False) -> MultiSetup:
+    """A_d = coeffs[d], determinant d = (phis_up[d], phis_dn[d]).
+
+    The trial energy E_T and the mean-field shifts lbar are constants of the method (any
+    value leaves the estimator exact, Sec. II.B.3, App. B.2); for a multi-determinant trial
+    they are taken from the leading determinant d = 0: E_T = E_L(Psi_0; Psi_0) and
+    lbar_g = <Psi_0|L_g|Psi_0> / <Psi_0|Psi_0>.  ``trial_energy_multi`` gives the Rayleigh
+    quotient of the whole expansion when its determinants are pairwise non-orthogonal."""
+    coeffs = np.asarray(coeffs, dtype=np.complex128)
+    dets = [setup(h0, h1, L, pu, pd, dtau, mean_field=mean_field) for pu, pd in zip(phis_up, phis_dn)]
+    lead = dets[0]
+    MS = MultiSetup(dets=dets, coeffs=coeffs, E_T=lead.E_T if e_trial is None else float(e_trial),
+                    dtau=float(dtau), lbar=lead.lbar.copy(), h0_prop=lead.h0_prop)
+    for S in dets:
+        S.E_T = MS.E_T
+        if mean_field:
+            S.lbar = MS.lbar
+            S.v0 = one_body_v0(S.h1, S.L) + np.einsum("g,gpq->pq", MS.lbar, S.L)
+            S.h0_prop = MS.h0_prop
+            S.Eh = sym_expm(S.v0, -0.5 * dtau)
+    return MS
+
+
+def trial_energy_multi(MS: MultiSetup) -> float:
+    """<Psi_T|H|Psi_T>/<Psi_T|Psi_T> = sum_d' A_d' <Psi_T|Psi_d'> E_L(Psi_d') / sum_d' A_d' <Psi_T|Psi_d'>,
+    exact when no two determinants of the expansion are orthogonal."""
+    num, den = 0.0, 0.0
+    for d, S in enumerate(MS.dets):
+        a, la, e, _ = measure_multi(MS, S.V[0].astype(complex), S.V[1].astype(complex))
+        w = MS.coeffs[d] * np.exp(la + 1j * a)
+        num, den = num + w * e, den + w
+    return float((num / den).real)
