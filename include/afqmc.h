@@ -172,6 +172,27 @@ typedef struct {
 AFQMC_API int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double* L_chol,
                 const double* phi_up, const double* phi_dn, void* stream, afqmc_sys* out);
 
+/* Setup with a multi-determinant trial Psi_T = sum_d A_d |Psi_d> (Sec. II.B; the mixed
+ * estimator of eq:localenergy2 and the traces of eq:precomputing2 are linear in <Psi_T|):
+ * every per-walker quantity is formed from r_d = conj(A_d) <Psi_d|Psi> as
+ *   <Psi_T|Psi> = sum_d r_d,  E_L = sum_d r_d E_L^d / sum_d r_d,  t_g = sum_d r_d t^d_g / sum_d r_d.
+ * n_det   1..1024 determinants.
+ * coeffs  host, n_det*2 doubles: A_d = coeffs[2d] + i coeffs[2d+1] (finite; not normalized).
+ * phi_up  host, n_det blocks of M*n_up row-major (block d is V_{d,up}); phi_dn likewise.
+ *         Block 0 is the leading determinant: E_T (when p->e_trial is NaN), E_HF and the
+ *         mean-field shifts are taken from it, and afqmc_walkers_init starts the walkers at it;
+ *         V_{0,s}^T V_{0,s} must be invertible.  The other blocks may be orthogonal to it.
+ * A determinant whose overlap with a walker is exactly singular contributes r_d = 0 and is
+ * left out of that walker's E_L (exact for walkers non-orthogonal to every determinant);
+ * a walker orthogonal to all of them is treated as a singular overlap.  With
+ * AFQMC_FLAG_CLOSED_SHELL every block needs phi_up == phi_dn.  The per-walker workspace
+ * grows with n_det (afqmc_workspace_bytes).  Requires max(n_up, n_dn) <= 32 and M <= 128
+ * (the MFMA kernels), else AFQMC_E_UNSUPPORTED; otherwise as afqmc_setup. */
+AFQMC_API int afqmc_setup_multidet(const afqmc_params* p, double h0, const double* h1,
+                                   const double* L_chol, int32_t n_det, const double* coeffs,
+                                   const double* phi_up, const double* phi_dn, void* stream,
+                                   afqmc_sys* out);
+
 /* Device bytes of workspace that n_walkers walkers need (for admission by HBM footprint). */
 AFQMC_API int afqmc_workspace_bytes(afqmc_sys s, int32_t n_walkers, size_t* bytes);
 

@@ -22,7 +22,7 @@ KERNEL_GROUPS = ["contract", "overlap", "fields", "abuild", "propagate", "qr", "
 EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walkers_init",
            "afqmc_measure", "afqmc_step", "afqmc_fields_draw", "afqmc_energy", "afqmc_get_status",
            "afqmc_kernel_timing", "afqmc_kernel_time", "afqmc_destroy", "afqmc_error_string",
-           "afqmc_mcd_workspace_bytes", "afqmc_modified_cholesky"]
+           "afqmc_mcd_workspace_bytes", "afqmc_modified_cholesky", "afqmc_setup_multidet"]
 
 
 class Params(C.Structure):
@@ -70,6 +70,9 @@ def load(path: str | None = None) -> C.CDLL:
     sig = {
         "afqmc_setup": ([P(Params), C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                          C.c_void_p, P(C.c_void_p)], C.c_int),
+        "afqmc_setup_multidet": ([P(Params), C.c_double, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_void_p)],
+                                 C.c_int),
         "afqmc_workspace_bytes": ([C.c_void_p, C.c_int32, P(C.c_size_t)], C.c_int),
         "afqmc_get_info": ([C.c_void_p, P(InfoC)], C.c_int),
         "afqmc_walkers_init": ([C.c_void_p, P(WalkersC)], C.c_int),

@@ -27,16 +27,18 @@ def _stream_handle(stream) -> int:
 
 
 class System:
-    """A Hamiltonian in Cholesky form plus a single-determinant trial, resident on the GPU.
+    """A Hamiltonian in Cholesky form plus a trial, resident on the GPU.
 
     h1 (M, M), L (n_chol, M, M), phi_up (M, n_up), phi_dn (M, n_dn): real float64 host arrays.
+    With ``coeffs`` (n_det complex A_d) the trial is sum_d A_d |Psi_d> and phi_up / phi_dn are
+    (n_det, M, n_up) / (n_det, M, n_dn), the leading determinant first (``System.multidet``).
     """
 
     def __init__(self, h0, h1, L_chol, phi_up, phi_dn, *, dtau: float, precision: str = "fp64",
                  n_taylor: int = 6, qr_period: int = 5, pop_period: int = 5, el_cap_C: float = 2.0,
                  w_max: float | None = None, fb_cap: float = 1.0, e_trial: float | None = None,
                  weight_mode: str = "phaseless", mean_field: bool = False,
-                 closed_shell: bool = False, stream=None):
+                 closed_shell: bool = False, coeffs=None, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise L.AfqmcError("no GPU visible: the AFQMC library runs on the GPU only")
@@ -44,9 +46,19 @@ class System:
         h1 = np.ascontiguousarray(h1, dtype=np.float64)
         M = h1.shape[0]
         L_chol = np.ascontiguousarray(L_chol, dtype=np.float64).reshape(-1, M, M)
-        phi_up = np.ascontiguousarray(phi_up, dtype=np.float64).reshape(M, -1)
-        phi_dn = np.ascontiguousarray(phi_dn, dtype=np.float64).reshape(M, -1)
-        self.M, self.n_up, self.n_dn, self.n_chol = M, phi_up.shape[1], phi_dn.shape[1], L_chol.shape[0]
+        if coeffs is None:
+            self.n_det = 1
+            phi_up = np.ascontiguousarray(phi_up, dtype=np.float64).reshape(M, -1)
+            phi_dn = np.ascontiguousarray(phi_dn, dtype=np.float64).reshape(M, -1)
+            n_up, n_dn = phi_up.shape[1], phi_dn.shape[1]
+        else:
+            cf = np.asarray(coeffs, dtype=np.complex128).reshape(-1)
+            self.n_det = cf.size
+            phi_up = np.ascontiguousarray(phi_up, dtype=np.float64).reshape(self.n_det, M, -1)
+            phi_dn = np.ascontiguousarray(phi_dn, dtype=np.float64).reshape(self.n_det, M, -1)
+            n_up, n_dn = phi_up.shape[2], phi_dn.shape[2]
+            cpair = np.ascontiguousarray(np.stack([cf.real, cf.imag], axis=1))
+        self.M, self.n_up, self.n_dn, self.n_chol = M, n_up, n_dn, L_chol.shape[0]
         self.closed_shell = bool(closed_shell)
         self.ntot = self.n_up if self.closed_shell else self.n_up + self.n_dn
         self.dtau = float(dtau)
@@ -63,10 +75,18 @@ class System:
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
-        rc = self.lib.afqmc_setup(C.byref(p), float(h0), h1.ctypes.data, L_chol.ctypes.data,
-                                  phi_up.ctypes.data, phi_dn.ctypes.data,
-                                  C.c_void_p(_stream_handle(self.stream)), C.byref(handle))
-        L.check(rc, "afqmc_setup")
+        if coeffs is None:
+            rc = self.lib.afqmc_setup(C.byref(p), float(h0), h1.ctypes.data, L_chol.ctypes.data,
+                                      phi_up.ctypes.data, phi_dn.ctypes.data,
+                                      C.c_void_p(_stream_handle(self.stream)), C.byref(handle))
+            L.check(rc, "afqmc_setup")
+        else:
+            rc = self.lib.afqmc_setup_multidet(C.byref(p), float(h0), h1.ctypes.data,
+                                               L_chol.ctypes.data, self.n_det, cpair.ctypes.data,
+                                               phi_up.ctypes.data, phi_dn.ctypes.data,
+                                               C.c_void_p(_stream_handle(self.stream)),
+                                               C.byref(handle))
+            L.check(rc, "afqmc_setup_multidet")
         self.handle = handle
         info = L.InfoC()
         L.check(self.lib.afqmc_get_info(self.handle, C.byref(info)), "afqmc_get_info")
@@ -77,6 +97,11 @@ class System:
     @classmethod
     def from_synthetic(cls, s, **kw):
         return cls(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, **kw)
+
+    @classmethod
+    def multidet(cls, h0, h1, L_chol, coeffs, phis_up, phis_dn, **kw):
+        """Trial sum_d coeffs[d] |Psi_d> with determinant d = (phis_up[d], phis_dn[d])."""
+        return cls(h0, h1, L_chol, phis_up, phis_dn, coeffs=coeffs, **kw)
 
     def close(self):
         if getattr(self, "handle", None):

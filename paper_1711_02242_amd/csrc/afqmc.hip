@@ -28,7 +28,7 @@ struct TimedLaunch {
 
 struct WsLayout {
   size_t thetaT, tcur, tpart, exch, e1, logdet, wflag, enew, y, A, X0, X1, Y, parent, csum,
-      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, mfterm, logR, psnap, total;
+      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, mfterm, logR, psnap, ldc, wflc, total;
 };
 
 }  // namespace
@@ -54,6 +54,10 @@ struct afqmc_sys_s {
   int sf = 1;              // spin factor: 2 in closed-shell mode (only the up block is stored)
   double h0p = 0.0;        // constant of the propagated Hamiltonian (H0 - 1/2 sum lbar^2)
   double* lbar = nullptr;  // [G] mean-field shifts <L_g>_T (zeros without subtraction)
+  // multi-determinant trial: V, ht, Lh and the MFMA tables hold n_det blocks (leading first)
+  int n_det = 1;
+  bool multi = false;
+  double* coef = nullptr;  // [n_det][2] expansion coefficients A_d
   size_t device_bytes = 0;
   // timing
   bool timing = false;
@@ -74,14 +78,14 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
     o += al256(bytes);
     return r;
   };
-  const size_t M = S->M, G = S->G, nt = S->ntot;
-  L.thetaT = take(nw * nt * M * 16);
+  const size_t M = S->M, G = S->G, nt = S->ntot, nd = S->n_det;
+  L.thetaT = take(nw * nd * nt * M * 16);
   L.tcur = take(nw * G * 16);
-  L.tpart = take(nw * 2 * G * 16);
-  L.exch = take(nw * 2 * 16);
-  L.e1 = take(nw * 2 * 16);
-  L.logdet = take(nw * 2 * 16);
-  L.wflag = take(nw * 2 * 4);
+  L.tpart = take(nw * nd * 2 * G * 16);
+  L.exch = take(nw * nd * 2 * 16);
+  L.e1 = take(nw * nd * 2 * 16);
+  L.logdet = take(nw * nd * 2 * 16);
+  L.wflag = take(nw * nd * 2 * 4);
   L.enew = take(nw * 16);
   L.y = take(nw * G * 16);
   L.A = take(nw * M * M * 16);
@@ -101,6 +105,8 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.mfterm = take((S->p.flags & AFQMC_FLAG_MEAN_FIELD) ? nw * nblk * 16 : 0);
   L.logR = take(nw * 2 * 8);
   L.psnap = take(nw * 8);
+  L.ldc = take(S->multi ? nw * 2 * 16 : 0);
+  L.wflc = take(S->multi ? nw * 2 * 4 : 0);
   L.total = o;
   return L;
 }
@@ -254,6 +260,7 @@ void free_sys(afqmc_sys_s* S) {
   hipFree(S->Lt32);
   hipFree(S->lbar);
   hipFree(S->Eh32);
+  hipFree(S->coef);
   mfma_free_tables(S->mt);
   delete S;
 }
@@ -276,7 +283,7 @@ size_t gj_lds_bytes(const afqmc_sys_s* S) {
 int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, int check_weight) {
   Timer tm(S, KG_OVERLAP);
   const int nmax = std::max(S->nup, S->ndn);
-  dim3 grid(w->n_walkers, 2);
+  dim3 grid(w->n_walkers, 2, S->n_det);  // only k_overlap_mfma reads blockIdx.z (n_det > 1 needs it)
   void* ws = w->workspace;
   void* packed0 = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
   const int kind0 = !S->mt.enabled ? 0
@@ -359,10 +366,18 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
     HIPCHK(hipGetLastError());
   } else {
     Timer tm(S, KG_CONTRACT);
-    HIPCHK(mfma_contract(S->mt, S->stream, w->n_walkers, S->G, at<void>(ws, L.thetaP), w->weight,
-                         at<cd>(ws, L.tpart), at<cd>(ws, L.exch)));
+    HIPCHK(mfma_contract(S->mt, S->stream, w->n_walkers, S->n_det, S->G, at<void>(ws, L.thetaP),
+                         w->weight, at<cd>(ws, L.tpart), at<cd>(ws, L.exch)));
   }
-  {
+  if (S->multi) {
+    Timer tm(S, KG_ASSEMBLE);
+    hipLaunchKernelGGL(k_energy_assemble_multi, dim3(w->n_walkers), dim3(256), 0, S->stream, S->G,
+                       S->n_det, S->h0, (double)S->sf, S->coef, at<cd>(ws, L.tpart),
+                       at<cd>(ws, L.exch), at<cd>(ws, L.e1), at<cd>(ws, L.logdet),
+                       at<unsigned>(ws, L.wflag), w->weight, 1, at<cd>(ws, L.tcur),
+                       at<cd>(ws, L.enew), at<cd>(ws, L.ldc), at<unsigned>(ws, L.wflc));
+    HIPCHK(hipGetLastError());
+  } else {
     Timer tm(S, KG_ASSEMBLE);
     hipLaunchKernelGGL(k_energy_assemble, dim3(w->n_walkers), dim3(256), 0, S->stream, S->G, S->h0,
                        (double)S->sf,
@@ -381,7 +396,8 @@ int do_measure(afqmc_sys_s* S, afqmc_walkers* w) {
   rc = launch_contract(S, w, L);
   if (rc) return rc;
   hipLaunchKernelGGL(k_measure_finish, dim3((w->n_walkers + 255) / 256), dim3(256), 0, S->stream,
-                     w->n_walkers, (double)S->sf, at<cd>(ws, L.logdet), at<unsigned>(ws, L.wflag),
+                     w->n_walkers, (double)S->sf, at<cd>(ws, S->multi ? L.ldc : L.logdet),
+                     at<unsigned>(ws, S->multi ? L.wflc : L.wflag),
                      at<cd>(ws, L.enew), w->weight, w->arg_ovlp, w->log_ovlp, (cd*)w->e_loc,
                      S->status);
   HIPCHK(hipGetLastError());
@@ -425,11 +441,23 @@ const char* afqmc_error_string(int code) {
   }
 }
 
-int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double* L_chol,
-                const double* phi_up, const double* phi_dn, void* stream, afqmc_sys* out) {
+}  // extern "C"
+
+namespace {
+
+// Setup of a trial with n_det determinants; coeffs == nullptr is the single-determinant trial
+// of afqmc_setup.  phi_up / phi_dn hold n_det blocks [M][n_up] / [M][n_dn], the leading first.
+int setup_impl(const afqmc_params* p, double h0, const double* h1, const double* L_chol, int n_det,
+               const double* coeffs, const double* phi_up, const double* phi_dn, void* stream,
+               afqmc_sys* out) {
   if (!p || !h1 || !out) return AFQMC_E_ARG;
   *out = nullptr;
   const int M = p->M, nup = p->n_up, ndn = p->n_dn, G = p->n_chol;
+  const bool multi = coeffs != nullptr;
+  if (n_det < 1 || n_det > AFQMC_MAX_DETS || (!multi && n_det != 1)) return AFQMC_E_ARG;
+  if (multi)
+    for (int i = 0; i < 2 * n_det; ++i)
+      if (!std::isfinite(coeffs[i])) return AFQMC_E_ARG;
   if (M < 1 || nup < 0 || ndn < 0 || nup > M || ndn > M || nup + ndn < 1 || G < 0)
     return AFQMC_E_ARG;
   if (!(p->dtau > 0.0) || p->n_taylor < 1 || p->n_taylor > 20 || p->qr_period < 0 ||
@@ -443,7 +471,10 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
     return AFQMC_E_ARG;
   if (p->flags & AFQMC_FLAG_CLOSED_SHELL) {
     if (nup != ndn || nup == 0) return AFQMC_E_ARG;
-    if (memcmp(phi_up, phi_dn, sizeof(double) * (size_t)M * nup) != 0) return AFQMC_E_ARG;
+    for (int d = 0; d < n_det; ++d)
+      if (memcmp(phi_up + (size_t)d * M * nup, phi_dn + (size_t)d * M * ndn,
+                 sizeof(double) * (size_t)M * nup) != 0)
+        return AFQMC_E_ARG;
   }
   if ((G > 0 && !L_chol) || (nup > 0 && !phi_up) || (ndn > 0 && !phi_dn)) return AFQMC_E_ARG;
   if (p->precision < AFQMC_FP64 || p->precision > AFQMC_BF16X3) return AFQMC_E_UNSUPPORTED;
@@ -502,35 +533,46 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
       v0[(size_t)i * M + j] = v0[(size_t)j * M + i] = v;
     }
 
-  // Trial orbitals as rows: V[c][p] = (V_s)_{p, c'}
-  std::vector<double> Vr((size_t)nt * M);
-  for (int c = 0; c < nup; ++c)
-    for (int q = 0; q < M; ++q) Vr[(size_t)c * M + q] = phi_up[(size_t)q * nup + c];
-  for (int c = 0; c < ndn; ++c)
-    for (int q = 0; q < M; ++q) Vr[(size_t)(nup + c) * M + q] = phi_dn[(size_t)q * ndn + c];
-  // Half rotation (eq:precomputing2): Lh[g][c][q] = sum_p V[c][p] L^g_pq; ht[c][q] = sum_p V[c][p] h_pq
-  std::vector<double> Lh((size_t)G * nt * M, 0.0), ht((size_t)nt * M, 0.0);
-  for (int g = 0; g < G; ++g) {
-    const double* Lg = L_chol + (size_t)g * M * M;
-    for (int c = 0; c < nt; ++c) {
-      double* dst = Lh.data() + ((size_t)g * nt + c) * M;
-      const double* vc = Vr.data() + (size_t)c * M;
-      for (int q = 0; q < M; ++q) {
-        const double a = vc[q];
-        if (a == 0.0) continue;
-        const double* row = Lg + (size_t)q * M;
-        for (int j = 0; j < M; ++j) dst[j] += a * row[j];
+  // Trial orbitals as rows: V[d][c][p] = (V_{d,s})_{p, c'}
+  std::vector<double> Vr((size_t)n_det * nt * M);
+  for (int d = 0; d < n_det; ++d) {
+    const double* pu = phi_up + (size_t)d * M * nup;
+    const double* pd = phi_dn + (size_t)d * M * ndn;
+    double* vd = Vr.data() + (size_t)d * nt * M;
+    for (int c = 0; c < nup; ++c)
+      for (int q = 0; q < M; ++q) vd[(size_t)c * M + q] = pu[(size_t)q * nup + c];
+    for (int c = 0; c < ndn; ++c)
+      for (int q = 0; q < M; ++q) vd[(size_t)(nup + c) * M + q] = pd[(size_t)q * ndn + c];
+  }
+  // Half rotation (eq:precomputing2) per determinant:
+  // Lh[d][g][c][q] = sum_p V[d][c][p] L^g_pq; ht[d][c][q] = sum_p V[d][c][p] h_pq
+  std::vector<double> Lh((size_t)n_det * G * nt * M, 0.0), ht((size_t)n_det * nt * M, 0.0);
+  for (int d = 0; d < n_det; ++d) {
+    const double* vd = Vr.data() + (size_t)d * nt * M;
+    for (int g = 0; g < G; ++g) {
+      const double* Lg = L_chol + (size_t)g * M * M;
+      for (int c = 0; c < nt; ++c) {
+        double* dst = Lh.data() + (((size_t)d * G + g) * nt + c) * M;
+        const double* vc = vd + (size_t)c * M;
+        for (int q = 0; q < M; ++q) {
+          const double a = vc[q];
+          if (a == 0.0) continue;
+          const double* row = Lg + (size_t)q * M;
+          for (int j = 0; j < M; ++j) dst[j] += a * row[j];
+        }
       }
     }
+    double* hd = ht.data() + (size_t)d * nt * M;
+    for (int c = 0; c < nt; ++c)
+      for (int q = 0; q < M; ++q) {
+        const double a = vd[(size_t)c * M + q];
+        for (int j = 0; j < M; ++j) hd[(size_t)c * M + j] += a * h1[(size_t)q * M + j];
+      }
   }
-  for (int c = 0; c < nt; ++c)
-    for (int q = 0; q < M; ++q) {
-      const double a = Vr[(size_t)c * M + q];
-      for (int j = 0; j < M; ++j) ht[(size_t)c * M + j] += a * h1[(size_t)q * M + j];
-    }
 
   // E_HF = E_L(Phi_T, Phi_T): Theta_s = V_s (V_s^T V_s)^{-1} (real), then eq:localenergy3;
-  // tvec[g] = <L_g>_T are the trial's traces.
+  // tvec[g] = <L_g>_T are the trial's traces.  A multi-determinant trial takes both from its
+  // leading determinant (the first block of Vr, Lh, ht).
   std::vector<double> tvec;
   {
     std::vector<double> th((size_t)nt * M, 0.0);  // rows of Theta^T
@@ -608,12 +650,17 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
   // Closed shell: keep only the up block; spin-summed quantities are counted twice.
   int nup_i = nup, ndn_i = ndn;
   if (p->flags & AFQMC_FLAG_CLOSED_SHELL) {
-    std::vector<double> Lh1((size_t)G * nup * M), ht1((size_t)nup * M), V1((size_t)nup * M);
-    for (int g = 0; g < G; ++g)
-      memcpy(Lh1.data() + (size_t)g * nup * M, Lh.data() + (size_t)g * nt * M,
+    std::vector<double> Lh1((size_t)n_det * G * nup * M), ht1((size_t)n_det * nup * M),
+        V1((size_t)n_det * nup * M);
+    for (int d = 0; d < n_det; ++d) {
+      for (int g = 0; g < G; ++g)
+        memcpy(Lh1.data() + ((size_t)d * G + g) * nup * M, Lh.data() + ((size_t)d * G + g) * nt * M,
+               sizeof(double) * (size_t)nup * M);
+      memcpy(ht1.data() + (size_t)d * nup * M, ht.data() + (size_t)d * nt * M,
              sizeof(double) * (size_t)nup * M);
-    memcpy(ht1.data(), ht.data(), sizeof(double) * (size_t)nup * M);
-    memcpy(V1.data(), Vr.data(), sizeof(double) * (size_t)nup * M);
+      memcpy(V1.data() + (size_t)d * nup * M, Vr.data() + (size_t)d * nt * M,
+             sizeof(double) * (size_t)nup * M);
+    }
     Lh.swap(Lh1);
     ht.swap(ht1);
     Vr.swap(V1);
@@ -622,12 +669,11 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
     S->ntot = nup;
     S->sf = 2;
   }
-  const int nt_i = S->ntot;
 
   int rc;
   if ((rc = dev_upload(S, &S->L, G ? L_chol : nullptr, (size_t)G * M * M)) ||
       (rc = dev_upload(S, &S->Eh, Eh.data(), (size_t)M * M)) ||
-      (rc = dev_upload(S, &S->V, Vr.data(), (size_t)nt_i * M)) ||
+      (rc = dev_upload(S, &S->V, Vr.data(), Vr.size())) ||
       (rc = dev_upload(S, &S->lbar, lb.data(), lb.size())) ||
       (rc = dev_upload(S, &S->Lh, Lh.data(), Lh.size())) ||
       (rc = dev_upload(S, &S->ht, ht.data(), ht.size())) ||
@@ -639,14 +685,23 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
     free_sys(S);
     return AFQMC_E_HIP;
   }
+  if (multi) {
+    S->multi = true;
+    S->n_det = n_det;
+    if ((rc = dev_upload(S, &S->coef, coeffs, (size_t)2 * n_det))) {
+      free_sys(S);
+      return rc;
+    }
+  }
   {
     const bool fits = std::max(nup_i, ndn_i) <= 32 && M <= MFMA_KMAX && gj_lds_bytes(S) <= 150 * 1024;
-    if (!fits && p->precision != AFQMC_FP64) {
+    // the mixed-precision modes and the multi-determinant trial run on the MFMA kernels only
+    if (!fits && (p->precision != AFQMC_FP64 || multi)) {
       free_sys(S);
       return AFQMC_E_UNSUPPORTED;
     }
     if (fits) {
-      rc = mfma_build_tables(S->mt, p->precision, M, nup_i, ndn_i, G, Lh.data());
+      rc = mfma_build_tables(S->mt, p->precision, M, nup_i, ndn_i, G, Lh.data(), n_det);
       if (rc != AFQMC_OK) {
         free_sys(S);
         return rc;
@@ -669,6 +724,22 @@ int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double
   }
   *out = S;
   return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int afqmc_setup(const afqmc_params* p, double h0, const double* h1, const double* L_chol,
+                const double* phi_up, const double* phi_dn, void* stream, afqmc_sys* out) {
+  return setup_impl(p, h0, h1, L_chol, 1, nullptr, phi_up, phi_dn, stream, out);
+}
+
+int afqmc_setup_multidet(const afqmc_params* p, double h0, const double* h1, const double* L_chol,
+                         int32_t n_det, const double* coeffs, const double* phi_up,
+                         const double* phi_dn, void* stream, afqmc_sys* out) {
+  if (!coeffs) return AFQMC_E_ARG;
+  return setup_impl(p, h0, h1, L_chol, n_det, coeffs, phi_up, phi_dn, stream, out);
 }
 
 int afqmc_workspace_bytes(afqmc_sys s, int32_t n_walkers, size_t* bytes) {
@@ -793,8 +864,9 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
                      : (s->p.flags & AFQMC_FLAG_HYBRID) ? 1 : 0;
     hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, s->stream, nw, mode,
                        (double)s->sf, s->p.dtau, s->h0p, s->e_trial,
-                       sqrt(s->p.el_cap_C / s->p.dtau), wmax, at<cd>(ws, L.logdet),
-                       at<unsigned>(ws, L.wflag), at<cd>(ws, L.enew),
+                       sqrt(s->p.el_cap_C / s->p.dtau), wmax,
+                       at<cd>(ws, s->multi ? L.ldc : L.logdet),
+                       at<unsigned>(ws, s->multi ? L.wflc : L.wflag), at<cd>(ws, L.enew),
                        mode ? at<cd>(ws, L.fbterm) : nullptr,
                        (s->p.flags & AFQMC_FLAG_MEAN_FIELD) ? at<cd>(ws, L.mfterm) : nullptr,
                        (s->G + 3) / 4,

@@ -25,16 +25,18 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
     const void* __restrict__ thp_, const double* __restrict__ weight, cd* __restrict__ tpart,
     cd* __restrict__ exch) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int s = blockIdx.y;
+  // blockIdx.y = 2 d + s: determinant d of the trial, spin s
+  const int s = blockIdx.y & 1, dd = blockIdx.y >> 1, n_det = gridDim.y >> 1;
   const int N = s ? ndn : nup;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int w = blockIdx.x * MFMA_WAVES + wave;
+  const int wd = w * n_det + dd;   // (walker, determinant) slot of the outputs
   const bool active = (w < nw) && (N > 0) && (weight[w] > 0.0);
   if (N == 0) {
     if (w < nw) {
-      for (int g = lane; g < G; g += 64) tpart[((size_t)w * 2 + s) * G + g] = mkc(0.0, 0.0);
-      if (lane == 0) exch[2 * w + s] = mkc(0.0, 0.0);
+      for (int g = lane; g < G; g += 64) tpart[((size_t)wd * 2 + s) * G + g] = mkc(0.0, 0.0);
+      if (lane == 0) exch[2 * wd + s] = mkc(0.0, 0.0);
     }
     return;
   }
@@ -52,7 +54,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
   float* ep_im = ep + NP * LDE;
 
   const unsigned char* Lbase =
-      reinterpret_cast<const unsigned char*>(Lp_) + (size_t)s * G * tile_elems * ESZ;
+      reinterpret_cast<const unsigned char*>(Lp_) + ((size_t)dd * 2 + s) * G * tile_elems * ESZ;
 
   // ---- copy of one g-tile global -> LDS, 16 bytes per thread per chunk
   const int chunks_per_row = KP * ESZ / 16;
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
   if (active) {
     const size_t per = (size_t)NP * KP;
     const unsigned char* tb = reinterpret_cast<const unsigned char*>(thp_) +
-                              ((size_t)w * 2 + s) * 2 * PLANES * per * ESZ;
+                              ((size_t)wd * 2 + s) * 2 * PLANES * per * ESZ;
 #pragma unroll
     for (int c = 0; c < MAXK; ++c) {
       if (c < nk) {
@@ -245,7 +247,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
       else if (lane < 2 * NP) d = ep_im[(lane - NP) * LDE + (lane - NP)];
 #pragma unroll
       for (int o = NP / 2; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-      double* tp = reinterpret_cast<double*>(tpart + ((size_t)w * 2 + s) * G + g);
+      double* tp = reinterpret_cast<double*>(tpart + ((size_t)wd * 2 + s) * G + g);
       if (lane == 0) tp[0] = (double)d;
       if (lane == NP) tp[1] = (double)d;
     }
@@ -255,7 +257,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
   if (active) {
     xr = wave_sum(xr);
     xi = wave_sum(xi);
-    if (lane == 0) exch[2 * w + s] = mkc(xr, xi);
+    if (lane == 0) exch[2 * wd + s] = mkc(xr, xi);
   }
 #undef AFQMC_GLOAD
 #undef AFQMC_LSTORE

@@ -262,6 +262,102 @@ __global__ void __launch_bounds__(256) k_energy_assemble(
   }
 }
 
+// Multi-determinant trial Psi_T = sum_d A_d Psi_d (Sec. II.B, eq:localenergy2, eq:precomputing2).
+// Per (walker, determinant) slot wd = w * n_det + d the overlap and contraction kernels have
+// left logdet, wflag, e1, tpart and exch of determinant d.  With
+//   r_d = conj(A_d) <Psi_d|Psi> / e^{ref},  ref = max_d log|<Psi_d|Psi>|,  R = sum_d r_d,
+// this kernel forms the mixed local energy E_L = sum_d r_d E_L^d / R, the force-bias traces
+// t_g = sum_d r_d t^d_g / R and log <Psi_T|Psi> = log R + ref.  Determinants with an exactly
+// singular overlap matrix have r_d = 0 and are skipped (their energy term is dropped, exact only
+// for walkers non-orthogonal to every determinant).  The combined log-overlap is written as a
+// spin pair (log/sf, 0) so that sf * first + second reproduces it in the weight kernels; a walker
+// with no usable determinant (or R = 0) is flagged singular.  One block per walker.
+constexpr int AFQMC_MAX_DETS = 1024;
+__global__ void __launch_bounds__(256) k_energy_assemble_multi(
+    int G, int n_det, double h0, double sf, const double* __restrict__ coef /*[n_det][2]*/,
+    const cd* __restrict__ tpart, const cd* __restrict__ exch, const cd* __restrict__ e1,
+    const cd* __restrict__ logdet, const unsigned* __restrict__ wflag,
+    const double* __restrict__ weight, int check_weight, cd* __restrict__ tcur /*[nw][G]*/,
+    cd* __restrict__ enew /*[nw]*/, cd* __restrict__ ldc /*[nw][2]*/,
+    unsigned* __restrict__ wflc /*[nw][2]*/) {
+  __shared__ double red[8];
+  __shared__ cd s_r[AFQMC_MAX_DETS];    // r_d / R
+  __shared__ cd s_lg[AFQMC_MAX_DETS];   // log <Psi_d|Psi>
+  __shared__ int s_ok[AFQMC_MAX_DETS];
+  __shared__ cd s_esum;
+  __shared__ int s_bad, s_first;
+  const int w = blockIdx.x, tid = threadIdx.x;
+  if (check_weight && !(weight[w] > 0.0)) return;
+  for (int d = tid; d < n_det; d += blockDim.x) {
+    const size_t wd = (size_t)w * n_det + d;
+    const cd l0 = logdet[2 * wd], l1 = logdet[2 * wd + 1];
+    const unsigned fl = wflag[2 * wd] | wflag[2 * wd + 1];
+    s_lg[d] = mkc(sf * l0.re + l1.re, sf * l0.im + l1.im);
+    s_ok[d] = (fl & WFLAG_SINGULAR) ? 0 : 1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ref = -INFINITY;
+    int first = -1;
+    for (int d = 0; d < n_det; ++d)
+      if (s_ok[d]) {
+        ref = fmax(ref, s_lg[d].re);
+        if (first < 0) first = d;
+      }
+    s_first = first;
+    cd R = mkc(0.0, 0.0);
+    for (int d = 0; d < n_det; ++d) {
+      cd r = mkc(0.0, 0.0);
+      if (s_ok[d]) {
+        const double m = exp(s_lg[d].re - ref);
+        // conj(A_d) * e^{lg - ref}
+        r = cconjmul(mkc(coef[2 * d], coef[2 * d + 1]), mkc(m * cos(s_lg[d].im), m * sin(s_lg[d].im)));
+      }
+      s_r[d] = r;
+      R = cadd(R, r);
+    }
+    const bool bad = !(ref > -INFINITY) || !(R.re != 0.0 || R.im != 0.0) || !cfinite(R);
+    s_bad = bad ? 1 : 0;
+    if (!bad) {
+      for (int d = 0; d < n_det; ++d) s_r[d] = cdiv(s_r[d], R);
+      const double lre = log(sqrt(R.re * R.re + R.im * R.im)) + ref;
+      const double lim = atan2(R.im, R.re);
+      ldc[2 * w] = mkc(lre / sf, lim / sf);
+    } else {
+      ldc[2 * w] = mkc(-INFINITY, 0.0);
+    }
+    ldc[2 * w + 1] = mkc(0.0, 0.0);
+    wflc[2 * w] = bad ? WFLAG_SINGULAR : 0u;
+    wflc[2 * w + 1] = 0u;
+    s_esum = mkc(0.0, 0.0);
+  }
+  __syncthreads();
+  if (s_bad) return;
+  for (int d = 0; d < n_det; ++d) {
+    if (!s_ok[d]) continue;  // uniform over the block
+    const size_t wd = (size_t)w * n_det + d;
+    const cd rd = s_r[d];
+    double jr = 0.0, ji = 0.0;
+    for (int g = tid; g < G; g += blockDim.x) {
+      const cd t = cadd(cscale(tpart[(wd * 2) * G + g], sf), tpart[(wd * 2 + 1) * G + g]);
+      const cd c = cmul(rd, t);
+      // the first usable determinant writes, later ones accumulate (same thread owns g)
+      tcur[(size_t)w * G + g] = (d == s_first) ? c : cadd(tcur[(size_t)w * G + g], c);
+      jr += t.re * t.re - t.im * t.im;
+      ji += 2.0 * t.re * t.im;
+    }
+    jr = block_sum(jr, red);
+    ji = block_sum(ji, red);
+    if (tid == 0) {
+      const cd x = cadd(cscale(exch[2 * wd], sf), exch[2 * wd + 1]);
+      const cd e = cadd(cscale(e1[2 * wd], sf), e1[2 * wd + 1]);
+      const cd ed = mkc(h0 + e.re + 0.5 * (jr - x.re), e.im + 0.5 * (ji - x.im));
+      s_esum = cadd(s_esum, cmul(rd, ed));
+    }
+  }
+  if (tid == 0) enew[w] = s_esum;
+}
+
 // ---------------------------------------------------------------------------
 // Auxiliary fields and force bias (eq:hs2, eq:fb, eq:precomputing2, App. B.1):
 // x from the Philox stream (or given), xbar = -i s t capped in modulus,

@@ -41,7 +41,7 @@ constexpr int MFMA_WAVES = 4;
 struct MfmaTables {
   bool enabled = false;
   int precision = 0;  // AFQMC_FP64, AFQMC_FP32 or AFQMC_BF16X3
-  int NP = 0, KP = 0, M = 0, G = 0, nup = 0, ndn = 0;
+  int NP = 0, KP = 0, M = 0, G = 0, nup = 0, ndn = 0, n_det = 1;
   void* Lp = nullptr;  // fp64 / fp32: [2][G][NP][KP]; bf16x3: [2][G][2 (hi, lo)][NP][KP] bf16 bits
   size_t bytes = 0;
 };
@@ -64,11 +64,11 @@ __host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
 inline size_t mfma_theta_bytes(const MfmaTables& t, size_t nw) {
   if (!t.enabled) return 0;
   // fp32 re/im, or bf16 re/im x hi/lo (same bytes); fp64 re/im
-  return nw * 2 * 2 * (size_t)t.NP * t.KP * (t.precision == AFQMC_FP64 ? 8 : 4);
+  return nw * (size_t)t.n_det * 2 * 2 * (size_t)t.NP * t.KP * (t.precision == AFQMC_FP64 ? 8 : 4);
 }
 
 inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int ndn, int G,
-                             const double* Lh /* host [G][nup+ndn][M] */) {
+                             const double* Lh /* host [n_det][G][nup+ndn][M] */, int n_det = 1) {
   const int nmax = nup > ndn ? nup : ndn;
   if (nmax > 32 || M > MFMA_KMAX) return AFQMC_E_UNSUPPORTED;
   t.precision = precision;
@@ -80,42 +80,47 @@ inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int n
   t.ndn = ndn;
   const int nt = nup + ndn;
   const size_t per = (size_t)t.NP * t.KP;
+  t.n_det = n_det;
   if (precision == AFQMC_FP64) {
-    std::vector<double> h((size_t)2 * G * per + 2, 0.0);
+    std::vector<double> h((size_t)n_det * 2 * G * per + 2, 0.0);
+    for (int d = 0; d < n_det; ++d)
     for (int s = 0; s < 2; ++s) {
       const int N = s ? ndn : nup, off = s ? nup : 0;
       for (int g = 0; g < G; ++g)
         for (int r = 0; r < N; ++r)
           for (int p = 0; p < M; ++p)
-            h[((size_t)s * G + g) * per + (size_t)r * t.KP + p] = Lh[((size_t)g * nt + off + r) * M + p];
+            h[(((size_t)d * 2 + s) * G + g) * per + (size_t)r * t.KP + p] =
+                Lh[(((size_t)d * G + g) * nt + off + r) * M + p];
     }
     t.bytes = h.size() * sizeof(double);
     if (hipMalloc(&t.Lp, t.bytes) != hipSuccess) return AFQMC_E_NOMEM;
     if (hipMemcpy(t.Lp, h.data(), t.bytes, hipMemcpyHostToDevice) != hipSuccess) return AFQMC_E_HIP;
   } else if (precision == AFQMC_FP32) {
-    std::vector<float> h((size_t)2 * G * per + 1, 0.0f);
+    std::vector<float> h((size_t)n_det * 2 * G * per + 1, 0.0f);
+    for (int d = 0; d < n_det; ++d)
     for (int s = 0; s < 2; ++s) {
       const int N = s ? ndn : nup, off = s ? nup : 0;
       for (int g = 0; g < G; ++g)
         for (int r = 0; r < N; ++r)
           for (int p = 0; p < M; ++p)
-            h[((size_t)s * G + g) * per + (size_t)r * t.KP + p] =
-                (float)Lh[((size_t)g * nt + off + r) * M + p];
+            h[(((size_t)d * 2 + s) * G + g) * per + (size_t)r * t.KP + p] =
+                (float)Lh[(((size_t)d * G + g) * nt + off + r) * M + p];
     }
     t.bytes = h.size() * sizeof(float);
     if (hipMalloc(&t.Lp, t.bytes) != hipSuccess) return AFQMC_E_NOMEM;
     if (hipMemcpy(t.Lp, h.data(), t.bytes, hipMemcpyHostToDevice) != hipSuccess) return AFQMC_E_HIP;
   } else if (precision == AFQMC_BF16X3) {
-    std::vector<uint16_t> h((size_t)2 * G * 2 * per + 2, 0);
+    std::vector<uint16_t> h((size_t)n_det * 2 * G * 2 * per + 2, 0);
+    for (int d = 0; d < n_det; ++d)
     for (int s = 0; s < 2; ++s) {
       const int N = s ? ndn : nup, off = s ? nup : 0;
       for (int g = 0; g < G; ++g)
         for (int r = 0; r < N; ++r)
           for (int p = 0; p < M; ++p) {
-            const float x = (float)Lh[((size_t)g * nt + off + r) * M + p];
+            const float x = (float)Lh[(((size_t)d * G + g) * nt + off + r) * M + p];
             const uint16_t hi = f32_to_bf16_bits(x);
             const uint16_t lo = f32_to_bf16_bits(x - bf16_bits_to_f32(hi));
-            const size_t base = (((size_t)s * G + g) * 2) * per + (size_t)r * t.KP + p;
+            const size_t base = ((((size_t)d * 2 + s) * G + g) * 2) * per + (size_t)r * t.KP + p;
             h[base] = hi;
             h[base + per] = lo;
           }
@@ -171,16 +176,18 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
   constexpr int KMAX = MFMA_KMAX;
   constexpr int NCH = KMAX / 8;               // K chunks of 8 held per lane as 4 x f64x2
   constexpr int LDE = NP + 1;
-  const int s = blockIdx.y;
+  const int s = blockIdx.y & 1, d = blockIdx.y >> 1, n_det = gridDim.y >> 1;
   const int N = s ? ndn : nup;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int pair = wave >> 1, part = wave & 1;  // part 0: Re Theta, 1: Im Theta
   const int w = blockIdx.x * 2 + pair;
+  const int wd = w * n_det + d;                 // (walker, determinant) slot of the outputs
+  Lp += (size_t)d * 2 * G * NP * KP;
   if (N == 0) {
     if (w < nw && part == 0) {
-      for (int g = lane; g < G; g += 64) tpart[((size_t)w * 2 + s) * G + g] = mkc(0.0, 0.0);
-      if (lane == 0) exch[2 * w + s] = mkc(0.0, 0.0);
+      for (int g = lane; g < G; g += 64) tpart[((size_t)wd * 2 + s) * G + g] = mkc(0.0, 0.0);
+      if (lane == 0) exch[2 * wd + s] = mkc(0.0, 0.0);
     }
     return;
   }
@@ -196,7 +203,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
   // B operand: lane holds Theta_part[16 b + j16][8 c + 2 q + {0, 1}]
   f64x2 breg[NB][NCH];
   if (active) {
-    const double* tb = thp + (((size_t)w * 2 + s) * 2 + part) * NP * KP;
+    const double* tb = thp + (((size_t)wd * 2 + s) * 2 + part) * NP * KP;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -291,10 +298,10 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
             }
           }
       xacc += pr;
-      double d = 0.0;
-      if (lane < NP) d = part ? epI[lane * LDE + lane] : epR[lane * LDE + lane];
-      d = wave_sum(d);
-      if (lane == 0) reinterpret_cast<double*>(tpart + ((size_t)w * 2 + s) * G + g)[part] = d;
+      double dg = 0.0;
+      if (lane < NP) dg = part ? epI[lane * LDE + lane] : epR[lane * LDE + lane];
+      dg = wave_sum(dg);
+      if (lane == 0) reinterpret_cast<double*>(tpart + ((size_t)wd * 2 + s) * G + g)[part] = dg;
     }
     if (g + 2 < G) F64_GLOAD(g + 2);
     __syncthreads();
@@ -303,7 +310,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
 #undef F64_LSTORE
   if (active) {
     xacc = wave_sum(xacc);
-    if (lane == 0) reinterpret_cast<double*>(exch + 2 * w + s)[part] = xacc;
+    if (lane == 0) reinterpret_cast<double*>(exch + 2 * wd + s)[part] = xacc;
   }
 }
 
@@ -311,11 +318,11 @@ inline size_t mfma_f64_contract_lds_bytes(const MfmaTables& t) {
   return ((size_t)t.NP * (t.KP + 2) + (size_t)2 * 2 * t.NP * (t.NP + 1)) * 8;
 }
 
-inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int G,
+inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int n_det, int G,
                                 const void* thetaP, const double* weight, cd* tpart, cd* exch) {
   if (t.precision == AFQMC_FP64) {
     const size_t shm = mfma_f64_contract_lds_bytes(t);
-    dim3 grid((nw + 1) / 2, 2);
+    dim3 grid((nw + 1) / 2, 2 * n_det);
     if (t.NP == 32) {
       (void)hipFuncSetAttribute((const void*)k_contract_f64mfma<32>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -330,7 +337,7 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
     return hipGetLastError();
   }
   const size_t shm = mfma_contract_lds_bytes(t);
-  dim3 grid((nw + MFMA_WAVES - 1) / MFMA_WAVES, 2);
+  dim3 grid((nw + MFMA_WAVES - 1) / MFMA_WAVES, 2 * n_det);
   const bool bf = t.precision == AFQMC_BF16X3;
 #define LAUNCH_CONTRACT(NPV, BFV)                                                               \
   do {                                                                                          \
@@ -369,6 +376,12 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
     unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   constexpr int NB = NPAD / 16;
+  // determinant d of the trial (blockIdx.z); per-determinant outputs are indexed by
+  // wd = w * n_det + d, and the trial arrays V, ht are offset to determinant d.
+  const int d = blockIdx.z, n_det = gridDim.z;
+  const int wd_ = blockIdx.x * n_det + d;
+  V += (size_t)d * (nup + ndn) * M;
+  ht += (size_t)d * (nup + ndn) * M;
   const int w = blockIdx.x, s = blockIdx.y;
   const int N = s == 0 ? nup : ndn;
   const int off = s == 0 ? 0 : nup;
@@ -377,9 +390,9 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (N == 0) {
     if (tid == 0) {
-      logdet[2 * w + s] = mkc(0.0, 0.0);
-      e1[2 * w + s] = mkc(0.0, 0.0);
-      wflag[2 * w + s] = 0u;
+      logdet[2 * wd_ + s] = mkc(0.0, 0.0);
+      e1[2 * wd_ + s] = mkc(0.0, 0.0);
+      wflag[2 * wd_ + s] = 0u;
     }
     return;
   }
@@ -481,20 +494,20 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
   }
   if (s_sing) {
     if (tid == 0) {
-      wflag[2 * w + s] = WFLAG_SINGULAR;
-      logdet[2 * w + s] = mkc(-INFINITY, 0.0);
-      e1[2 * w + s] = mkc(0.0, 0.0);
+      wflag[2 * wd_ + s] = WFLAG_SINGULAR;
+      logdet[2 * wd_ + s] = mkc(-INFINITY, 0.0);
+      e1[2 * wd_ + s] = mkc(0.0, 0.0);
     }
     return;
   }
   if (tid == 0) {
-    logdet[2 * w + s] = mkc(s_la, s_ar + M_PI * (double)(s_nswap & 1));
-    wflag[2 * w + s] = 0u;
+    logdet[2 * wd_ + s] = mkc(s_la, s_ar + M_PI * (double)(s_nswap & 1));
+    wflag[2 * wd_ + s] = 0u;
   }
   // ---- Theta^T[c][p] = sum_j Tinv[j][c] U^T[j][p] on MFMA (K = j, padded to NPAD)
   const int CB = (M + 15) / 16;
   const size_t per = (size_t)NP * KP;
-  cd* Tw = thetaT + ((size_t)w * ntot + off) * M;
+  cd* Tw = thetaT + ((size_t)wd_ * ntot + off) * M;
   const double* hts = ht + (size_t)off * M;
   double e1re = 0.0, e1im = 0.0;
   for (int t = wave; t < NB * CB; t += 4) {
@@ -522,15 +535,15 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       e1re = fma(hv, th.re, e1re);
       e1im = fma(hv, th.im, e1im);
       if (packed_kind == 3) {
-        double* o = reinterpret_cast<double*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
+        double* o = reinterpret_cast<double*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
         o[0] = th.re;
         o[per] = th.im;
       } else if (packed_kind == 1) {
-        float* o = reinterpret_cast<float*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
+        float* o = reinterpret_cast<float*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
         o[0] = (float)th.re;
         o[per] = (float)th.im;
       } else if (packed_kind == 2) {
-        uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)w * 2 + s) * 4 * per + (size_t)c * KP + p;
+        uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)wd_ * 2 + s) * 4 * per + (size_t)c * KP + p;
         const float xr = (float)th.re, xi = (float)th.im;
         const uint16_t hr = f32_to_bf16_bits(xr), hi = f32_to_bf16_bits(xi);
         o[0] = hr;
@@ -546,7 +559,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       const int pl = (int)(e / per);
       const int c = (int)((e % per) / KP), p = (int)(e % KP);
       if (c < N && p < M) continue;
-      const size_t o = ((size_t)w * 2 + s) * planes * per + (size_t)pl * per + (size_t)c * KP + p;
+      const size_t o = ((size_t)wd_ * 2 + s) * planes * per + (size_t)pl * per + (size_t)c * KP + p;
       if (packed_kind == 3) reinterpret_cast<double*>(packed)[o] = 0.0;
       else if (packed_kind == 1) reinterpret_cast<float*>(packed)[o] = 0.f;
       else reinterpret_cast<uint16_t*>(packed)[o] = 0;
@@ -554,5 +567,5 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
   }
   e1re = block_sum(e1re, red);
   e1im = block_sum(e1im, red);
-  if (tid == 0) e1[2 * w + s] = mkc(e1re, e1im);
+  if (tid == 0) e1[2 * wd_ + s] = mkc(e1re, e1im);
 }

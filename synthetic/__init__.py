@@ -24,3 +24,4 @@ from .fields import (  # noqa: F401
     philox_u64,
     u64_to_unit,
 )
+from .trials import excitation_trial, noci_trial, occupation_det  # noqa: F401

@@ -49,6 +49,29 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.afqmc_workspace_bytes(None, 4, C.byref(b)) == -1
 
 
+def test_multidet_argument_checks_precede_device_work():
+    """n_det outside 1..1024, a missing or non-finite coefficient array are argument errors."""
+    import numpy as np
+    lib = pkg.load()
+    M, n = 4, 1
+    p = pkg._lib.Params(M=M, n_up=n, n_dn=n, n_chol=0, dtau=0.01, e_trial=float("nan"),
+                        n_taylor=6, qr_period=5, pop_period=5, precision=0, el_cap_C=2.0,
+                        w_max=float("nan"), fb_cap=1.0, flags=0, reserved=0)
+    h1 = np.eye(M)
+    phi = np.zeros((2, M, n))
+    phi[:, 0, 0] = 1.0
+    out = C.c_void_p()
+    ok_coef = np.array([1.0, 0.0, 0.5, 0.0])
+    bad_coef = np.array([1.0, 0.0, np.nan, 0.0])
+    args = lambda nd, cf: (C.byref(p), 0.0, h1.ctypes.data, None, nd, cf, phi.ctypes.data,
+                           phi.ctypes.data, None, C.byref(out))
+    assert lib.afqmc_setup_multidet(*args(2, None)) == -1
+    assert lib.afqmc_setup_multidet(*args(0, ok_coef.ctypes.data)) == -1
+    assert lib.afqmc_setup_multidet(*args(1025, ok_coef.ctypes.data)) == -1
+    assert lib.afqmc_setup_multidet(*args(2, bad_coef.ctypes.data)) == -1
+    assert out.value is None
+
+
 def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "probe.c"
     src.write_text(r"""

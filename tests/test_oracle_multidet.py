@@ -9,62 +9,7 @@ import pytest
 from oracle import afqmc as A
 from oracle import fock as F
 from synthetic import config_system, random_walkers
-
-
-def occ_det(M, occ):
-    V = np.zeros((M, len(occ)))
-    for j, p in enumerate(occ):
-        V[p, j] = 1.0
-    return V
-
-
-def noci_trial(s, n_det, seed, angle=0.4):
-    """Non-orthogonal determinants: the lowest orbitals rotated into the virtual space by
-    random angles (every pair of determinants overlaps)."""
-    rng = np.random.default_rng(seed)
-    _, C = np.linalg.eigh(s.h1)
-    N, M = s.n_up, s.M
-    ups, dns = [], []
-    for d in range(n_det):
-        K = np.zeros((M, M))
-        if d > 0:
-            X = angle * rng.standard_normal((M - N, N)) / np.sqrt(N)
-            K[N:, :N] = X
-            K[:N, N:] = -X.T
-        import scipy.linalg
-        R = scipy.linalg.expm(K)
-        ups.append(C @ R[:, :N])
-        K2 = np.zeros((M, M))
-        if d > 0:
-            X = angle * rng.standard_normal((M - N, N)) / np.sqrt(N)
-            K2[N:, :N] = X
-            K2[:N, N:] = -X.T
-        dns.append(C @ scipy.linalg.expm(K2)[:, :N])
-    coeffs = np.concatenate([[1.0], 0.4 * rng.standard_normal(n_det - 1)]) + 0j
-    return coeffs, ups, dns
-
-
-def excitation_trial(s, n_det, seed):
-    """The lowest determinant of h1's eigenbasis plus excitations, with random coefficients;
-    every determinant is built from the eigenvectors (the molecular orbitals)."""
-    rng = np.random.default_rng(seed)
-    _, C = np.linalg.eigh(s.h1)
-    N = s.n_up
-    occs = [list(range(N))]
-    cands = []
-    for i in range(N):
-        for a in range(N, s.M):
-            occ = list(range(N))
-            occ[i] = a
-            cands.append(sorted(occ))
-    rng.shuffle(cands)
-    ups, dns = [C[:, occs[0]]], [C[:, occs[0]]]
-    for k in range(n_det - 1):
-        ups.append(C[:, cands[k]])
-        dns.append(C[:, cands[(k + 3) % len(cands)]])
-    coeffs = np.concatenate([[1.0], 0.3 * rng.standard_normal(n_det - 1)]) + 0j
-    coeffs[1:] += 0.1j * rng.standard_normal(n_det - 1)
-    return coeffs, ups, dns
+from synthetic import excitation_trial, noci_trial, occupation_det as occ_det
 
 
 @pytest.fixture(scope="module")
