@@ -275,67 +275,32 @@ int check_walkers(const afqmc_sys_s* S, const afqmc_walkers* w) {
   return AFQMC_OK;
 }
 
-size_t gj_lds_bytes(const afqmc_sys_s* S) {
-  const size_t N = std::max(S->nup, S->ndn), M = S->M;
-  return N * (M + 1) * 16 + N * (2 * N + 1) * 16 + N * 16 + 64;
-}
-
 int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, int check_weight) {
   Timer tm(S, KG_OVERLAP);
   const int nmax = std::max(S->nup, S->ndn);
-  dim3 grid(w->n_walkers, 2, S->n_det);  // only k_overlap_mfma reads blockIdx.z (n_det > 1 needs it)
+  // one workgroup per (walker, spin, determinant); only the Gauss-Jordan matrix sits in LDS
+  dim3 grid(w->n_walkers, 2, S->n_det);
   void* ws = w->workspace;
-  void* packed0 = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
-  const int kind0 = !S->mt.enabled ? 0
-                    : S->mt.precision == AFQMC_FP64 ? 3
-                    : S->mt.precision == AFQMC_BF16X3 ? 2 : 1;
-  if (nmax <= 32) {
-    const size_t shm = (size_t)nmax * (2 * nmax + 1) * 16 + (size_t)nmax * 16 + 64;
-    if (nmax <= 16)
-      hipLaunchKernelGGL(k_overlap_mfma<16>, grid, dim3(256), shm, S->stream, S->M, S->nup, S->ndn,
-                         S->V, S->ht, (const cd*)w->U, w->weight, check_weight, at<cd>(ws, L.thetaT),
-                         at<cd>(ws, L.logdet), at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed0,
-                         kind0, S->mt.NP, S->mt.KP);
-    else
-      hipLaunchKernelGGL(k_overlap_mfma<32>, grid, dim3(256), shm, S->stream, S->M, S->nup, S->ndn,
-                         S->V, S->ht, (const cd*)w->U, w->weight, check_weight, at<cd>(ws, L.thetaT),
-                         at<cd>(ws, L.logdet), at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed0,
-                         kind0, S->mt.NP, S->mt.KP);
-    HIPCHK(hipGetLastError());
-    return AFQMC_OK;
-  }
-  const size_t gj = gj_lds_bytes(S);
-  if (gj <= 150 * 1024) {
-    (void)hipFuncSetAttribute((const void*)k_overlap_gj, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)gj);
-    void* packed = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
-    const int kind = !S->mt.enabled ? 0
-                     : S->mt.precision == AFQMC_FP64 ? 3
-                     : S->mt.precision == AFQMC_BF16X3 ? 2 : 1;
-    hipLaunchKernelGGL(k_overlap_gj, grid, dim3(256), gj, S->stream, S->M, S->nup, S->ndn, S->V,
-                       S->ht, (const cd*)w->U, w->weight, check_weight, at<cd>(ws, L.thetaT),
-                       at<cd>(ws, L.logdet), at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed,
-                       kind, S->mt.NP, S->mt.KP);
-    HIPCHK(hipGetLastError());
-    return AFQMC_OK;
-  }
-  if (S->mt.enabled) return AFQMC_E_UNSUPPORTED;  // the MFMA operand is packed by k_overlap_gj only
-  const size_t shm = (size_t)nmax * (nmax + 1) * 16 + 64 * 4 + 8 * 8;
-#define OVL(NM)                                                                                \
+  void* packed = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
+  const int kind = !S->mt.enabled ? 0
+                   : S->mt.precision == AFQMC_FP64 ? 3
+                   : S->mt.precision == AFQMC_BF16X3 ? 2 : 1;
+  const size_t shm = (size_t)nmax * (2 * nmax + 1) * 16 + (size_t)nmax * 16 + 64;
+#define OVL(NPAD)                                                                              \
   do {                                                                                         \
-    (void)hipFuncSetAttribute((const void*)k_overlap_theta<NM>,                                \
+    (void)hipFuncSetAttribute((const void*)k_overlap_mfma<NPAD>,                               \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
-    hipLaunchKernelGGL(k_overlap_theta<NM>, grid, dim3(256), shm, S->stream, S->M, S->nup,      \
+    hipLaunchKernelGGL(k_overlap_mfma<NPAD>, grid, dim3(256), shm, S->stream, S->M, S->nup,     \
                        S->ndn, S->V, S->ht, (const cd*)w->U, w->weight, check_weight,          \
                        at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet), at<cd>(ws, L.e1),           \
-                       at<unsigned>(ws, L.wflag));                                            \
+                       at<unsigned>(ws, L.wflag), packed, kind, S->mt.NP, S->mt.KP);          \
   } while (0)
-  if (nmax <= 8)
-    OVL(8);
-  else if (nmax <= 16)
+  if (nmax <= 16)
     OVL(16);
   else if (nmax <= 32)
     OVL(32);
+  else if (nmax <= 48)
+    OVL(48);
   else
     OVL(64);
 #undef OVL
@@ -694,22 +659,20 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     }
   }
   {
-    const bool fits = std::max(nup_i, ndn_i) <= 32 && M <= MFMA_KMAX && gj_lds_bytes(S) <= 150 * 1024;
-    // the mixed-precision modes and the multi-determinant trial run on the MFMA kernels only
-    if (!fits && (p->precision != AFQMC_FP64 || multi)) {
+    // MFMA contraction tables; the plain FP64 single-determinant path falls back to the
+    // VALU contraction where no MFMA kernel covers the shape.  The mixed-precision modes and
+    // the multi-determinant trial need the MFMA kernels.
+    rc = mfma_build_tables(S->mt, p->precision, M, nup_i, ndn_i, G, Lh.data(), n_det);
+    if (rc == AFQMC_E_UNSUPPORTED && p->precision == AFQMC_FP64 && !multi) rc = AFQMC_OK;
+    if (rc != AFQMC_OK) {
       free_sys(S);
-      return AFQMC_E_UNSUPPORTED;
+      return rc;
     }
-    if (fits) {
-      rc = mfma_build_tables(S->mt, p->precision, M, nup_i, ndn_i, G, Lh.data(), n_det);
-      if (rc != AFQMC_OK) {
-        free_sys(S);
-        return rc;
-      }
-      S->device_bytes += S->mt.bytes;
-    }
+    if (S->mt.enabled) S->device_bytes += S->mt.bytes;
   }
-  if (p->precision != AFQMC_FP64) {
+  // FP32 A-build and propagation where k_propagate_f32 covers the shape (M <= 128,
+  // N_up + N_dn <= 64); otherwise the FP64 kernels run in every mode.
+  if (p->precision != AFQMC_FP64 && M <= MFMA_KMAX && S->ntot <= 64) {
     S->f32_prop = true;
     S->Gp = ((G + 31) / 32) * 32;
     std::vector<float> lt((size_t)M * M * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);

@@ -1,0 +1,225 @@
+// Wide form of the FP32 / BF16x3 MFMA local-energy contraction (arXiv:1711.02242,
+// Sec. III.D.3, eq:localenergy3; force-bias traces of eq:precomputing2), for the
+// shapes the register-resident kernel of contract_mfma.hpp cannot hold: N up to 64
+// electrons per spin and M up to 224 orbitals.
+//
+// One workgroup owns one (walker, determinant, spin).  Its NPW / 16 wavefronts
+// split the columns of Theta: wave j keeps [Re | Im] Theta[:, 16 j .. 16 j + 15]
+// (K up to 224) in registers for the whole kernel and computes the column block
+// Omega[:, 16 j .. 16 j + 15] = Lh^g Theta[:, block] for every g on
+// v_mfma_f32_16x16x4_f32 (BF16x3: v_mfma_f32_16x16x32_bf16, three products
+// hi*hi + hi*lo + lo*hi).  The Lh^g tiles (NPW x KP) are double-buffered in LDS and
+// shared by the waves; the copy of tile g + 1 is interleaved chunk by chunk with
+// the MFMA chain of tile g (one 16-byte chunk per thread per K chunk, so only one
+// or two chunks are in flight in registers).  Omega is then written column-major to LDS so that each lane reads
+// the partner Omega_ji of every Omega_ij it holds; tr(Omega Omega) is summed per g
+// in FP32 and across g in FP64, and wave 0 / wave 1 form Re / Im tr Omega.
+#pragma once
+
+template <int NPW, bool BF16>
+__global__ void __launch_bounds__(256) k_contract_mfma_wide(
+    int nw, int G, int nup, int ndn, int KP, const void* __restrict__ Lp_,
+    const void* __restrict__ thp_, const double* __restrict__ weight, cd* __restrict__ tpart,
+    cd* __restrict__ exch) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  constexpr int NW = NPW / 16;   // wavefronts = 16-column blocks of Theta
+  constexpr int NR = NPW / 16;   // 16-row tiles of Omega
+  constexpr int NT = 64 * NW;    // threads
+  const int s = blockIdx.y & 1, dd = blockIdx.y >> 1, n_det = gridDim.y >> 1;
+  const int N = s ? ndn : nup;
+  const int w = blockIdx.x;
+  const int wd = w * n_det + dd;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (w >= nw) return;
+  if (N == 0) {
+    for (int g = tid; g < G; g += NT) tpart[((size_t)wd * 2 + s) * G + g] = mkc(0.0, 0.0);
+    if (tid == 0) exch[2 * wd + s] = mkc(0.0, 0.0);
+    return;
+  }
+  if (!(weight[w] > 0.0)) return;  // the whole workgroup is one walker
+
+  constexpr int ESZ = BF16 ? 2 : 4;
+  constexpr int PLANES = BF16 ? 2 : 1;
+  const int lda = KP + (BF16 ? 8 : 4);                  // LDS row stride in elements
+  const size_t tile_elems = (size_t)NPW * KP * PLANES;  // one g in global memory
+  const int tile_lds_bytes = NPW * lda * ESZ * PLANES;
+  constexpr int LDE = NPW + 4;
+  float* ep_re = reinterpret_cast<float*>(smem + 2 * tile_lds_bytes);  // Omega column-major
+  float* ep_im = ep_re + NPW * LDE;
+  double* red = reinterpret_cast<double*>(ep_im + NPW * LDE);         // [2][NW]
+
+  const unsigned char* Lbase =
+      reinterpret_cast<const unsigned char*>(Lp_) + ((size_t)dd * 2 + s) * G * tile_elems * ESZ;
+
+  // Copy of a g-tile in 16-byte chunks: chunk ch = tid + k NT, k < KP / 16 (exactly
+  // NPW * PLANES * KP * ESZ / 16 = (KP / 16) * NT chunks).
+  const int chunks_per_row = KP * ESZ / 16;
+  const int nchunks = NPW * PLANES * chunks_per_row;
+  auto chunk_src = [&](int g, int k) {
+    const int ch = tid + k * NT;
+    return reinterpret_cast<const u32x4*>(Lbase + (size_t)g * tile_elems * ESZ) +
+           (ch < nchunks ? ch : 0);
+  };
+  auto chunk_dst = [&](unsigned char* buf, int k) {
+    const int ch = tid + k * NT;
+    const int row = ch / chunks_per_row, colc = (ch % chunks_per_row) * (16 / ESZ);
+    return reinterpret_cast<u32x4*>(buf + ((size_t)row * lda + colc) * ESZ);
+  };
+
+  // ---- Theta column block into registers (B operand: rows k, column 16 wave + col)
+  constexpr int KCH = BF16 ? 32 : 16;      // K per register chunk (4 lane groups)
+  constexpr int MAXK = WIDE_KMAX / KCH;
+  constexpr int CPK = BF16 ? 2 : 1;        // copy chunks per K chunk and thread
+  const int nk = KP / KCH;
+  const int col = lane & 15, kg = lane >> 4;
+  const int kofs = BF16 ? 8 * kg : 4 * kg;
+  const int bcol = 16 * wave + col;        // Theta column of this lane
+  u32x4 bre[MAXK], bim[MAXK];
+  u32x4 bre_lo[BF16 ? MAXK : 1], bim_lo[BF16 ? MAXK : 1];
+  {
+    const size_t per = (size_t)NPW * KP;
+    const unsigned char* tb = reinterpret_cast<const unsigned char*>(thp_) +
+                              ((size_t)wd * 2 + s) * 2 * PLANES * per * ESZ;
+#pragma unroll
+    for (int c = 0; c < MAXK; ++c) {
+      if (c < nk) {
+        const size_t off = ((size_t)bcol * KP + c * KCH + kofs) * ESZ;
+        bre[c] = *reinterpret_cast<const u32x4*>(tb + off);
+        if (BF16) {
+          bre_lo[BF16 ? c : 0] = *reinterpret_cast<const u32x4*>(tb + per * ESZ + off);
+          bim[c] = *reinterpret_cast<const u32x4*>(tb + 2 * per * ESZ + off);
+          bim_lo[BF16 ? c : 0] = *reinterpret_cast<const u32x4*>(tb + 3 * per * ESZ + off);
+        } else {
+          bim[c] = *reinterpret_cast<const u32x4*>(tb + per * ESZ + off);
+        }
+      }
+    }
+  }
+
+  double xr = 0.0, xi = 0.0;
+  if (G > 0)
+    for (int k = 0; k < nk * CPK; ++k) *chunk_dst(smem, k) = *chunk_src(0, k);
+  __syncthreads();
+  for (int g = 0; g < G; ++g) {
+    const unsigned char* Abuf = smem + (g & 1) * tile_lds_bytes;
+    unsigned char* Anext = smem + ((g + 1) & 1) * tile_lds_bytes;
+    const bool more = g + 1 < G;
+    f32x4 cre[NR], cim[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+      cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    u32x4 stage[CPK];
+#pragma unroll
+    for (int c = 0; c < MAXK; ++c) {
+      if (c < nk) {
+        // chunks of tile g + 1: the ones loaded one K chunk ago go to LDS now
+        u32x4 ld[CPK];
+        if (more) {
+#pragma unroll
+          for (int e = 0; e < CPK; ++e) ld[e] = *chunk_src(g + 1, CPK * c + e);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const unsigned char* arow = Abuf + ((size_t)(16 * r + col) * lda + c * KCH + kofs) * ESZ;
+          if constexpr (!BF16) {
+            const f32x4 a = *reinterpret_cast<const f32x4*>(arow);
+            const f32x4 br = __builtin_bit_cast(f32x4, bre[c]);
+            const f32x4 bi = __builtin_bit_cast(f32x4, bim[c]);
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, br.x, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bi.x, cim[r], 0, 0, 0);
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, br.y, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bi.y, cim[r], 0, 0, 0);
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, br.z, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bi.z, cim[r], 0, 0, 0);
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, br.w, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bi.w, cim[r], 0, 0, 0);
+          } else {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow));
+            const bf16x8 al = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4*>(arow + (size_t)NPW * lda * ESZ));
+            const bf16x8 brh = __builtin_bit_cast(bf16x8, bre[c]);
+            const bf16x8 brl = __builtin_bit_cast(bf16x8, bre_lo[BF16 ? c : 0]);
+            const bf16x8 bih = __builtin_bit_cast(bf16x8, bim[c]);
+            const bf16x8 bil = __builtin_bit_cast(bf16x8, bim_lo[BF16 ? c : 0]);
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, brh, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bih, cim[r], 0, 0, 0);
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brl, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bil, cim[r], 0, 0, 0);
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brh, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bih, cim[r], 0, 0, 0);
+          }
+        }
+        if (more) {
+          if (c > 0) {
+#pragma unroll
+            for (int e = 0; e < CPK; ++e) *chunk_dst(Anext, CPK * (c - 1) + e) = stage[e];
+          }
+#pragma unroll
+          for (int e = 0; e < CPK; ++e) stage[e] = ld[e];
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < CPK; ++e) *chunk_dst(Anext, CPK * (nk - 1) + e) = stage[e];
+    }
+    // lane holds Omega[16 r + 4 kg + v][bcol], v = 0..3: column-major store
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      *reinterpret_cast<float4*>(ep_re + bcol * LDE + 16 * r + 4 * kg) =
+          make_float4(cre[r][0], cre[r][1], cre[r][2], cre[r][3]);
+      *reinterpret_cast<float4*>(ep_im + bcol * LDE + 16 * r + 4 * kg) =
+          make_float4(cim[r][0], cim[r][1], cim[r][2], cim[r][3]);
+    }
+    __syncthreads();  // Omega complete; tile g + 1 stored
+    {
+      float pr = 0.f, pi = 0.f;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * r + 4 * kg + v;
+          const float R = cre[r][v], I = cim[r][v];
+          const float Rt = ep_re[i * LDE + bcol], It = ep_im[i * LDE + bcol];
+          pr += R * Rt - I * It;
+          pi += R * It + I * Rt;
+        }
+      }
+      xr += (double)pr;
+      xi += (double)pi;
+    }
+    if (wave < 2) {
+      // trace: wave 0 sums Re Omega_jj, wave 1 Im Omega_jj
+      const float* epp = wave == 0 ? ep_re : ep_im;
+      float d = lane < NPW ? epp[lane * LDE + lane] : 0.f;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+      if (lane == 0) reinterpret_cast<double*>(tpart + ((size_t)wd * 2 + s) * G + g)[wave] = (double)d;
+    }
+    __syncthreads();  // Omega reads done before the next g writes it
+  }
+  xr = wave_sum(xr);
+  xi = wave_sum(xi);
+  if (lane == 0) {
+    red[wave] = xr;
+    red[NW + wave] = xi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < NW; ++k) {
+      sr += red[k];
+      si += red[NW + k];
+    }
+    exch[2 * wd + s] = mkc(sr, si);
+  }
+}
+
+template <int NPW, bool BF16>
+constexpr size_t wide_contract_lds_bytes_t(int KP) {
+  return (size_t)2 * NPW * (KP + (BF16 ? 8 : 4)) * (BF16 ? 2 : 4) * (BF16 ? 2 : 1) +
+         (size_t)2 * NPW * (NPW + 4) * 4 + 2 * (NPW / 16) * 8;
+}

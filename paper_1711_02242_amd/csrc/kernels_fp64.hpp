@@ -16,159 +16,6 @@
 #define WFLAG_SINGULAR 1u
 
 // ---------------------------------------------------------------------------
-// Overlap, determinant and Theta (Theorem 1.1-1.2, eq:precomputing).
-// One block per (walker, spin).  T = V_s^T U_s (N x N), LU with partial
-// pivoting in LDS, log det T = sum log(pivot) + i pi * (#row swaps),
-// Theta_s = U_s T^{-1} (rows of Theta^T = columns of Theta), and
-// e1_s = tr(ht_s Theta_s).
-// ---------------------------------------------------------------------------
-template <int NMAX>
-__global__ void __launch_bounds__(256) k_overlap_theta(
-    int M, int nup, int ndn, const double* __restrict__ V, const double* __restrict__ ht,
-    const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
-    cd* __restrict__ thetaT, cd* __restrict__ logdet /*[nw][2]*/, cd* __restrict__ e1 /*[nw][2]*/,
-    unsigned* __restrict__ wflag /*[nw][2]*/) {
-  extern __shared__ unsigned char smem_raw[];
-  const int w = blockIdx.x, s = blockIdx.y;
-  const int N = s == 0 ? nup : ndn;
-  const int off = s == 0 ? 0 : nup;
-  const int ntot = nup + ndn;
-  const int tid = threadIdx.x;
-  if (N == 0) {
-    if (tid == 0) {
-      logdet[2 * w + s] = mkc(0.0, 0.0);
-      e1[2 * w + s] = mkc(0.0, 0.0);
-      wflag[2 * w + s] = 0u;
-    }
-    return;
-  }
-  if (check_weight && !(weight[w] > 0.0)) return;
-  const int ld = N + 1;
-  cd* T = reinterpret_cast<cd*>(smem_raw);                       // [N][N+1]
-  int* perm = reinterpret_cast<int*>(T + N * ld);                // [N]
-  double* red = reinterpret_cast<double*>(perm + NMAX);          // [8]
-  __shared__ int s_piv;
-  __shared__ int s_nswap;
-  __shared__ int s_sing;
-
-  const cd* Uw = U + ((size_t)w * ntot + off) * M;
-  const double* Vs = V + (size_t)off * M;
-  // T_ij = sum_p V_pi U_pj
-  for (int e = tid; e < N * N; e += blockDim.x) {
-    const int i = e / N, j = e % N;
-    cd acc = mkc(0.0, 0.0);
-    const double* vi = Vs + (size_t)i * M;
-    const cd* uj = Uw + (size_t)j * M;
-    for (int p = 0; p < M; ++p) cfmar(acc, uj[p], vi[p]);
-    T[i * ld + j] = acc;
-  }
-  if (tid < N) perm[tid] = tid;
-  if (tid == 0) {
-    s_nswap = 0;
-    s_sing = 0;
-  }
-  __syncthreads();
-  // LU with partial pivoting: P T = L R, L unit lower, R upper.
-  for (int k = 0; k < N; ++k) {
-    if (tid == 0) {
-      int piv = k;
-      double best = -1.0;
-      for (int i = k; i < N; ++i) {
-        const cd v = T[i * ld + k];
-        const double m = v.re * v.re + v.im * v.im;
-        if (m > best) {
-          best = m;
-          piv = i;
-        }
-      }
-      s_piv = piv;
-      if (!(best > 0.0)) s_sing = 1;
-      if (piv != k) {
-        const int t = perm[k];
-        perm[k] = perm[piv];
-        perm[piv] = t;
-        s_nswap += 1;
-      }
-    }
-    __syncthreads();
-    const int piv = s_piv;
-    if (piv != k) {
-      for (int j = tid; j < N; j += blockDim.x) {
-        const cd a = T[k * ld + j];
-        T[k * ld + j] = T[piv * ld + j];
-        T[piv * ld + j] = a;
-      }
-    }
-    __syncthreads();
-    if (s_sing) break;
-    const cd pk = T[k * ld + k];
-    for (int i = k + 1 + tid; i < N; i += blockDim.x) T[i * ld + k] = cdiv(T[i * ld + k], pk);
-    __syncthreads();
-    const int rem = N - k - 1;
-    for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      cfms(T[i * ld + j], T[i * ld + k], T[k * ld + j]);
-    }
-    __syncthreads();
-  }
-  if (s_sing) {
-    if (tid == 0) {
-      wflag[2 * w + s] = WFLAG_SINGULAR;
-      logdet[2 * w + s] = mkc(-INFINITY, 0.0);
-      e1[2 * w + s] = mkc(0.0, 0.0);
-    }
-    return;
-  }
-  if (tid == 0) {
-    double la = 0.0, ar = 0.0;
-    for (int k = 0; k < N; ++k) {
-      const cd v = T[k * ld + k];
-      la += log(hypot(v.re, v.im));
-      ar += atan2(v.im, v.re);
-    }
-    ar += M_PI * (double)(s_nswap & 1);
-    logdet[2 * w + s] = mkc(la, ar);
-    wflag[2 * w + s] = 0u;
-  }
-  // Theta rows: theta_p T = u_p  <=>  z L R = u with z_k = theta_{perm[k]}.
-  double e1re = 0.0, e1im = 0.0;
-  cd* Tw = thetaT + ((size_t)w * ntot + off) * M;
-  const double* hts = ht + (size_t)off * M;
-  for (int p = tid; p < M; p += blockDim.x) {
-    cd y[NMAX];
-#pragma unroll
-    for (int j = 0; j < NMAX; ++j) {
-      if (j < N) {
-        cd acc = Uw[(size_t)j * M + p];
-        for (int i = 0; i < j; ++i) cfms(acc, y[i], T[i * ld + j]);
-        y[j] = cdiv(acc, T[j * ld + j]);
-      }
-    }
-#pragma unroll
-    for (int jj = NMAX - 1; jj >= 0; --jj) {
-      if (jj < N) {
-        cd acc = y[jj];
-        for (int i = jj + 1; i < N; ++i) cfms(acc, y[i], T[i * ld + jj]);
-        y[jj] = acc;  // now z_jj
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NMAX; ++k) {
-      if (k < N) {
-        const int c = perm[k];
-        Tw[(size_t)c * M + p] = y[k];
-        const double hv = hts[(size_t)c * M + p];
-        e1re = fma(hv, y[k].re, e1re);
-        e1im = fma(hv, y[k].im, e1im);
-      }
-    }
-  }
-  e1re = block_sum(e1re, red);
-  e1im = block_sum(e1im, red);
-  if (tid == 0) e1[2 * w + s] = mkc(e1re, e1im);
-}
-
-// ---------------------------------------------------------------------------
 // Local-energy contraction in FP64 (eq:localenergy3): for every g,
 // Omega = Lh^g_s Theta_s (N x N), tpart[w][s][g] = tr Omega and
 // exch[w][s] = sum_g tr(Omega Omega).  One block per (walker, spin).
@@ -878,189 +725,4 @@ __global__ void k_init_walkers(int nw, int rowlen, const double* __restrict__ V,
     walker_id[w] = w;
     if (phase) phase[w] = 0.0;
   }
-}
-
-// ---------------------------------------------------------------------------
-// Overlap, determinant and Theta with the walker's orbitals staged in LDS
-// (Theorem 1.1-1.2, eq:precomputing).  One block per (walker, spin):
-//   T = V_s^T U_s;  Gauss-Jordan with partial pivoting on [T | I] gives T^{-1}
-//   and log det T = sum log(pivot) + i pi (#row swaps);
-//   Theta^T[c][p] = sum_j (T^{-1})_jc U^T[j][p];  e1 = tr(ht_s Theta_s).
-// When `packed` is non-null the Theta operand of the MFMA contraction is written
-// too (FP32 Re/Im planes, or BF16 hi/lo of each), zero-padded to NP x KP.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_overlap_gj(
-    int M, int nup, int ndn, const double* __restrict__ V, const double* __restrict__ ht,
-    const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
-    cd* __restrict__ thetaT, cd* __restrict__ logdet, cd* __restrict__ e1,
-    unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  const int w = blockIdx.x, s = blockIdx.y;
-  const int N = s == 0 ? nup : ndn;
-  const int off = s == 0 ? 0 : nup;
-  const int ntot = nup + ndn;
-  const int tid = threadIdx.x, lane = tid & 63;
-  if (N == 0) {
-    if (tid == 0) {
-      logdet[2 * w + s] = mkc(0.0, 0.0);
-      e1[2 * w + s] = mkc(0.0, 0.0);
-      wflag[2 * w + s] = 0u;
-    }
-    return;
-  }
-  if (check_weight && !(weight[w] > 0.0)) return;
-  const int ldu = M + 1, lda = 2 * N + 1;
-  cd* Ut = reinterpret_cast<cd*>(smem_raw);      // [N][M+1]
-  cd* Ag = Ut + (size_t)N * ldu;                  // [N][2N+1]
-  cd* fac = Ag + (size_t)N * lda;                 // [N]
-  double* red = reinterpret_cast<double*>(fac + N);  // [8]
-  __shared__ int s_piv, s_sing, s_nswap;
-  __shared__ double s_la, s_ar;
-
-  const cd* Uw = U + ((size_t)w * ntot + off) * M;
-  for (int e = tid; e < N * M; e += blockDim.x) Ut[(e / M) * ldu + e % M] = Uw[e];
-  if (tid == 0) {
-    s_sing = 0;
-    s_nswap = 0;
-    s_la = 0.0;
-    s_ar = 0.0;
-  }
-  __syncthreads();
-  const double* Vs = V + (size_t)off * M;
-  for (int e = tid; e < N * N; e += blockDim.x) {
-    const int i = e / N, j = e % N;
-    const double* vi = Vs + (size_t)i * M;
-    const cd* uj = Ut + (size_t)j * ldu;
-    cd acc = mkc(0.0, 0.0);
-    for (int p = 0; p < M; ++p) cfmar(acc, uj[p], vi[p]);
-    Ag[i * lda + j] = acc;
-    Ag[i * lda + N + j] = mkc(i == j ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  for (int k = 0; k < N; ++k) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = k;
-      for (int i = k + lane; i < N; i += 64) {
-        const cd v = Ag[i * lda + k];
-        const double m = v.re * v.re + v.im * v.im;
-        if (m > best) {
-          best = m;
-          bi = i;
-        }
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        s_piv = bi;
-        if (!(best > 0.0)) s_sing = 1;
-        if (bi != k) s_nswap += 1;
-      }
-    }
-    __syncthreads();
-    if (s_sing) break;
-    const int piv = s_piv;
-    if (piv != k) {
-      for (int j = tid; j < 2 * N; j += blockDim.x) {
-        const cd a = Ag[k * lda + j];
-        Ag[k * lda + j] = Ag[piv * lda + j];
-        Ag[piv * lda + j] = a;
-      }
-    }
-    __syncthreads();
-    const cd pk = Ag[k * lda + k];
-    if (tid < N) fac[tid] = Ag[tid * lda + k];
-    if (tid == 0) {
-      s_la += log(hypot(pk.re, pk.im));
-      s_ar += atan2(pk.im, pk.re);
-    }
-    __syncthreads();
-    for (int j = tid; j < 2 * N; j += blockDim.x) Ag[k * lda + j] = cdiv(Ag[k * lda + j], pk);
-    __syncthreads();
-    for (int e = tid; e < N * 2 * N; e += blockDim.x) {
-      const int i = e / (2 * N), j = e % (2 * N);
-      if (i != k) cfms(Ag[i * lda + j], fac[i], Ag[k * lda + j]);
-    }
-    __syncthreads();
-  }
-  if (s_sing) {
-    if (tid == 0) {
-      wflag[2 * w + s] = WFLAG_SINGULAR;
-      logdet[2 * w + s] = mkc(-INFINITY, 0.0);
-      e1[2 * w + s] = mkc(0.0, 0.0);
-    }
-    return;
-  }
-  if (tid == 0) {
-    logdet[2 * w + s] = mkc(s_la, s_ar + M_PI * (double)(s_nswap & 1));
-    wflag[2 * w + s] = 0u;
-  }
-  // Theta^T[c][p] = sum_j Tinv[j][c] Ut[j][p]
-  double e1re = 0.0, e1im = 0.0;
-  cd* Tw = thetaT + ((size_t)w * ntot + off) * M;
-  const double* hts = ht + (size_t)off * M;
-  const size_t per = (size_t)NP * KP;
-  for (int e = tid; e < N * M; e += blockDim.x) {
-    const int c = e / M, p = e % M;
-    cd acc = mkc(0.0, 0.0);
-    for (int j = 0; j < N; ++j) cfma(acc, Ag[j * lda + N + c], Ut[(size_t)j * ldu + p]);
-    Tw[(size_t)c * M + p] = acc;
-    const double hv = hts[(size_t)c * M + p];
-    e1re = fma(hv, acc.re, e1re);
-    e1im = fma(hv, acc.im, e1im);
-    if (packed_kind == 3) {
-      double* o = reinterpret_cast<double*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
-      o[0] = acc.re;
-      o[per] = acc.im;
-    } else if (packed_kind == 1) {
-      float* o = reinterpret_cast<float*>(packed) + ((size_t)w * 2 + s) * 2 * per + (size_t)c * KP + p;
-      o[0] = (float)acc.re;
-      o[per] = (float)acc.im;
-    } else if (packed_kind == 2) {
-      uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)w * 2 + s) * 4 * per + (size_t)c * KP + p;
-      const float xr = (float)acc.re, xi = (float)acc.im;
-      // round-to-nearest-even to bf16, then the residual likewise
-      auto bf = [](float f) -> uint16_t {
-        uint32_t u;
-        memcpy(&u, &f, 4);
-        if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (uint16_t)(u >> 16);
-      };
-      auto up = [](uint16_t b) -> float {
-        uint32_t u = (uint32_t)b << 16;
-        float f;
-        memcpy(&f, &u, 4);
-        return f;
-      };
-      const uint16_t hr = bf(xr), hi = bf(xi);
-      o[0] = hr;
-      o[per] = bf(xr - up(hr));
-      o[2 * per] = hi;
-      o[3 * per] = bf(xi - up(hi));
-    }
-  }
-  // zero padding of the packed operand (rows N..NP-1, columns M..KP-1)
-  if (packed_kind) {
-    const int planes = packed_kind == 2 ? 4 : 2;
-    for (size_t e = tid; e < (size_t)planes * per; e += blockDim.x) {
-      const int pl = (int)(e / per);
-      const int c = (int)((e % per) / KP), p = (int)(e % KP);
-      if (c < N && p < M) continue;
-      const size_t o = ((size_t)w * 2 + s) * planes * per + (size_t)pl * per + (size_t)c * KP + p;
-      if (packed_kind == 3) reinterpret_cast<double*>(packed)[o] = 0.0;
-      else if (packed_kind == 1) reinterpret_cast<float*>(packed)[o] = 0.f;
-      else reinterpret_cast<uint16_t*>(packed)[o] = 0;
-    }
-  }
-  e1re = block_sum(e1re, red);
-  e1im = block_sum(e1im, red);
-  if (tid == 0) e1[2 * w + s] = mkc(e1re, e1im);
 }

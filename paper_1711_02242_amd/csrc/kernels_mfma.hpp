@@ -35,14 +35,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int MFMA_KMAX = 128;
+constexpr int MFMA_KMAX = 128;   // K limit of the register-resident contraction kernels
+constexpr int WIDE_KMAX = 224;   // K limit of the wide (workgroup-per-walker) kernel
 constexpr int MFMA_WAVES = 4;
 
 struct MfmaTables {
   bool enabled = false;
   int precision = 0;  // AFQMC_FP64, AFQMC_FP32 or AFQMC_BF16X3
   int NP = 0, KP = 0, M = 0, G = 0, nup = 0, ndn = 0, n_det = 1;
-  void* Lp = nullptr;  // fp64 / fp32: [2][G][NP][KP]; bf16x3: [2][G][2 (hi, lo)][NP][KP] bf16 bits
+  bool wide = false;   // N > 32 or M > 128 (up to 64, 224): the kernel of contract_wide.hpp
+  void* Lp = nullptr;  // fp64 / fp32: [n_det][2][G][NP][KP]; bf16x3: [n_det][2][G][2 (hi, lo)][NP][KP]
   size_t bytes = 0;
 };
 
@@ -70,9 +72,15 @@ inline size_t mfma_theta_bytes(const MfmaTables& t, size_t nw) {
 inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int ndn, int G,
                              const double* Lh /* host [n_det][G][nup+ndn][M] */, int n_det = 1) {
   const int nmax = nup > ndn ? nup : ndn;
-  if (nmax > 32 || M > MFMA_KMAX) return AFQMC_E_UNSUPPORTED;
+  // register-resident kernels up to N = 32, M = 128 (all precisions); beyond, up to N = 64,
+  // M = 256, the wide FP32 / BF16x3 kernel
+  const bool fast = nmax <= 32 && M <= MFMA_KMAX;
+  const bool wide = !fast && precision != AFQMC_FP64 && nmax <= 64 && M <= WIDE_KMAX;
+  if (!fast && !wide) return AFQMC_E_UNSUPPORTED;
   t.precision = precision;
-  t.NP = nmax <= 16 ? 16 : 32;
+  t.wide = wide;
+  t.NP = nmax <= 16 ? 16 : nmax <= 32 ? 32 : nmax <= 48 ? 48 : 64;
+  if (wide && t.NP < 32) t.NP = 32;
   t.KP = ((M + 31) / 32) * 32;
   t.M = M;
   t.G = G;
@@ -142,6 +150,7 @@ inline void mfma_free_tables(MfmaTables& t) {
 }
 
 #include "contract_mfma.hpp"
+#include "contract_wide.hpp"
 
 inline size_t mfma_contract_lds_bytes(const MfmaTables& t) {
   const bool bf = t.precision == AFQMC_BF16X3;
@@ -336,9 +345,32 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
     }
     return hipGetLastError();
   }
+  const bool bf = t.precision == AFQMC_BF16X3;
+  if (t.wide) {
+    dim3 grid(nw, 2 * n_det);
+#define LAUNCH_WIDE(NPV, BFV)                                                                   \
+  do {                                                                                          \
+    const size_t shm_ = wide_contract_lds_bytes_t<NPV, BFV>(t.KP);                              \
+    (void)hipFuncSetAttribute((const void*)k_contract_mfma_wide<NPV, BFV>,                      \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_);           \
+    hipLaunchKernelGGL((k_contract_mfma_wide<NPV, BFV>), grid, dim3(4 * NPV), shm_, st, nw, G,  \
+                       t.nup, t.ndn, t.KP, (const void*)t.Lp, thetaP, weight, tpart, exch);     \
+  } while (0)
+    if (t.NP == 64) {
+      if (bf) LAUNCH_WIDE(64, true);
+      else LAUNCH_WIDE(64, false);
+    } else if (t.NP == 48) {
+      if (bf) LAUNCH_WIDE(48, true);
+      else LAUNCH_WIDE(48, false);
+    } else {
+      if (bf) LAUNCH_WIDE(32, true);
+      else LAUNCH_WIDE(32, false);
+    }
+#undef LAUNCH_WIDE
+    return hipGetLastError();
+  }
   const size_t shm = mfma_contract_lds_bytes(t);
   dim3 grid((nw + MFMA_WAVES - 1) / MFMA_WAVES, 2 * n_det);
-  const bool bf = t.precision == AFQMC_BF16X3;
 #define LAUNCH_CONTRACT(NPV, BFV)                                                               \
   do {                                                                                          \
     (void)hipFuncSetAttribute((const void*)k_contract_mfma<NPV, BFV>,                           \
@@ -359,14 +391,14 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
 
 // ---------------------------------------------------------------------------
 // Overlap, determinant and Theta with the two small products on FP64 MFMA
-// (Theorem 1.1-1.2, eq:precomputing), for N <= 32.  One block (4 waves) per
-// (walker, spin); only the Gauss-Jordan matrix [T | I] lives in LDS, which keeps
+// (Theorem 1.1-1.2, eq:precomputing), for N <= 64.  One block (4 waves) per
+// (walker, spin, determinant); only the Gauss-Jordan matrix [T | I] lives in LDS, which keeps
 // several blocks per CU.
 //   T = V^T U             (16x16 blocks, K = M, U read from global as complex)
 //   [T | I] -> [I | T^-1] (Gauss-Jordan, partial pivoting, log det from the pivots)
 //   Theta^T = (T^-1)^T U^T  (16x16 blocks, K = N, complex product as four real ones)
-// The outputs are those of k_overlap_gj: Theta^T (FP64), e1 = tr(ht Theta), logdet,
-// flags, and optionally the packed MFMA operand of the contraction.
+// Outputs: Theta^T (FP64), e1 = tr(ht Theta), log det T (complex), singular flags,
+// and optionally the packed MFMA operand of the contraction.
 // ---------------------------------------------------------------------------
 template <int NPAD>
 __global__ void __launch_bounds__(256) k_overlap_mfma(

@@ -170,8 +170,8 @@ def test_gpu_singular_and_nonfinite_walkers_are_killed(torch_cuda, precision):
 
 @pytest.mark.parametrize("case", ["n34_m136", "n48_m200"])
 def test_gpu_fp64_beyond_mfma_tile_limits(torch_cuda, case):
-    """FP64 sizes outside the MFMA tiles (N > 32 or M > 128) run on the FP64 VALU kernels;
-    M=200, N=48 also exceeds the LDS of the staged inverse and uses the LU kernel."""
+    """FP64 sizes outside the register-resident MFMA tiles (N > 32 or M > 128) run the FP64
+    VALU contraction, with the overlap on k_overlap_mfma<48>."""
     if case == "n34_m136":
         s, nw, steps = gen_system(136, 34, 40, seed=21, n_dn=30), 3, 5
     else:

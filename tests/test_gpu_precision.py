@@ -114,7 +114,49 @@ def test_dynamic_drift_shapes(precision, case):
 
 
 def test_mixed_precision_refuses_unsupported_sizes():
+    """The MFMA kernels cover N <= 64 electrons per spin and M <= 224 orbitals."""
     import paper_1711_02242_amd as afq
-    s = gen_system(136, 34, 40, seed=1)
+    s = gen_system(232, 20, 6, seed=1)
     with pytest.raises(afq.AfqmcError):
         afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
+    s = gen_system(70, 65, 4, seed=2)
+    for precision in ("fp64", "fp32"):
+        with pytest.raises(afq.AfqmcError):
+            afq.System.from_synthetic(s, dtau=0.005, precision=precision)
+
+
+WIDE = {
+    # name: (M, N_up, N_dn, N_g, walkers); tile of the wide kernel in brackets
+    "n34_m136": (136, 34, 30, 40, 5),    # NP 48, KP 160
+    "n20_m150": (150, 20, 20, 50, 5),    # NP 32 (M > 128), KP 160
+    "n40_m160": (160, 40, 40, 60, 4),    # NP 48, KP 160 (largest batch draw)
+    "n50_m200": (200, 50, 48, 30, 3),    # NP 64, KP 224 (largest serving draw)
+    "n64_m96": (96, 64, 60, 30, 3),      # NP 64, KP 96
+}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", list(WIDE))
+def test_static_local_energy_wide(precision, case):
+    """Shapes beyond the register-resident kernels run on the wide MFMA contraction."""
+    M, nu, nd, G, nw = WIDE[case]
+    s = gen_system(M, nu, G, seed=31, n_dn=nd)
+    log(f"static wide {precision} {case}")
+    err, arg_err, gs, wk = _static(s, nw, precision, amplitude=0.4)
+    log(f"  max |dE_L| = {err:.3e} Ha")
+    assert err < EL_TOL
+    assert arg_err < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["n34_m136", "n50_m200"])
+def test_dynamic_drift_wide(precision, case):
+    M, nu, nd, G, nw = WIDE[case]
+    s = gen_system(M, nu, G, seed=32, n_dn=nd)
+    log(f"dynamic wide {precision} {case}")
+    worst, gs, wk, S, wo = run_lockstep(s, nw, 5, dtau=0.005, precision=precision, rtol=1e-4,
+                                        label=f"wide-{case}-{precision}")
+    st = gpu_state(wk)
+    alive = wo.W > 0
+    assert np.abs(st["e"][alive] - wo.e_loc[alive]).max() < EL_TOL
+    log(f"  worst {worst}")
