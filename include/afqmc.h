@@ -213,6 +213,32 @@ AFQMC_API int afqmc_measure(afqmc_sys s, afqmc_walkers* w);
  * Asynchronous; allocates nothing. */
 AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
 
+/* Batches: many systems (uneven M, N, N_g and walker counts) stepped together, one graph
+ * launch per step.  Each system keeps its own walkers, fields stream and parameters; the batch
+ * captures one afqmc_step of every system into a HIP graph -- each system on a branch stream
+ * of its own, forked from and joined into the batch stream, so independent systems may run
+ * concurrently -- and replays it with hipGraphLaunch.  One graph is kept per combination of
+ * due re-orthonormalization / comb phases.  The results are those of afqmc_step on every
+ * system in turn: same kernels, same arithmetic, same field stream.
+ *
+ * afqmc_batch_create: n >= 1 systems and their walkers (distinct populations, initialized;
+ *   the walkers structs and every array they point to must stay valid and unmoved until
+ *   afqmc_batch_destroy).  stream: the caller's stream (NULL = the null stream); each batch
+ *   step runs after the work enqueued on it before the call, and work enqueued on it after
+ *   the call runs after the step.  The graphs run on a stream the batch owns.  Synchronizes
+ *   the systems' streams once.  Work of the systems' own streams issued later must be
+ *   ordered with the batch's stream by the caller.
+ * afqmc_batch_step: fields[n], one per system, with x == NULL (the fields are drawn on the
+ *   device from the counter stream) and u_comb NaN; a change of seed or job id recaptures.
+ *   Advances every walkers->step.  Asynchronous; allocates nothing once every phase has
+ *   been captured (the first steps capture and instantiate the graphs).
+ * afqmc_batch_destroy: synchronizes the batch stream and frees the graphs and streams. */
+typedef struct afqmc_batch_s* afqmc_batch;
+AFQMC_API int afqmc_batch_create(int32_t n, const afqmc_sys* systems, afqmc_walkers* const* walkers,
+                                 void* stream, afqmc_batch* out);
+AFQMC_API int afqmc_batch_step(afqmc_batch b, const afqmc_fields* fields);
+AFQMC_API int afqmc_batch_destroy(afqmc_batch b);
+
 /* Draw (or copy) the fields the next afqmc_step would use, into device x_out
  * [n_walkers][n_chol] doubles.  Asynchronous. */
 AFQMC_API int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc_fields* f, double* x_out);

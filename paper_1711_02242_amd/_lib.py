@@ -22,7 +22,8 @@ KERNEL_GROUPS = ["contract", "overlap", "fields", "abuild", "propagate", "qr", "
 EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walkers_init",
            "afqmc_measure", "afqmc_step", "afqmc_fields_draw", "afqmc_energy", "afqmc_get_status",
            "afqmc_kernel_timing", "afqmc_kernel_time", "afqmc_destroy", "afqmc_error_string",
-           "afqmc_mcd_workspace_bytes", "afqmc_modified_cholesky", "afqmc_setup_multidet"]
+           "afqmc_mcd_workspace_bytes", "afqmc_modified_cholesky", "afqmc_setup_multidet",
+           "afqmc_batch_create", "afqmc_batch_step", "afqmc_batch_destroy"]
 
 
 class Params(C.Structure):
@@ -84,6 +85,10 @@ def load(path: str | None = None) -> C.CDLL:
         "afqmc_kernel_timing": ([C.c_void_p, C.c_int], C.c_int),
         "afqmc_kernel_time": ([C.c_void_p, C.c_int, P(C.c_double), P(C.c_int64)], C.c_int),
         "afqmc_destroy": ([C.c_void_p], C.c_int),
+        "afqmc_batch_create": ([C.c_int32, P(C.c_void_p), P(P(WalkersC)), C.c_void_p,
+                                P(C.c_void_p)], C.c_int),
+        "afqmc_batch_step": ([C.c_void_p, P(FieldsC)], C.c_int),
+        "afqmc_batch_destroy": ([C.c_void_p], C.c_int),
         "afqmc_error_string": ([C.c_int], C.c_char_p),
         "afqmc_mcd_workspace_bytes": ([C.c_int32, P(C.c_size_t)], C.c_int),
         "afqmc_modified_cholesky": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p,

@@ -238,6 +238,51 @@ class Walkers:
         self.step = int(self._c.step)
 
 
+class Batch:
+    """Systems with their walkers stepped together by one graph launch per step
+    (``afqmc_batch_*``).  Keeps the systems and walkers alive while it exists."""
+
+    def __init__(self, pairs, stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        self.pairs = list(pairs)
+        n = len(self.pairs)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        sysv = (C.c_void_p * n)(*[gs.handle.value for gs, _ in self.pairs])
+        for _, wk in self.pairs:
+            wk.c_ref()
+        wv = (C.POINTER(L.WalkersC) * n)(*[C.pointer(wk._c) for _, wk in self.pairs])
+        self._keep = (sysv, wv)
+        h = C.c_void_p()
+        L.check(self.lib.afqmc_batch_create(n, sysv, wv, C.c_void_p(_stream_handle(self.stream)),
+                                            C.byref(h)), "afqmc_batch_create")
+        self.handle = h
+        self._fields = (L.FieldsC * n)()
+
+    def step(self, seeds, job_ids=None) -> None:
+        """One step of every system; fields drawn on the device from (seed, job_id)."""
+        n = len(self.pairs)
+        for i in range(n):
+            self._fields[i].seed = int(seeds[i])
+            self._fields[i].job_id = 0 if job_ids is None else int(job_ids[i])
+            self._fields[i].x = None
+            self._fields[i].u_comb = math.nan
+        L.check(self.lib.afqmc_batch_step(self.handle, self._fields), "afqmc_batch_step")
+        for _, wk in self.pairs:
+            wk.sync_from_c()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.check(self.lib.afqmc_batch_destroy(self.handle), "afqmc_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def modified_cholesky(eri, delta: float, max_vectors: int | None = None, stream=None):
     """Modified Cholesky decomposition of a device tensor eri[p, q, r, s] = v_pqrs (float64,
     (M, M, M, M)) on the GPU.  Returns (L, converged) with L a device tensor (n, M, M)."""

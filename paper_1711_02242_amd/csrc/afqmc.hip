@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/afqmc.h"
@@ -28,7 +29,7 @@ struct TimedLaunch {
 
 struct WsLayout {
   size_t thetaT, tcur, tpart, exch, e1, logdet, wflag, enew, y, A, X0, X1, Y, parent, csum,
-      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, mfterm, logR, psnap, ldc, wflc, total;
+      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, mfterm, logR, psnap, ldc, wflc, dstep, total;
 };
 
 }  // namespace
@@ -107,6 +108,7 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.psnap = take(nw * 8);
   L.ldc = take(S->multi ? nw * 2 * 16 : 0);
   L.wflc = take(S->multi ? nw * 2 * 4 : 0);
+  L.dstep = take(8);
   L.total = o;
   return L;
 }
@@ -356,6 +358,7 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
 int do_measure(afqmc_sys_s* S, afqmc_walkers* w) {
   const WsLayout L = layout(S, (size_t)w->n_walkers);
   void* ws = w->workspace;
+  hipLaunchKernelGGL(k_step_set, dim3(1), dim3(1), 0, S->stream, at<int64_t>(ws, L.dstep), w->step);
   int rc = launch_overlap(S, w, L, 1);
   if (rc) return rc;
   rc = launch_contract(S, w, L);
@@ -370,7 +373,7 @@ int do_measure(afqmc_sys_s* S, afqmc_walkers* w) {
 }
 
 int launch_fields(afqmc_sys_s* S, const afqmc_walkers* w, const afqmc_fields* f, const WsLayout& L,
-                  double* xout) {
+                  double* xout, const int64_t* dstep = nullptr) {
   Timer tm(S, KG_FIELDS);
   const int nblk = (S->G + 3) / 4;
   const long n = (long)w->n_walkers * nblk;
@@ -378,7 +381,7 @@ int launch_fields(afqmc_sys_s* S, const afqmc_walkers* w, const afqmc_fields* f,
   void* ws = w->workspace;
   hipLaunchKernelGGL(k_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S->stream,
                      w->n_walkers, S->G, S->s, S->p.fb_cap, at<cd>(ws, L.tcur), w->weight,
-                     w->walker_id, f->seed, f->job_id, w->step, f->x, at<cd>(ws, L.y), xout,
+                     w->walker_id, f->seed, f->job_id, w->step, dstep, f->x, at<cd>(ws, L.y), xout,
                      S->status,
                      ((S->p.flags & (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION)) && !xout)
                          ? at<cd>(ws, L.fbterm) : nullptr,
@@ -727,7 +730,7 @@ int afqmc_walkers_init(afqmc_sys s, afqmc_walkers* w) {
                      s->ntot * s->M, s->V, (cd*)w->U, w->weight, w->walker_id, w->phase);
   HIPCHK(hipGetLastError());
   w->step = 0;
-  return do_measure(s, w);
+  return do_measure(s, w);   // also sets the device step counter
 }
 
 int afqmc_measure(afqmc_sys s, afqmc_walkers* w) {
@@ -745,16 +748,23 @@ int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc_fields* f
   return launch_fields(s, w, f, L, x_out);
 }
 
-int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
-  if (!s || !f) return AFQMC_E_ARG;
-  int rc = check_walkers(s, w);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace {
+
+// One step of the random walk (Sec. III.E) enqueued on s->stream.  With `graph` the step
+// number is read on the device from the workspace counter (so that a captured graph can be
+// replayed) and the counter is advanced at the end; otherwise the host value is used and
+// the counter is set to it.
+int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool graph) {
   const WsLayout L = layout(s, (size_t)w->n_walkers);
   void* ws = w->workspace;
   const int nw = w->n_walkers, M = s->M, nt = s->ntot;
   const int64_t k = w->step;
+  int64_t* dstep = at<int64_t>(ws, L.dstep);
+  int rc;
   // 1. fields and force bias
-  if ((rc = launch_fields(s, w, f, L, nullptr))) return rc;
+  if ((rc = launch_fields(s, w, f, L, nullptr, graph ? dstep : nullptr))) return rc;
   // 2-3. propagator exponent A and propagation U <- E_h T_n(A) E_h U
   if (s->f32_prop) {
     float* Are = at<float>(ws, L.A);
@@ -843,22 +853,12 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
     const double u = f->u_comb;
     const size_t cshm = nw <= 8192 ? (size_t)nw * 8 : 0;
     hipLaunchKernelGGL(k_comb_select, dim3(1), dim3(1024), cshm, s->stream, nw, w->weight, u, f->seed,
-                       f->job_id, k, at<double>(ws, L.csum), at<int>(ws, L.parent),
-                       at<double>(ws, L.wnew), s->status);
-    const size_t rowb = (size_t)nt * M * 16;
-    HIPCHK(hipMemcpyAsync(at<void>(ws, L.X0), w->U, rowb * nw, hipMemcpyDeviceToDevice, s->stream));
-    if (s->G > 0)
-      HIPCHK(hipMemcpyAsync(at<void>(ws, L.y), at<void>(ws, L.tcur), (size_t)nw * s->G * 16,
-                            hipMemcpyDeviceToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(at<void>(ws, L.enew), w->e_loc, (size_t)nw * 16, hipMemcpyDeviceToDevice,
-                          s->stream));
-    HIPCHK(hipMemcpyAsync(at<void>(ws, L.asnap), w->arg_ovlp, (size_t)nw * 8,
-                          hipMemcpyDeviceToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(at<void>(ws, L.lsnap), w->log_ovlp, (size_t)nw * 8,
-                          hipMemcpyDeviceToDevice, s->stream));
-    if (w->phase)
-      HIPCHK(hipMemcpyAsync(at<void>(ws, L.psnap), w->phase, (size_t)nw * 8,
-                            hipMemcpyDeviceToDevice, s->stream));
+                       f->job_id, k, graph ? dstep : nullptr, at<double>(ws, L.csum),
+                       at<int>(ws, L.parent), at<double>(ws, L.wnew), s->status);
+    hipLaunchKernelGGL(k_comb_snapshot, dim3(nw), dim3(256), 0, s->stream, nw, nt * M, s->G,
+                       (const cd*)w->U, at<cd>(ws, L.tcur), (const cd*)w->e_loc, w->arg_ovlp,
+                       w->log_ovlp, w->phase, at<cd>(ws, L.X0), at<cd>(ws, L.y), at<cd>(ws, L.enew),
+                       at<double>(ws, L.asnap), at<double>(ws, L.lsnap), at<double>(ws, L.psnap));
     hipLaunchKernelGGL(k_comb_gather, dim3(nw), dim3(256), 0, s->stream, nw, nt * M, s->G,
                        at<int>(ws, L.parent), at<double>(ws, L.wnew), at<cd>(ws, L.X0),
                        at<cd>(ws, L.y), at<cd>(ws, L.enew), at<double>(ws, L.asnap),
@@ -867,7 +867,224 @@ int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
                        w->weight, w->walker_id);
     HIPCHK(hipGetLastError());
   }
+  if (graph)
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s->stream, dstep);
+  else
+    hipLaunchKernelGGL(k_step_set, dim3(1), dim3(1), 0, s->stream, dstep, k + 1);
+  HIPCHK(hipGetLastError());
   w->step = k + 1;
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f) {
+  if (!s || !f) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  return step_impl(s, w, f, false);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of systems stepped by one graph launch.  The step of every system is captured
+// once per combination of due QR / comb phases, each system on a branch stream of its own
+// (fork from and join into the batch stream), and replayed with hipGraphLaunch.
+// ---------------------------------------------------------------------------
+struct afqmc_batch_s {
+  std::vector<afqmc_sys_s*> sys;
+  std::vector<afqmc_walkers*> w;
+  std::vector<afqmc_fields> f;          // seeds the graphs were captured with
+  std::vector<int64_t> expected;        // host step each device counter holds
+  hipStream_t stream = nullptr;         // the caller's stream (may be the null stream)
+  hipStream_t cap = nullptr;            // owned stream the graphs are captured on and run on
+  hipEvent_t in_ev = nullptr, out_ev = nullptr;  // order cap after / before the caller's stream
+  std::vector<hipStream_t> branch;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  std::vector<std::pair<std::vector<uint8_t>, hipGraphExec_t>> graphs;
+  bool have_fields = false;
+};
+
+namespace {
+
+void batch_drop_graphs(afqmc_batch_s* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+}
+
+void batch_free(afqmc_batch_s* b) {
+  if (!b) return;
+  batch_drop_graphs(b);
+  for (auto st : b->branch) (void)hipStreamDestroy(st);
+  for (auto ev : b->join) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->in_ev) (void)hipEventDestroy(b->in_ev);
+  if (b->out_ev) (void)hipEventDestroy(b->out_ev);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+// Reports a failing HIP call on stderr when AFQMC_DEBUG is set (the return code is the API).
+bool hip_ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  if (getenv("AFQMC_DEBUG")) fprintf(stderr, "afqmc: %s: %s\n", what, hipGetErrorString(e));
+  return false;
+}
+
+int batch_capture(afqmc_batch_s* b, hipGraphExec_t* exec) {
+  const size_t n = b->sys.size();
+  std::vector<hipStream_t> saved(n);
+  std::vector<bool> timing(n);
+  std::vector<int64_t> steps(n);
+  if (!hip_ok(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture"))
+    return AFQMC_E_HIP;
+  int rc = AFQMC_OK;
+  if (!hip_ok(hipEventRecord(b->fork, b->cap), "fork record")) rc = AFQMC_E_HIP;
+  for (size_t i = 0; i < n && rc == AFQMC_OK; ++i) {
+    afqmc_sys_s* S = b->sys[i];
+    if (!hip_ok(hipStreamWaitEvent(b->branch[i], b->fork, 0), "fork wait")) {
+      rc = AFQMC_E_HIP;
+      break;
+    }
+    saved[i] = S->stream;
+    timing[i] = S->timing;
+    steps[i] = b->w[i]->step;
+    S->stream = b->branch[i];
+    S->timing = false;
+    rc = step_impl(S, b->w[i], &b->f[i], true);
+    S->stream = saved[i];
+    S->timing = timing[i];
+    b->w[i]->step = steps[i];   // capture executes nothing
+    if (rc == AFQMC_OK && (!hip_ok(hipEventRecord(b->join[i], b->branch[i]), "join record") ||
+                           !hip_ok(hipStreamWaitEvent(b->cap, b->join[i], 0), "join wait")))
+      rc = AFQMC_E_HIP;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (rc == AFQMC_OK && !hip_ok(e, "end capture")) rc = AFQMC_E_HIP;
+  if (rc == AFQMC_OK && !hip_ok(hipGraphInstantiate(exec, g, nullptr, nullptr, 0), "instantiate"))
+    rc = AFQMC_E_HIP;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int afqmc_batch_create(int32_t n, const afqmc_sys* systems, afqmc_walkers* const* walkers,
+                       void* stream, afqmc_batch* out) {
+  if (!out || n < 1 || !systems || !walkers) return AFQMC_E_ARG;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!systems[i] || !walkers[i]) return AFQMC_E_ARG;
+    const int rc = check_walkers(systems[i], walkers[i]);
+    if (rc) return rc;
+    for (int j = 0; j < i; ++j)
+      if (walkers[j] == walkers[i] || walkers[j]->workspace == walkers[i]->workspace ||
+          walkers[j]->U == walkers[i]->U)
+        return AFQMC_E_ARG;   // one walker population appears twice
+  }
+  afqmc_batch_s* b = new (std::nothrow) afqmc_batch_s();
+  if (!b) return AFQMC_E_NOMEM;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < n; ++i) {
+    b->sys.push_back(systems[i]);
+    b->w.push_back(walkers[i]);
+    b->expected.push_back(walkers[i]->step);
+  }
+  b->f.resize(n);
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->in_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    batch_free(b);
+    return AFQMC_E_HIP;
+  }
+  for (int i = 0; i < n; ++i) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      batch_free(b);
+      return AFQMC_E_HIP;
+    }
+    b->branch.push_back(st);
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      batch_free(b);
+      return AFQMC_E_HIP;
+    }
+    b->join.push_back(ev);
+  }
+  // the systems' earlier work (init, measure) completes before the batch stream runs
+  for (int i = 0; i < n; ++i)
+    if (hipStreamSynchronize(systems[i]->stream) != hipSuccess) {
+      batch_free(b);
+      return AFQMC_E_HIP;
+    }
+  *out = b;
+  return AFQMC_OK;
+}
+
+int afqmc_batch_step(afqmc_batch b, const afqmc_fields* fields) {
+  if (!b || !fields) return AFQMC_E_ARG;
+  const size_t n = b->sys.size();
+  bool same = b->have_fields;
+  for (size_t i = 0; i < n; ++i) {
+    if (fields[i].x != nullptr || !std::isnan(fields[i].u_comb)) return AFQMC_E_ARG;
+    if (!same || fields[i].seed != b->f[i].seed || fields[i].job_id != b->f[i].job_id) same = false;
+  }
+  if (!same) {
+    batch_drop_graphs(b);
+    for (size_t i = 0; i < n; ++i) b->f[i] = fields[i];
+    b->have_fields = true;
+  }
+  std::vector<uint8_t> key(n);
+  for (size_t i = 0; i < n; ++i) {
+    const afqmc_params& p = b->sys[i]->p;
+    const int64_t k = b->w[i]->step;
+    key[i] = (uint8_t)((p.qr_period > 0 && (k + 1) % p.qr_period == 0 ? 1 : 0) |
+                       (p.pop_period > 0 && (k + 1) % p.pop_period == 0 ? 2 : 0));
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : b->graphs)
+    if (g.first == key) exec = g.second;
+  if (!exec) {
+    const int rc = batch_capture(b, &exec);
+    if (rc) return rc;
+    b->graphs.emplace_back(key, exec);
+  }
+  // the graph runs on the owned stream, after the caller's stream's earlier work
+  if (!hip_ok(hipEventRecord(b->in_ev, b->stream), "in record") ||
+      !hip_ok(hipStreamWaitEvent(b->cap, b->in_ev, 0), "in wait"))
+    return AFQMC_E_HIP;
+  // device counters of walkers that were stepped or edited outside the batch
+  for (size_t i = 0; i < n; ++i)
+    if (b->w[i]->step != b->expected[i]) {
+      const WsLayout L = layout(b->sys[i], (size_t)b->w[i]->n_walkers);
+      hipLaunchKernelGGL(k_step_set, dim3(1), dim3(1), 0, b->cap,
+                         at<int64_t>(b->w[i]->workspace, L.dstep), b->w[i]->step);
+    }
+  if (!hip_ok(hipGraphLaunch(exec, b->cap), "graph launch") ||
+      !hip_ok(hipEventRecord(b->out_ev, b->cap), "out record") ||
+      !hip_ok(hipStreamWaitEvent(b->stream, b->out_ev, 0), "out wait"))
+    return AFQMC_E_HIP;
+  for (size_t i = 0; i < n; ++i) {
+    b->w[i]->step += 1;
+    b->expected[i] = b->w[i]->step;
+  }
+  return AFQMC_OK;
+}
+
+int afqmc_batch_destroy(afqmc_batch b) {
+  if (!b) return AFQMC_E_ARG;
+  (void)hipStreamSynchronize(b->cap);
+  (void)hipStreamSynchronize(b->stream);
+  batch_free(b);
   return AFQMC_OK;
 }
 

@@ -213,9 +213,12 @@ __global__ void __launch_bounds__(256) k_energy_assemble_multi(
 __global__ void __launch_bounds__(256) k_fields(
     int nw, int G, double s, double fb_cap, const cd* __restrict__ tcur,
     const double* __restrict__ weight, const int64_t* __restrict__ walker_id, uint64_t seed,
-    uint64_t job, int64_t step, const double* __restrict__ xin, cd* __restrict__ y,
+    uint64_t job, int64_t step_arg, const int64_t* __restrict__ dstep,
+    const double* __restrict__ xin, cd* __restrict__ y,
     double* __restrict__ xout, unsigned* __restrict__ status, cd* __restrict__ fbterm,
     const double* __restrict__ lbar, cd* __restrict__ mfterm) {
+  // the step number comes from the device counter when one is given (graph replays)
+  const int64_t step = dstep ? *dstep : step_arg;
   const int nblk = (G + 3) / 4;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)nw * nblk) return;
@@ -581,7 +584,9 @@ __global__ void k_measure_finish(int nw, double sf, const cd* __restrict__ logde
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_comb_select(int nw, const double* __restrict__ weight,
                                                       double u_given, uint64_t seed, uint64_t job,
-                                                      int64_t step, double* __restrict__ csum,
+                                                      int64_t step_arg,
+                                                      const int64_t* __restrict__ dstep,
+                                                      double* __restrict__ csum,
                                                       int* __restrict__ parent,
                                                       double* __restrict__ wnew,
                                                       unsigned* __restrict__ status) {
@@ -598,6 +603,7 @@ __global__ void __launch_bounds__(1024) k_comb_select(int nw, const double* __re
   if (threadIdx.x == 0) {
     double u = u_given;
     if (isnan(u)) {
+      const int64_t step = dstep ? *dstep : step_arg;
       const u64x4 r = philox4x64_10(0ull, 0ull, (uint64_t)step, 1ull, seed, job);
       u = u64_unit(r.v[0]);
     }
@@ -641,6 +647,30 @@ __global__ void __launch_bounds__(1024) k_comb_select(int nw, const double* __re
 }
 
 // Gather walker state from a snapshot by parent index.  One block per walker.
+// Snapshot of every walker's state before the comb overwrites it (one block per walker).
+__global__ void __launch_bounds__(256) k_comb_snapshot(
+    int nw, int rowlen /*ntot*M*/, int G, const cd* __restrict__ U, const cd* __restrict__ tcur,
+    const cd* __restrict__ e_loc, const double* __restrict__ arg_ovlp,
+    const double* __restrict__ log_ovlp, const double* __restrict__ phase, cd* __restrict__ Usnap,
+    cd* __restrict__ tsnap, cd* __restrict__ esnap, double* __restrict__ asnap,
+    double* __restrict__ lsnap, double* __restrict__ psnap) {
+  const int j = blockIdx.x;
+  for (int e = threadIdx.x; e < rowlen; e += blockDim.x)
+    Usnap[(size_t)j * rowlen + e] = U[(size_t)j * rowlen + e];
+  for (int e = threadIdx.x; e < G; e += blockDim.x) tsnap[(size_t)j * G + e] = tcur[(size_t)j * G + e];
+  if (threadIdx.x == 0) {
+    esnap[j] = e_loc[j];
+    asnap[j] = arg_ovlp[j];
+    lsnap[j] = log_ovlp[j];
+    if (phase) psnap[j] = phase[j];
+  }
+}
+
+// Device copy of the walkers' step counter: set from the host value, or advanced by one at
+// the end of a replayed step.
+__global__ void k_step_set(int64_t* __restrict__ dstep, int64_t v) { *dstep = v; }
+__global__ void k_step_advance(int64_t* __restrict__ dstep) { *dstep += 1; }
+
 __global__ void __launch_bounds__(256) k_comb_gather(
     int nw, int rowlen /*ntot*M*/, int G, const int* __restrict__ parent,
     const double* __restrict__ wnew, const cd* __restrict__ Usnap, const cd* __restrict__ tsnap,

@@ -49,6 +49,15 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.afqmc_workspace_bytes(None, 4, C.byref(b)) == -1
 
 
+def test_batch_argument_checks_precede_device_work():
+    lib = pkg.load()
+    out = C.c_void_p()
+    assert lib.afqmc_batch_create(0, None, None, None, C.byref(out)) == -1
+    assert lib.afqmc_batch_create(2, None, None, None, C.byref(out)) == -1
+    assert lib.afqmc_batch_step(None, None) == -1
+    assert lib.afqmc_batch_destroy(None) == -1
+
+
 def test_multidet_argument_checks_precede_device_work():
     """n_det outside 1..1024, a missing or non-finite coefficient array are argument errors."""
     import numpy as np
