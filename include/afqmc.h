@@ -213,6 +213,30 @@ AFQMC_API int afqmc_measure(afqmc_sys s, afqmc_walkers* w);
  * Asynchronous; allocates nothing. */
 AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
 
+/* Tile shapes of the local-energy contraction (the dominant kernel).  The register-resident
+ * FP32 / BF16x3 kernel takes W = 4 or 2 walkers per workgroup (W = 2 gives small walker
+ * populations twice the workgroups); the wide kernel takes one walker per workgroup and splits
+ * Theta's columns over its wavefronts.  Every variant computes the same quantities.
+ *   AFQMC_TILE_DEFAULT  W = 4 where the shape fits it (N <= 32, M <= 128), else wide
+ *   AFQMC_TILE_W4, AFQMC_TILE_W2, AFQMC_TILE_WIDE  (wide needs N_P >= 32, i.e. N > 16 or M > 128)
+ * The FP64 mode has one contraction kernel per shape and accepts only the default. */
+#define AFQMC_TILE_DEFAULT 0
+#define AFQMC_TILE_W4 1
+#define AFQMC_TILE_W2 2
+#define AFQMC_TILE_WIDE 3
+
+/* Autotuner: times every variant valid for the system's shape on these walkers (initialized
+ * or measured; one untimed and three timed launches each, on the system's stream, writing only
+ * workspace partial sums), keeps the fastest for every later step and returns it in *tile
+ * (and its time per launch in *ms if ms != NULL).  With reuse != 0 a shape tuned before in the
+ * process (same device, precision, M, N_up, N_dn, N_g, determinants and walker count) takes
+ * the stored choice without timing (*ms = -1).  Synchronizes the stream. */
+AFQMC_API int afqmc_autotune(afqmc_sys s, afqmc_walkers* w, int32_t reuse, int32_t* tile,
+                             double* ms);
+/* Force a variant (AFQMC_E_UNSUPPORTED if it does not fit the shape) / read the one in use. */
+AFQMC_API int afqmc_set_tile(afqmc_sys s, int32_t tile);
+AFQMC_API int afqmc_get_tile(afqmc_sys s, int32_t* tile);
+
 /* Batches: many systems (uneven M, N, N_g and walker counts) stepped together, one graph
  * launch per step.  Each system keeps its own walkers, fields stream and parameters; the batch
  * captures one afqmc_step of every system into a HIP graph -- each system on a branch stream

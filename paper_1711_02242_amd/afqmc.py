@@ -182,6 +182,25 @@ class System:
         L.check(self.lib.afqmc_get_status(self.handle, C.byref(st), int(clear)), "afqmc_get_status")
         return int(st.value)
 
+    # ---------------------------------------------------------------- tiles
+    def autotune(self, wk: "Walkers", reuse: bool = True):
+        """Time the contraction variants on these walkers, keep the fastest; returns
+        (tile name, ms per launch or -1 when a stored choice was reused)."""
+        t = C.c_int32()
+        ms = C.c_double()
+        L.check(self.lib.afqmc_autotune(self.handle, wk.c_ref(), int(reuse), C.byref(t),
+                                        C.byref(ms)), "afqmc_autotune")
+        return {v: k for k, v in L.TILES.items()}[t.value], ms.value
+
+    def set_tile(self, tile: str) -> None:
+        L.check(self.lib.afqmc_set_tile(self.handle, L.TILES[tile]), "afqmc_set_tile")
+
+    @property
+    def tile(self) -> str:
+        t = C.c_int32()
+        L.check(self.lib.afqmc_get_tile(self.handle, C.byref(t)), "afqmc_get_tile")
+        return {v: k for k, v in L.TILES.items()}[t.value]
+
     # ---------------------------------------------------------------- timing
     def kernel_timing(self, enable: bool) -> None:
         L.check(self.lib.afqmc_kernel_timing(self.handle, int(enable)), "afqmc_kernel_timing")
@@ -242,11 +261,18 @@ class Batch:
     """Systems with their walkers stepped together by one graph launch per step
     (``afqmc_batch_*``).  Keeps the systems and walkers alive while it exists."""
 
-    def __init__(self, pairs, stream=None):
+    def __init__(self, pairs, stream=None, autotune: bool = False):
         torch = _torch()
         self.lib = L.load()
         self.pairs = list(pairs)
         n = len(self.pairs)
+        self.tiles = []
+        for gs, wk in self.pairs:
+            if autotune:
+                self.tiles.append(gs.autotune(wk)[0])
+                gs.measure(wk)   # cached traces and E_L from the tile now in use
+            else:
+                self.tiles.append(gs.tile)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         sysv = (C.c_void_p * n)(*[gs.handle.value for gs, _ in self.pairs])
         for _, wk in self.pairs:

@@ -6,7 +6,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -59,6 +62,7 @@ struct afqmc_sys_s {
   int n_det = 1;
   bool multi = false;
   double* coef = nullptr;  // [n_det][2] expansion coefficients A_d
+  int tile = 0;            // contraction variant (TILE_*), set by afqmc_autotune / afqmc_set_tile
   size_t device_bytes = 0;
   // timing
   bool timing = false;
@@ -334,7 +338,7 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
   } else {
     Timer tm(S, KG_CONTRACT);
     HIPCHK(mfma_contract(S->mt, S->stream, w->n_walkers, S->n_det, S->G, at<void>(ws, L.thetaP),
-                         w->weight, at<cd>(ws, L.tpart), at<cd>(ws, L.exch)));
+                         w->weight, at<cd>(ws, L.tpart), at<cd>(ws, L.exch), S->tile));
   }
   if (S->multi) {
     Timer tm(S, KG_ASSEMBLE);
@@ -1192,6 +1196,91 @@ int afqmc_modified_cholesky(const double* eri, int32_t M, double delta, int32_t 
   if (!h.done) return AFQMC_E_STATE;
   *n_vectors = h.count;
   if (converged) *converged = h.count < max_vectors || h.dmax < delta ? 1 : 0;
+  return AFQMC_OK;
+}
+
+int afqmc_set_tile(afqmc_sys s, int32_t tile) {
+  if (!s || tile < 0 || tile >= TILE_COUNT) return AFQMC_E_ARG;
+  if (!mfma_tile_valid(s->mt, tile)) return AFQMC_E_UNSUPPORTED;
+  s->tile = tile;
+  return AFQMC_OK;
+}
+
+int afqmc_get_tile(afqmc_sys s, int32_t* tile) {
+  if (!s || !tile) return AFQMC_E_ARG;
+  *tile = s->tile;
+  return AFQMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Shapes already tuned in this process: (device, precision, M, N_up, N_dn, G, n_det, n_walkers)
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int>;
+std::map<TuneKey, int> g_tuned;
+std::mutex g_tuned_mu;
+}  // namespace
+
+extern "C" {
+
+int afqmc_autotune(afqmc_sys s, afqmc_walkers* w, int32_t reuse, int32_t* tile, double* ms) {
+  if (!s || !tile) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  const TuneKey key{s->device, s->p.precision, s->M, s->nup, s->ndn, s->G, s->n_det, w->n_walkers};
+  if (reuse) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      s->tile = it->second;
+      *tile = it->second;
+      if (ms) *ms = -1.0;
+      return AFQMC_OK;
+    }
+  }
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  void* ws = w->workspace;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return AFQMC_E_HIP;
+  }
+  int best = TILE_DEFAULT;
+  double best_ms = 0.0;
+  bool any = false;
+  constexpr int REPS = 3;
+  for (int t = TILE_W4; t < TILE_COUNT && rc == AFQMC_OK; ++t) {
+    if (!mfma_tile_valid(s->mt, t)) continue;
+    // one untimed launch, then REPS timed ones; only the workspace partial sums are written
+    for (int r = 0; r <= REPS && rc == AFQMC_OK; ++r) {
+      if (r == 1 && hipEventRecord(a, s->stream) != hipSuccess) rc = AFQMC_E_HIP;
+      if (rc == AFQMC_OK &&
+          mfma_contract(s->mt, s->stream, w->n_walkers, s->n_det, s->G, at<void>(ws, L.thetaP),
+                        w->weight, at<cd>(ws, L.tpart), at<cd>(ws, L.exch), t) != hipSuccess)
+        rc = AFQMC_E_HIP;
+    }
+    float el = 0.f;
+    if (rc == AFQMC_OK && (hipEventRecord(b, s->stream) != hipSuccess ||
+                           hipEventSynchronize(b) != hipSuccess ||
+                           hipEventElapsedTime(&el, a, b) != hipSuccess))
+      rc = AFQMC_E_HIP;
+    if (rc == AFQMC_OK && (!any || el / REPS < best_ms)) {
+      best = t;
+      best_ms = el / REPS;
+      any = true;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  s->tile = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[key] = best;
+  }
+  *tile = best;
+  if (ms) *ms = any ? best_ms : 0.0;
   return AFQMC_OK;
 }
 

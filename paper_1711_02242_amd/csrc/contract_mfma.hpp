@@ -8,19 +8,19 @@
 //   Omega = Lh^g_s Theta_s     (N x N complex = real N x M times complex M x N)
 //   tpart[w][s][g] = tr Omega,  exch[w][s] = sum_g tr(Omega Omega).
 // One wavefront owns one walker-spin and keeps [Re Theta | Im Theta] (M x 2N)
-// in registers for the whole kernel; the four wavefronts of a workgroup (four
-// walkers of the same spin) stream the shared tiles Lh^g_s (N x M) through
-// double-buffered LDS.  Per g the wave runs the MFMA chain over K = M for the
+// in registers for the whole kernel; the WPB wavefronts of a workgroup (WPB
+// walkers of the same spin, WPB = 4 or 2) stream the shared tiles Lh^g_s (N x M)
+// through double-buffered LDS.  Per g the wave runs the MFMA chain over K = M for the
 // Re and Im halves, then an LDS transpose gives every lane the partner element
 // Omega_ji of each Omega_ij it holds.  Per-g partial products are summed in
 // FP32 and accumulated across g in FP64.
 #pragma once
 
 // ---------------------------------------------------------------------------
-// The contraction kernel.  Grid: (ceil(nw / 4), 2 spins); 256 threads.
+// The contraction kernel.  Grid: (ceil(nw / WPB), 2 n_det); 64 WPB threads.
 // ---------------------------------------------------------------------------
-template <int NP, bool BF16>
-__global__ void __launch_bounds__(256, 2) k_contract_mfma(
+template <int NP, bool BF16, int WPB>
+__global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
     int nw, int G, int nup, int ndn, int KP, const void* __restrict__ Lp_,
     const void* __restrict__ thp_, const double* __restrict__ weight, cd* __restrict__ tpart,
     cd* __restrict__ exch) {
@@ -30,7 +30,8 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
   const int N = s ? ndn : nup;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int w = blockIdx.x * MFMA_WAVES + wave;
+  constexpr int NT = 64 * WPB;
+  const int w = blockIdx.x * WPB + wave;
   const int wd = w * n_det + dd;   // (walker, determinant) slot of the outputs
   const bool active = (w < nw) && (N > 0) && (weight[w] > 0.0);
   if (N == 0) {
@@ -59,20 +60,20 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma(
   // ---- copy of one g-tile global -> LDS, 16 bytes per thread per chunk
   const int chunks_per_row = KP * ESZ / 16;
   const int nchunks = NP * PLANES * chunks_per_row;
-  constexpr int MAXCH = (32 * MFMA_KMAX * 4 + 255 * 16) / (256 * 16);  // 4
+  constexpr int MAXCH = (32 * MFMA_KMAX * 4 / 16 + NT - 1) / NT;  // 4 (WPB 4), 8 (WPB 2)
   u32x4 pre[MAXCH];
 #define AFQMC_GLOAD(G_)                                                                        \
   do {                                                                                         \
     const u32x4* src_ = reinterpret_cast<const u32x4*>(Lbase + (size_t)(G_) * tile_elems * ESZ); \
     _Pragma("unroll") for (int c_ = 0; c_ < MAXCH; ++c_) {                                     \
-      const int ch_ = tid + c_ * 256;                                                          \
+      const int ch_ = tid + c_ * NT;                                                           \
       pre[c_] = src_[ch_ < nchunks ? ch_ : 0];                                                 \
     }                                                                                          \
   } while (0)
 #define AFQMC_LSTORE(DST_)                                                                     \
   do {                                                                                         \
     _Pragma("unroll") for (int c_ = 0; c_ < MAXCH; ++c_) {                                     \
-      const int ch_ = tid + c_ * 256;                                                          \
+      const int ch_ = tid + c_ * NT;                                                           \
       if (ch_ < nchunks) {                                                                     \
         const int row_ = ch_ / chunks_per_row;                                                 \
         const int col_ = (ch_ % chunks_per_row) * (16 / ESZ);                                  \

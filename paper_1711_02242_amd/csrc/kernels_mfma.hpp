@@ -37,7 +37,8 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MFMA_KMAX = 128;   // K limit of the register-resident contraction kernels
 constexpr int WIDE_KMAX = 224;   // K limit of the wide (workgroup-per-walker) kernel
-constexpr int MFMA_WAVES = 4;
+// Contraction kernel variants (tile shapes) the autotuner chooses among.
+enum { TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_COUNT = 4 };
 
 struct MfmaTables {
   bool enabled = false;
@@ -152,12 +153,25 @@ inline void mfma_free_tables(MfmaTables& t) {
 #include "contract_mfma.hpp"
 #include "contract_wide.hpp"
 
-inline size_t mfma_contract_lds_bytes(const MfmaTables& t) {
+inline size_t mfma_contract_lds_bytes(const MfmaTables& t, int wpb) {
   const bool bf = t.precision == AFQMC_BF16X3;
   const int esz = bf ? 2 : 4, planes = bf ? 2 : 1;
   const int lda = t.KP + (bf ? 8 : 4);
   const size_t tile = (size_t)t.NP * lda * esz * planes;
-  return 2 * tile + (size_t)MFMA_WAVES * 2 * t.NP * (t.NP + 4) * 4;
+  return 2 * tile + (size_t)wpb * 2 * t.NP * (t.NP + 4) * 4;
+}
+
+// Whether a contraction variant can run on these tables.
+inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
+  if (!t.enabled) return false;
+  if (t.precision == AFQMC_FP64) return tile == TILE_DEFAULT;
+  switch (tile) {
+    case TILE_DEFAULT: return true;
+    case TILE_W4:
+    case TILE_W2: return !t.wide;
+    case TILE_WIDE: return t.NP >= 32 && t.KP <= WIDE_KMAX;
+    default: return false;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +342,8 @@ inline size_t mfma_f64_contract_lds_bytes(const MfmaTables& t) {
 }
 
 inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int n_det, int G,
-                                const void* thetaP, const double* weight, cd* tpart, cd* exch) {
+                                const void* thetaP, const double* weight, cd* tpart, cd* exch,
+                                int tile = TILE_DEFAULT) {
   if (t.precision == AFQMC_FP64) {
     const size_t shm = mfma_f64_contract_lds_bytes(t);
     dim3 grid((nw + 1) / 2, 2 * n_det);
@@ -346,7 +361,8 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
     return hipGetLastError();
   }
   const bool bf = t.precision == AFQMC_BF16X3;
-  if (t.wide) {
+  if (!mfma_tile_valid(t, tile)) tile = TILE_DEFAULT;
+  if (t.wide || tile == TILE_WIDE) {
     dim3 grid(nw, 2 * n_det);
 #define LAUNCH_WIDE(NPV, BFV)                                                                   \
   do {                                                                                          \
@@ -369,21 +385,32 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
 #undef LAUNCH_WIDE
     return hipGetLastError();
   }
-  const size_t shm = mfma_contract_lds_bytes(t);
-  dim3 grid((nw + MFMA_WAVES - 1) / MFMA_WAVES, 2 * n_det);
-#define LAUNCH_CONTRACT(NPV, BFV)                                                               \
+  const int wpb = tile == TILE_W2 ? 2 : 4;
+  const size_t shm = mfma_contract_lds_bytes(t, wpb);
+  dim3 grid((nw + wpb - 1) / wpb, 2 * n_det);
+#define LAUNCH_CONTRACT(NPV, BFV, WPBV)                                                         \
   do {                                                                                          \
-    (void)hipFuncSetAttribute((const void*)k_contract_mfma<NPV, BFV>,                           \
+    (void)hipFuncSetAttribute((const void*)k_contract_mfma<NPV, BFV, WPBV>,                     \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);            \
-    hipLaunchKernelGGL((k_contract_mfma<NPV, BFV>), grid, dim3(256), shm, st, nw, G, t.nup,     \
-                       t.ndn, t.KP, (const void*)t.Lp, thetaP, weight, tpart, exch);            \
+    hipLaunchKernelGGL((k_contract_mfma<NPV, BFV, WPBV>), grid, dim3(64 * WPBV), shm, st, nw,   \
+                       G, t.nup, t.ndn, t.KP, (const void*)t.Lp, thetaP, weight, tpart, exch);  \
   } while (0)
-  if (t.NP == 32) {
-    if (bf) LAUNCH_CONTRACT(32, true);
-    else LAUNCH_CONTRACT(32, false);
+  if (wpb == 4) {
+    if (t.NP == 32) {
+      if (bf) LAUNCH_CONTRACT(32, true, 4);
+      else LAUNCH_CONTRACT(32, false, 4);
+    } else {
+      if (bf) LAUNCH_CONTRACT(16, true, 4);
+      else LAUNCH_CONTRACT(16, false, 4);
+    }
   } else {
-    if (bf) LAUNCH_CONTRACT(16, true);
-    else LAUNCH_CONTRACT(16, false);
+    if (t.NP == 32) {
+      if (bf) LAUNCH_CONTRACT(32, true, 2);
+      else LAUNCH_CONTRACT(32, false, 2);
+    } else {
+      if (bf) LAUNCH_CONTRACT(16, true, 2);
+      else LAUNCH_CONTRACT(16, false, 2);
+    }
   }
 #undef LAUNCH_CONTRACT
   return hipGetLastError();

@@ -74,6 +74,31 @@ def test_batch_equals_systems_stepped_alone():
     b.close()
 
 
+def test_autotuned_batch_equals_systems_alone_with_the_same_tiles():
+    import paper_1711_02242_amd as afq
+    steps = 6
+    specs = _systems()
+    pairs = []
+    for name, make, nw, seed in specs:
+        gs = make()
+        wk = gs.walkers(nw)
+        gs.init(wk)
+        pairs.append((gs, wk))
+    b = afq.Batch(pairs, autotune=True)
+    log(f"tiles {b.tiles}")
+    for _ in range(steps):
+        b.step([sp[3] for sp in specs])
+    for (name, make, nw, seed), tile, (gsb, wkb) in zip(specs, b.tiles, pairs):
+        gs = make()
+        gs.set_tile(tile)
+        wk = gs.walkers(nw)
+        gs.init(wk)
+        for _ in range(steps):
+            gs.step(wk, seed=seed)
+        _assert_same(_state(wkb), _state(wk), name)
+    b.close()
+
+
 def test_batch_mixed_with_single_steps():
     """Steps taken outside the batch between batch steps keep the device step counter right."""
     import paper_1711_02242_amd as afq
