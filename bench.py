@@ -112,6 +112,79 @@ def cpu_baseline(s, args):
                       f"{dt:.1f} s)"}
 
 
+def batch_leg(args):
+    """Uneven batch: 24 systems (M uniform on 24..160, N = M/4, N_g = 6M, 128-2048 walkers),
+    FP32 bulk.  The same systems and walkers are stepped (a) by per-system launches with the
+    default tiles, one system after the other on one stream, and (b) by one graph launch per
+    step with autotuned tiles.  Returns the comparison (whole-batch walker-steps/s)."""
+    import torch
+
+    import paper_1711_02242_amd as afq
+    from synthetic import batch_workload, gen_system
+    specs = batch_workload(args.batch_systems)
+    t0 = time.perf_counter()
+    pairs = []
+    for sp in specs:
+        s = gen_system(sp["M"], sp["N"], sp["n_chol"], seed=sp["seed"])
+        gs = afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
+        wk = gs.walkers(sp["n_walkers"])
+        gs.init(wk)
+        pairs.append((gs, wk))
+        del s
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    nw_total = sum(sp["n_walkers"] for sp in specs)
+    flops = sum(contraction_flops(sp["M"], sp["N"], sp["N"], sp["n_chol"], sp["n_walkers"])
+                for sp in specs)
+    eprint(f"bench: batch of {len(specs)} systems, {nw_total} walkers, setup {t_setup:.1f} s")
+
+    def per_system(nsteps):
+        for _ in range(nsteps):
+            for (gs, wk), sp in zip(pairs, specs):
+                gs.step(wk, seed=sp["seed"])
+
+    per_system(args.batch_warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_system(args.batch_steps)
+    torch.cuda.synchronize()
+    dt_a = time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    b = afq.Batch(pairs, autotune=True)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    seeds = [sp["seed"] for sp in specs]
+    for _ in range(max(args.batch_warmup, 5)):   # captures the graphs of every phase
+        b.step(seeds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        b.step(seeds)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    tiles = {}
+    for t in b.tiles:
+        tiles[t] = tiles.get(t, 0) + 1
+    b.close()
+    for gs, _ in pairs:
+        gs.close()
+    va = nw_total * args.batch_steps / dt_a
+    vb = nw_total * args.batch_steps / dt_b
+    eprint(f"bench: batch per-system {1e3 * dt_a / args.batch_steps:.2f} ms/step, "
+           f"graph+autotune {1e3 * dt_b / args.batch_steps:.2f} ms/step")
+    return {"workload": f"{len(specs)} synthetic systems, M uniform on 24..160, N=M/4, "
+                        "N_g=6M, 128-2048 walkers (log-uniform), fp32 bulk, dtau=0.005",
+            "systems": len(specs), "walkers_total": nw_total,
+            "steps": args.batch_steps, "contraction_tflop_per_step": round(flops / 1e12, 3),
+            "per_system_launches": {"value": round(va, 1), "unit": "walker-steps/s",
+                                    "ms_per_step": round(1e3 * dt_a / args.batch_steps, 3)},
+            "graph_autotuned": {"value": round(vb, 1), "unit": "walker-steps/s",
+                                "ms_per_step": round(1e3 * dt_b / args.batch_steps, 3),
+                                "tiles": tiles, "autotune_s": round(t_tune, 2)},
+            "speedup": round(vb / va, 3), "setup_s": round(t_setup, 1)}
+
+
 def el_error(s, args, gs, wk):
     """Per-walker local-energy error of this precision on the current walkers: against the
     GPU FP64 path on every walker, and against the FP64 oracle on a sample."""
@@ -163,6 +236,11 @@ def main():
     ap.add_argument("--oracle-sample", type=int, default=4)
     ap.add_argument("--no-closed-shell", action="store_true",
                     help="skip the closed-shell one-spin measurement")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven multi-system batch comparison")
+    ap.add_argument("--batch-systems", type=int, default=24)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -241,6 +319,9 @@ def main():
                                "ms_per_step": round(1e3 * dt3 / args.steps, 3),
                                "e_mix": e3[0] / e3[2]}
         g3.close()
+
+    if not args.no_batch:
+        out["batch"] = batch_leg(args)
 
     if not args.no_cpu:
         cb = cpu_baseline(s, args)

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -240,6 +241,28 @@ bool host_inverse(std::vector<double>& a, int n) {
   }
   a = inv;
   return true;
+}
+
+// Runs body(i, thread) for i in [0, n) on up to 16 host threads (setup precompute only).
+template <class F>
+void parallel_for(int n, F body) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nt = std::max(1, std::min({n, 16, (int)(hw ? hw : 1)}));
+  if (nt == 1) {
+    for (int i = 0; i < n; ++i) body(i, 0);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t] {
+      for (int i = t; i < n; i += nt) body(i, t);
+    });
+  for (auto& th : pool) th.join();
+}
+
+int setup_threads(int n) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return std::max(1, std::min({n, 16, (int)(hw ? hw : 1)}));
 }
 
 template <typename T>
@@ -486,18 +509,25 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
   (void)hipGetDevice(&S->device);
   const int nt = S->ntot;
 
-  // v0 = h1 - 1/2 sum_g L^g L^g  (eq:mcd1)
+  // v0 = h1 - 1/2 sum_g L^g L^g  (eq:mcd1); per-thread partial sums over g, then reduced
   std::vector<double> v0(h1, h1 + (size_t)M * M);
-  for (int g = 0; g < G; ++g) {
-    const double* Lg = L_chol + (size_t)g * M * M;
-    for (int i = 0; i < M; ++i)
-      for (int k = 0; k < M; ++k) {
-        const double a = 0.5 * Lg[(size_t)i * M + k];
-        if (a == 0.0) continue;
-        const double* row = Lg + (size_t)k * M;
-        double* dst = v0.data() + (size_t)i * M;
-        for (int j = 0; j < M; ++j) dst[j] -= a * row[j];
-      }
+  {
+    const int nthr = setup_threads(G);
+    std::vector<std::vector<double>> part(nthr, std::vector<double>((size_t)M * M, 0.0));
+    parallel_for(G, [&](int g, int t) {
+      const double* Lg = L_chol + (size_t)g * M * M;
+      double* acc = part[t].data();
+      for (int i = 0; i < M; ++i)
+        for (int k = 0; k < M; ++k) {
+          const double a = 0.5 * Lg[(size_t)i * M + k];
+          if (a == 0.0) continue;
+          const double* row = Lg + (size_t)k * M;
+          double* dst = acc + (size_t)i * M;
+          for (int j = 0; j < M; ++j) dst[j] += a * row[j];
+        }
+    });
+    for (int t = 0; t < nthr; ++t)
+      for (size_t e = 0; e < v0.size(); ++e) v0[e] -= part[t][e];
   }
   for (int i = 0; i < M; ++i)
     for (int j = i + 1; j < M; ++j) {
@@ -519,21 +549,23 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
   // Half rotation (eq:precomputing2) per determinant:
   // Lh[d][g][c][q] = sum_p V[d][c][p] L^g_pq; ht[d][c][q] = sum_p V[d][c][p] h_pq
   std::vector<double> Lh((size_t)n_det * G * nt * M, 0.0), ht((size_t)n_det * nt * M, 0.0);
-  for (int d = 0; d < n_det; ++d) {
+  parallel_for(n_det * G, [&](int dg, int) {
+    const int d = dg / (G > 0 ? G : 1), g = dg % (G > 0 ? G : 1);
     const double* vd = Vr.data() + (size_t)d * nt * M;
-    for (int g = 0; g < G; ++g) {
-      const double* Lg = L_chol + (size_t)g * M * M;
-      for (int c = 0; c < nt; ++c) {
-        double* dst = Lh.data() + (((size_t)d * G + g) * nt + c) * M;
-        const double* vc = vd + (size_t)c * M;
-        for (int q = 0; q < M; ++q) {
-          const double a = vc[q];
-          if (a == 0.0) continue;
-          const double* row = Lg + (size_t)q * M;
-          for (int j = 0; j < M; ++j) dst[j] += a * row[j];
-        }
+    const double* Lg = L_chol + (size_t)g * M * M;
+    for (int c = 0; c < nt; ++c) {
+      double* dst = Lh.data() + (((size_t)d * G + g) * nt + c) * M;
+      const double* vc = vd + (size_t)c * M;
+      for (int q = 0; q < M; ++q) {
+        const double a = vc[q];
+        if (a == 0.0) continue;
+        const double* row = Lg + (size_t)q * M;
+        for (int j = 0; j < M; ++j) dst[j] += a * row[j];
       }
     }
+  });
+  for (int d = 0; d < n_det; ++d) {
+    const double* vd = Vr.data() + (size_t)d * nt * M;
     double* hd = ht.data() + (size_t)d * nt * M;
     for (int c = 0; c < nt; ++c)
       for (int q = 0; q < M; ++q) {
@@ -573,10 +605,11 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     double e1 = 0.0, jsum = 0.0, xsum = 0.0;
     for (int c = 0; c < nt; ++c)
       for (int q = 0; q < M; ++q) e1 += ht[(size_t)c * M + q] * th[(size_t)c * M + q];
-    std::vector<double> om;
     tvec.assign((size_t)G, 0.0);
-    for (int g = 0; g < G; ++g) {
-      double t = 0.0;
+    std::vector<double> xg((size_t)G, 0.0);
+    parallel_for(G, [&](int g, int) {
+      std::vector<double> om;
+      double t = 0.0, x = 0.0;
       for (int s = 0; s < 2; ++s) {
         const int N = s == 0 ? nup : ndn, off = s == 0 ? 0 : nup;
         om.assign((size_t)N * N, 0.0);
@@ -590,11 +623,15 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
           }
         for (int r = 0; r < N; ++r) {
           t += om[(size_t)r * N + r];
-          for (int c = 0; c < N; ++c) xsum += om[(size_t)r * N + c] * om[(size_t)c * N + r];
+          for (int c = 0; c < N; ++c) x += om[(size_t)r * N + c] * om[(size_t)c * N + r];
         }
       }
-      jsum += t * t;
       tvec[g] = t;
+      xg[g] = x;
+    });
+    for (int g = 0; g < G; ++g) {   // fixed order
+      jsum += tvec[g] * tvec[g];
+      xsum += xg[g];
     }
     S->e_hf = h0 + e1 + 0.5 * (jsum - xsum);
   }

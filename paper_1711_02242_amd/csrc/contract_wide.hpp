@@ -8,16 +8,17 @@
 // (K up to 224) in registers for the whole kernel and computes the column block
 // Omega[:, 16 j .. 16 j + 15] = Lh^g Theta[:, block] for every g on
 // v_mfma_f32_16x16x4_f32 (BF16x3: v_mfma_f32_16x16x32_bf16, three products
-// hi*hi + hi*lo + lo*hi).  The Lh^g tiles (NPW x KP) are double-buffered in LDS and
-// shared by the waves; the copy of tile g + 1 is interleaved chunk by chunk with
-// the MFMA chain of tile g (one 16-byte chunk per thread per K chunk, so only one
-// or two chunks are in flight in registers).  Omega is then written column-major to LDS so that each lane reads
-// the partner Omega_ji of every Omega_ij it holds; tr(Omega Omega) is summed per g
-// in FP32 and across g in FP64, and wave 0 / wave 1 form Re / Im tr Omega.
+// hi*hi + hi*lo + lo*hi).  The A operand (rows of Lh^g) is read by every wave
+// straight from the cache hierarchy, one K chunk ahead in registers; the waves of a
+// workgroup read the same rows at nearly the same time, so L1 serves the sharing and
+// LDS holds only Omega.  That keeps several workgroups per CU at these shapes.
+// Omega is written column-major to LDS so that each lane reads the partner
+// Omega_ji of every Omega_ij it holds; tr(Omega Omega) is summed per g in FP32 and
+// across g in FP64, and wave 0 / wave 1 form Re / Im tr Omega.
 #pragma once
 
-template <int NPW, bool BF16>
-__global__ void __launch_bounds__(256) k_contract_mfma_wide(
+template <int NPW, bool BF16, int NK>
+__global__ void __launch_bounds__(256, 2) k_contract_mfma_wide(
     int nw, int G, int nup, int ndn, int KP, const void* __restrict__ Lp_,
     const void* __restrict__ thp_, const double* __restrict__ weight, cd* __restrict__ tpart,
     cd* __restrict__ exch) {
@@ -41,37 +42,19 @@ __global__ void __launch_bounds__(256) k_contract_mfma_wide(
 
   constexpr int ESZ = BF16 ? 2 : 4;
   constexpr int PLANES = BF16 ? 2 : 1;
-  const int lda = KP + (BF16 ? 8 : 4);                  // LDS row stride in elements
   const size_t tile_elems = (size_t)NPW * KP * PLANES;  // one g in global memory
-  const int tile_lds_bytes = NPW * lda * ESZ * PLANES;
   constexpr int LDE = NPW + 4;
-  float* ep_re = reinterpret_cast<float*>(smem + 2 * tile_lds_bytes);  // Omega column-major
+  float* ep_re = reinterpret_cast<float*>(smem);        // Omega column-major
   float* ep_im = ep_re + NPW * LDE;
-  double* red = reinterpret_cast<double*>(ep_im + NPW * LDE);         // [2][NW]
+  double* red = reinterpret_cast<double*>(ep_im + NPW * LDE);  // [2][NW]
 
   const unsigned char* Lbase =
       reinterpret_cast<const unsigned char*>(Lp_) + ((size_t)dd * 2 + s) * G * tile_elems * ESZ;
 
-  // Copy of a g-tile in 16-byte chunks: chunk ch = tid + k NT, k < KP / 16 (exactly
-  // NPW * PLANES * KP * ESZ / 16 = (KP / 16) * NT chunks).
-  const int chunks_per_row = KP * ESZ / 16;
-  const int nchunks = NPW * PLANES * chunks_per_row;
-  auto chunk_src = [&](int g, int k) {
-    const int ch = tid + k * NT;
-    return reinterpret_cast<const u32x4*>(Lbase + (size_t)g * tile_elems * ESZ) +
-           (ch < nchunks ? ch : 0);
-  };
-  auto chunk_dst = [&](unsigned char* buf, int k) {
-    const int ch = tid + k * NT;
-    const int row = ch / chunks_per_row, colc = (ch % chunks_per_row) * (16 / ESZ);
-    return reinterpret_cast<u32x4*>(buf + ((size_t)row * lda + colc) * ESZ);
-  };
-
   // ---- Theta column block into registers (B operand: rows k, column 16 wave + col)
   constexpr int KCH = BF16 ? 32 : 16;      // K per register chunk (4 lane groups)
-  constexpr int MAXK = WIDE_KMAX / KCH;
-  constexpr int CPK = BF16 ? 2 : 1;        // copy chunks per K chunk and thread
-  const int nk = KP / KCH;
+  constexpr int MAXK = NK;                 // K chunks held: KP = NK * KCH exactly
+  constexpr int nk = NK;
   const int col = lane & 15, kg = lane >> 4;
   const int kofs = BF16 ? 8 * kg : 4 * kg;
   const int bcol = 16 * wave + col;        // Theta column of this lane
@@ -96,36 +79,53 @@ __global__ void __launch_bounds__(256) k_contract_mfma_wide(
       }
     }
   }
+  // A operand of row tile r, K chunk c of a tile: this lane's 16 bytes (and the lo plane) at
+  // tile base (wave-uniform) + row offset (per lane) + c KCH ESZ (immediate)
+  const size_t plane_bytes = (size_t)NPW * KP * ESZ;
+  const size_t tile_bytes = tile_elems * ESZ;
+  uint32_t roff[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) roff[r] = (uint32_t)(((16 * r + col) * KP + kofs) * ESZ);
+  auto a_ld = [&](const unsigned char* tg, int r, int c) {
+    return *reinterpret_cast<const u32x4*>(tg + roff[r] + c * KCH * ESZ);
+  };
 
   double xr = 0.0, xi = 0.0;
-  if (G > 0)
-    for (int k = 0; k < nk * CPK; ++k) *chunk_dst(smem, k) = *chunk_src(0, k);
-  __syncthreads();
+  u32x4 acur[NR], acur_lo[BF16 ? NR : 1];
+  if (G > 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      acur[r] = a_ld(Lbase, r, 0);
+      if (BF16) acur_lo[BF16 ? r : 0] = a_ld(Lbase + plane_bytes, r, 0);
+    }
+  }
   for (int g = 0; g < G; ++g) {
-    const unsigned char* Abuf = smem + (g & 1) * tile_lds_bytes;
-    unsigned char* Anext = smem + ((g + 1) & 1) * tile_lds_bytes;
-    const bool more = g + 1 < G;
+    const unsigned char* tg = Lbase + (size_t)g * tile_bytes;
     f32x4 cre[NR], cim[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
       cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    u32x4 stage[CPK];
 #pragma unroll
     for (int c = 0; c < MAXK; ++c) {
       if (c < nk) {
-        // chunks of tile g + 1: the ones loaded one K chunk ago go to LDS now
-        u32x4 ld[CPK];
+        // next chunk (or the first chunk of the next g) one step ahead
+        const bool more = c + 1 < nk || g + 1 < G;
+        const unsigned char* tn = c + 1 < nk ? tg : tg + tile_bytes;
+        const int cn = c + 1 < nk ? c + 1 : 0;
+        u32x4 anx[NR], anx_lo[BF16 ? NR : 1];
         if (more) {
 #pragma unroll
-          for (int e = 0; e < CPK; ++e) ld[e] = *chunk_src(g + 1, CPK * c + e);
+          for (int r = 0; r < NR; ++r) {
+            anx[r] = a_ld(tn, r, cn);
+            if (BF16) anx_lo[BF16 ? r : 0] = a_ld(tn + plane_bytes, r, cn);
+          }
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const unsigned char* arow = Abuf + ((size_t)(16 * r + col) * lda + c * KCH + kofs) * ESZ;
           if constexpr (!BF16) {
-            const f32x4 a = *reinterpret_cast<const f32x4*>(arow);
+            const f32x4 a = __builtin_bit_cast(f32x4, acur[r]);
             const f32x4 br = __builtin_bit_cast(f32x4, bre[c]);
             const f32x4 bi = __builtin_bit_cast(f32x4, bim[c]);
             cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, br.x, cre[r], 0, 0, 0);
@@ -137,9 +137,8 @@ __global__ void __launch_bounds__(256) k_contract_mfma_wide(
             cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, br.w, cre[r], 0, 0, 0);
             cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bi.w, cim[r], 0, 0, 0);
           } else {
-            const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow));
-            const bf16x8 al = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4*>(arow + (size_t)NPW * lda * ESZ));
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, acur[r]);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, acur_lo[BF16 ? r : 0]);
             const bf16x8 brh = __builtin_bit_cast(bf16x8, bre[c]);
             const bf16x8 brl = __builtin_bit_cast(bf16x8, bre_lo[BF16 ? c : 0]);
             const bf16x8 bih = __builtin_bit_cast(bf16x8, bim[c]);
@@ -153,18 +152,15 @@ __global__ void __launch_bounds__(256) k_contract_mfma_wide(
           }
         }
         if (more) {
-          if (c > 0) {
 #pragma unroll
-            for (int e = 0; e < CPK; ++e) *chunk_dst(Anext, CPK * (c - 1) + e) = stage[e];
+          for (int r = 0; r < NR; ++r) {
+            acur[r] = anx[r];
+            if (BF16) acur_lo[BF16 ? r : 0] = anx_lo[BF16 ? r : 0];
           }
-#pragma unroll
-          for (int e = 0; e < CPK; ++e) stage[e] = ld[e];
         }
       }
-    }
-    if (more) {
-#pragma unroll
-      for (int e = 0; e < CPK; ++e) *chunk_dst(Anext, CPK * (nk - 1) + e) = stage[e];
+      // keep each chunk's loads one chunk ahead instead of hoisting them all
+      __builtin_amdgcn_sched_barrier(0);
     }
     // lane holds Omega[16 r + 4 kg + v][bcol], v = 0..3: column-major store
 #pragma unroll
@@ -174,7 +170,7 @@ __global__ void __launch_bounds__(256) k_contract_mfma_wide(
       *reinterpret_cast<float4*>(ep_im + bcol * LDE + 16 * r + 4 * kg) =
           make_float4(cim[r][0], cim[r][1], cim[r][2], cim[r][3]);
     }
-    __syncthreads();  // Omega complete; tile g + 1 stored
+    __syncthreads();  // Omega complete
     {
       float pr = 0.f, pi = 0.f;
 #pragma unroll
@@ -219,7 +215,6 @@ __global__ void __launch_bounds__(256) k_contract_mfma_wide(
 }
 
 template <int NPW, bool BF16>
-constexpr size_t wide_contract_lds_bytes_t(int KP) {
-  return (size_t)2 * NPW * (KP + (BF16 ? 8 : 4)) * (BF16 ? 2 : 4) * (BF16 ? 2 : 1) +
-         (size_t)2 * NPW * (NPW + 4) * 4 + 2 * (NPW / 16) * 8;
+constexpr size_t wide_contract_lds_bytes_t(int) {
+  return (size_t)2 * NPW * (NPW + 4) * 4 + 2 * (NPW / 16) * 8;
 }

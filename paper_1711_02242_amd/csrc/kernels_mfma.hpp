@@ -364,13 +364,25 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   if (!mfma_tile_valid(t, tile)) tile = TILE_DEFAULT;
   if (t.wide || tile == TILE_WIDE) {
     dim3 grid(nw, 2 * n_det);
-#define LAUNCH_WIDE(NPV, BFV)                                                                   \
+#define LAUNCH_WIDE_K(NPV, BFV, KM)                                                             \
   do {                                                                                          \
     const size_t shm_ = wide_contract_lds_bytes_t<NPV, BFV>(t.KP);                              \
-    (void)hipFuncSetAttribute((const void*)k_contract_mfma_wide<NPV, BFV>,                      \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_);           \
-    hipLaunchKernelGGL((k_contract_mfma_wide<NPV, BFV>), grid, dim3(4 * NPV), shm_, st, nw, G,  \
-                       t.nup, t.ndn, t.KP, (const void*)t.Lp, thetaP, weight, tpart, exch);     \
+    hipLaunchKernelGGL((k_contract_mfma_wide<NPV, BFV, KM>), grid, dim3(4 * NPV), shm_, st, nw, \
+                       G, t.nup, t.ndn, t.KP, (const void*)t.Lp, thetaP, weight, tpart, exch);  \
+  } while (0)
+  // one instantiation per K chunk count (K_P = 32 .. 224 in steps of 32)
+#define LAUNCH_WIDE(NPV, BFV)                                                                   \
+  do {                                                                                          \
+    constexpr int KCH_ = BFV ? 32 : 16;                                                         \
+    switch (t.KP / KCH_) {                                                                      \
+      case 32 / KCH_: LAUNCH_WIDE_K(NPV, BFV, 32 / KCH_); break;                                \
+      case 64 / KCH_: LAUNCH_WIDE_K(NPV, BFV, 64 / KCH_); break;                                \
+      case 96 / KCH_: LAUNCH_WIDE_K(NPV, BFV, 96 / KCH_); break;                                \
+      case 128 / KCH_: LAUNCH_WIDE_K(NPV, BFV, 128 / KCH_); break;                              \
+      case 160 / KCH_: LAUNCH_WIDE_K(NPV, BFV, 160 / KCH_); break;                              \
+      case 192 / KCH_: LAUNCH_WIDE_K(NPV, BFV, 192 / KCH_); break;                              \
+      default: LAUNCH_WIDE_K(NPV, BFV, 224 / KCH_); break;                                      \
+    }                                                                                           \
   } while (0)
     if (t.NP == 64) {
       if (bf) LAUNCH_WIDE(64, true);
@@ -383,6 +395,7 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
       else LAUNCH_WIDE(32, false);
     }
 #undef LAUNCH_WIDE
+#undef LAUNCH_WIDE_K
     return hipGetLastError();
   }
   const int wpb = tile == TILE_W2 ? 2 : 4;

@@ -25,3 +25,4 @@ from .fields import (  # noqa: F401
     u64_to_unit,
 )
 from .trials import excitation_trial, noci_trial, occupation_det  # noqa: F401
+from .workloads import batch_workload, serving_trace  # noqa: F401
