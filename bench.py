@@ -185,6 +185,70 @@ def batch_leg(args):
             "speedup": round(vb / va, 3), "setup_s": round(t_setup, 1)}
 
 
+def serving_leg(args):
+    """Serving: the first jobs of a Poisson(4/s) trace (M uniform on 32..200, N=M/4, N_g=6M,
+    256-2048 walkers) replayed in real time through the continuous-batching server, FP32 bulk,
+    each job run to its target standard error or its step cap.  The serial plain-FP64 figure
+    runs every job alone in FP64 for a few steps, scales its step time to the steps the job
+    took, and queues the jobs first-come-first-served on the same arrival times."""
+    import numpy as np
+    import torch
+
+    import paper_1711_02242_amd as afq
+    from paper_1711_02242_amd.serve import JobSpec, Server
+    from synthetic import gen_system, serving_trace
+    trace = serving_trace(args.serve_jobs)
+    specs = []
+    for t in trace:
+        make = (lambda t=t: gen_system(t["M"], t["N"], t["n_chol"], seed=t["seed"]))
+        specs.append(JobSpec(t["job_id"], make, t["M"], t["N"], t["N"], t["n_chol"],
+                             t["n_walkers"], t["seed"], precision="fp32", dtau=0.005,
+                             target_stderr=args.serve_target, max_steps=args.serve_steps,
+                             discard=args.serve_steps // 3, arrival=t["arrival"]))
+    srv = Server(int(args.serve_budget_gib * (1 << 30)), check_every=50, autotune=True)
+    t0 = time.perf_counter()
+    res = srv.run(specs, realtime=True)
+    makespan = time.perf_counter() - t0
+    tte = np.array([r.time_to_energy for r in res])
+    ws = sum(r.steps * sp.n_walkers for r, sp in zip(res, specs))
+    eprint(f"bench: served {len(res)} jobs in {makespan:.1f} s, max resident {srv.max_resident}, "
+           f"TTE p50 {np.percentile(tte, 50):.1f} s p99 {np.percentile(tte, 99):.1f} s")
+    # serial plain FP64: per-job step time alone, FIFO over the same arrivals
+    t_end, serial_tte = 0.0, []
+    for r, sp in zip(res, specs):
+        s = sp.make_system()
+        gs = afq.System.from_synthetic(s, dtau=sp.dtau, precision="fp64")
+        wk = gs.walkers(sp.n_walkers)
+        gs.init(wk)
+        gs.step(wk, seed=sp.seed, job_id=sp.job_id)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.serve_fp64_steps):
+            gs.step(wk, seed=sp.seed, job_id=sp.job_id)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - a) / args.serve_fp64_steps
+        gs.close()
+        del s
+        start = max(sp.arrival, t_end)
+        t_end = start + per * r.steps
+        serial_tte.append(t_end - sp.arrival)
+    serial_tte = np.array(serial_tte)
+    return {"workload": f"first {len(specs)} jobs of a Poisson(4/s) trace: M uniform on 32..200, "
+                        "N=M/4, N_g=6M, 256-2048 walkers, fp32 bulk, dtau=0.005",
+            "jobs": len(res), "hbm_budget_gib": args.serve_budget_gib,
+            "target_stderr_ha": args.serve_target, "step_cap": args.serve_steps,
+            "reached_target": int(sum(r.plateau and r.stderr < args.serve_target for r in res)),
+            "p50_time_to_energy_s": round(float(np.percentile(tte, 50)), 2),
+            "p99_time_to_energy_s": round(float(np.percentile(tte, 99)), 2),
+            "walker_steps_per_s": round(ws / makespan, 1), "makespan_s": round(makespan, 2),
+            "max_resident": srv.max_resident,
+            "serial_fp64": {"p50_time_to_energy_s": round(float(np.percentile(serial_tte, 50)), 2),
+                            "p99_time_to_energy_s": round(float(np.percentile(serial_tte, 99)), 2),
+                            "walker_steps_per_s": round(ws / float(t_end), 1),
+                            "method": f"each job alone in FP64, {args.serve_fp64_steps} timed "
+                                      "steps scaled to its step count, FIFO on the arrivals"}}
+
+
 def el_error(s, args, gs, wk):
     """Per-walker local-energy error of this precision on the current walkers: against the
     GPU FP64 path on every walker, and against the FP64 oracle on a sample."""
@@ -241,6 +305,12 @@ def main():
     ap.add_argument("--batch-systems", type=int, default=24)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop trace")
+    ap.add_argument("--serve-jobs", type=int, default=8)
+    ap.add_argument("--serve-steps", type=int, default=300, help="step cap per job")
+    ap.add_argument("--serve-target", type=float, default=0.005, help="target stderr (Ha)")
+    ap.add_argument("--serve-budget-gib", type=float, default=128.0)
+    ap.add_argument("--serve-fp64-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
@@ -322,6 +392,9 @@ def main():
 
     if not args.no_batch:
         out["batch"] = batch_leg(args)
+
+    if not args.no_serve:
+        out["serving"] = serving_leg(args)
 
     if not args.no_cpu:
         cb = cpu_baseline(s, args)

@@ -280,6 +280,20 @@ AFQMC_API int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc
  * Returns AFQMC_E_NUMERIC if no walker is alive or a sum is not finite. */
 AFQMC_API int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[6]);
 
+/* The sums of afqmc_energy written to device memory out_dev[0..5] (out_dev[4] = the status
+ * word as a double) without synchronizing: per-step records of the mixed estimator in a
+ * caller-owned device buffer, read back in blocks (the serving loop).  Asynchronous. */
+AFQMC_API int afqmc_energy_enqueue(afqmc_sys s, const afqmc_walkers* w, double* out_dev);
+
+/* HBM footprint of a job before it is set up (admission by memory): *system_bytes = the
+ * device memory afqmc_setup (n_det == 1) or afqmc_setup_multidet would hold for these
+ * parameters (the value afqmc_get_info reports), *walker_bytes = afqmc_workspace_bytes for
+ * n_walkers plus the walker arrays of afqmc_walkers (U, weight, arg_ovlp, log_ovlp, e_loc,
+ * phase, walker_id) and 256 bytes of workspace alignment.  Host arithmetic only; returns
+ * AFQMC_E_UNSUPPORTED for shapes afqmc_setup would refuse for their size. */
+AFQMC_API int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walkers,
+                                    size_t* system_bytes, size_t* walker_bytes);
+
 /* Read and clear the sticky status word (synchronizes the stream). */
 AFQMC_API int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear);
 

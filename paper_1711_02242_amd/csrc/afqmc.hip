@@ -1138,7 +1138,7 @@ int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[6]) {
   const double half = sqrt(s->p.el_cap_C / s->p.dtau);
   const int fp = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 1 : 0;
   hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, fp, s->e_trial,
-                     half, w->weight, w->phase, (const cd*)w->e_loc, d);
+                     half, w->weight, w->phase, (const cd*)w->e_loc, nullptr, d);
   HIPCHK(hipGetLastError());
   double h[6];
   unsigned st = 0;
@@ -1151,6 +1151,53 @@ int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[6]) {
   if (!(h[3] > 0.0) || !std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2]) ||
       !std::isfinite(h[5]) || (!fp && !(h[2] > 0.0)))
     return AFQMC_E_NUMERIC;
+  return AFQMC_OK;
+}
+
+int afqmc_energy_enqueue(afqmc_sys s, const afqmc_walkers* w, double* out_dev) {
+  if (!s || !out_dev) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  const double half = sqrt(s->p.el_cap_C / s->p.dtau);
+  const int fp = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 1 : 0;
+  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, fp, s->e_trial,
+                     half, w->weight, w->phase, (const cd*)w->e_loc, s->status, out_dev);
+  HIPCHK(hipGetLastError());
+  return AFQMC_OK;
+}
+
+int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walkers,
+                          size_t* system_bytes, size_t* walker_bytes) {
+  if (!p || n_det < 1 || n_walkers < 1 || !system_bytes || !walker_bytes) return AFQMC_E_ARG;
+  const int M = p->M, G = p->n_chol;
+  if (M < 1 || p->n_up < 0 || p->n_dn < 0 || p->n_up + p->n_dn < 1 || G < 0) return AFQMC_E_ARG;
+  // the shape fields setup_impl derives, on a host-only descriptor (nothing is allocated)
+  afqmc_sys_s S;
+  S.p = *p;
+  S.M = M;
+  S.G = G;
+  S.nup = p->n_up;
+  S.ndn = (p->flags & AFQMC_FLAG_CLOSED_SHELL) ? 0 : p->n_dn;
+  S.ntot = S.nup + S.ndn;
+  S.n_det = n_det;
+  S.multi = n_det > 1;
+  const int rc = mfma_plan(S.mt, p->precision, M, S.nup, S.ndn, G, n_det);
+  if (rc == AFQMC_OK) S.mt.enabled = true;
+  else if (!(p->precision == AFQMC_FP64 && n_det == 1)) return rc;
+  S.f32_prop = p->precision != AFQMC_FP64 && M <= MFMA_KMAX && S.ntot <= 64;
+  S.Gp = S.f32_prop ? ((G + 31) / 32) * 32 : 0;
+  const size_t nt = S.ntot, MM = (size_t)M * M, g1 = G > 0 ? G : 1;
+  size_t sb = G > 0 ? (size_t)G * MM * 8 : 8;                 // L
+  sb += MM * 8 + n_det * nt * M * 8 + g1 * 8;                 // E_h, V, lbar
+  sb += (n_det * (size_t)G * nt * M > 0 ? n_det * (size_t)G * nt * M : 1) * 8;  // Lh
+  sb += n_det * nt * M * 8 + 4;                              // ht, status
+  if (S.multi) sb += (size_t)2 * n_det * 8;                  // coefficients
+  if (S.mt.enabled) sb += S.mt.bytes;
+  if (S.f32_prop) sb += MM * (S.Gp > 0 ? S.Gp : 1) * 4 + MM * 4;   // L^T, E_h (FP32)
+  *system_bytes = sb;
+  const size_t nw = (size_t)n_walkers;
+  *walker_bytes = layout(&S, nw).total + 256 + nw * nt * M * 16 + nw * (8 * 4 + 16 + 8);
+  S.mt.enabled = false;   // the descriptor owns no device memory
   return AFQMC_OK;
 }
 

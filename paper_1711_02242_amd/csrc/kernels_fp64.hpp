@@ -705,6 +705,7 @@ __global__ void __launch_bounds__(256) k_energy_sum(int nw, int free_proj, doubl
                                                     const double* __restrict__ weight,
                                                     const double* __restrict__ phase,
                                                     const cd* __restrict__ e_loc,
+                                                    const unsigned* __restrict__ status,
                                                     double* __restrict__ out) {
   // c = W e^{i theta}: sums of c E (Re, Im), of c (Re, Im) and the live count.  The local
   // energy is capped (eq:cap) in the phaseless modes and taken as is in free projection.
@@ -739,6 +740,7 @@ __global__ void __launch_bounds__(256) k_energy_sum(int nw, int free_proj, doubl
     out[1] = b;
     out[2] = c;
     out[3] = d;
+    out[4] = status ? (double)*status : 0.0;
     out[5] = f;
   }
 }

@@ -70,14 +70,15 @@ inline size_t mfma_theta_bytes(const MfmaTables& t, size_t nw) {
   return nw * (size_t)t.n_det * 2 * 2 * (size_t)t.NP * t.KP * (t.precision == AFQMC_FP64 ? 8 : 4);
 }
 
-inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int ndn, int G,
-                             const double* Lh /* host [n_det][G][nup+ndn][M] */, int n_det = 1) {
+// Shape of the tables (no allocation): NP, KP, kernel family and device bytes.
+inline int mfma_plan(MfmaTables& t, int precision, int M, int nup, int ndn, int G, int n_det) {
   const int nmax = nup > ndn ? nup : ndn;
   // register-resident kernels up to N = 32, M = 128 (all precisions); beyond, up to N = 64,
-  // M = 256, the wide FP32 / BF16x3 kernel
+  // M = 224, the wide FP32 / BF16x3 kernel
   const bool fast = nmax <= 32 && M <= MFMA_KMAX;
   const bool wide = !fast && precision != AFQMC_FP64 && nmax <= 64 && M <= WIDE_KMAX;
   if (!fast && !wide) return AFQMC_E_UNSUPPORTED;
+  if (precision < AFQMC_FP64 || precision > AFQMC_BF16X3) return AFQMC_E_UNSUPPORTED;
   t.precision = precision;
   t.wide = wide;
   t.NP = nmax <= 16 ? 16 : nmax <= 32 ? 32 : nmax <= 48 ? 48 : 64;
@@ -87,9 +88,20 @@ inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int n
   t.G = G;
   t.nup = nup;
   t.ndn = ndn;
+  t.n_det = n_det;
+  const size_t per = (size_t)t.NP * t.KP;
+  if (precision == AFQMC_FP64) t.bytes = ((size_t)n_det * 2 * G * per + 2) * sizeof(double);
+  else if (precision == AFQMC_FP32) t.bytes = ((size_t)n_det * 2 * G * per + 1) * sizeof(float);
+  else t.bytes = ((size_t)n_det * 2 * G * 2 * per + 2) * sizeof(uint16_t);
+  return AFQMC_OK;
+}
+
+inline int mfma_build_tables(MfmaTables& t, int precision, int M, int nup, int ndn, int G,
+                             const double* Lh /* host [n_det][G][nup+ndn][M] */, int n_det = 1) {
+  const int prc = mfma_plan(t, precision, M, nup, ndn, G, n_det);
+  if (prc != AFQMC_OK) return prc;
   const int nt = nup + ndn;
   const size_t per = (size_t)t.NP * t.KP;
-  t.n_det = n_det;
   if (precision == AFQMC_FP64) {
     std::vector<double> h((size_t)n_det * 2 * G * per + 2, 0.0);
     for (int d = 0; d < n_det; ++d)

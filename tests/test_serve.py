@@ -1,0 +1,37 @@
+"""Host logic of the serving loop: the reblocked energy estimate against the oracle's reblocking
+(App. C) and the footprint arithmetic used for admission."""
+
+import numpy as np
+import pytest
+
+from oracle import reblock as R
+
+
+def _ar1(n, phi, seed):
+    rng = np.random.default_rng(seed)
+    x = np.empty(n)
+    x[0] = rng.standard_normal()
+    for i in range(1, n):
+        x[i] = phi * x[i - 1] + rng.standard_normal()
+    return -10.0 + 0.01 * x, 1.0 + 0.1 * rng.random(n)
+
+
+@pytest.mark.parametrize("phi", [0.0, 0.6, 0.95])
+def test_blocked_error_matches_oracle(phi):
+    from paper_1711_02242_amd.serve import blocked_error, energy_estimate
+    x, w = _ar1(4096, phi, seed=int(phi * 100))
+    for L in (1, 4, 32):
+        a = blocked_error(x, w, L)
+        b = R.reblock(x, w, L)
+        assert np.allclose(a, b, rtol=1e-12, atol=0)
+    assert np.allclose(energy_estimate(x, w, 200), R.reblock_converged(x, w, 200), rtol=1e-12)
+
+
+def test_footprint_grows_with_walkers_and_size():
+    from paper_1711_02242_amd.serve import JobSpec, footprint
+    mk = lambda M, nw, prec="fp32": JobSpec(0, None, M, M // 4, M // 4, 6 * M, nw, 0, prec)
+    assert footprint(mk(64, 512)) < footprint(mk(64, 1024)) < footprint(mk(96, 1024))
+    assert footprint(mk(160, 256)) > 0 and footprint(mk(200, 256)) > footprint(mk(160, 256))
+    assert footprint(mk(64, 512, "fp64")) > 0
+    with pytest.raises(Exception):
+        footprint(mk(240, 256))       # beyond the MFMA kernels in a mixed-precision mode
