@@ -380,6 +380,19 @@ def main():
     else:
         gs.close()
 
+    if args.precision == "fp32" and not args.no_compare:
+        # the BF16x3 split-product bulk on the same workload (local-energy error reported)
+        g4, w4, dt4, kt4, e4 = run_gpu(s, args, "bf16x3", args.steps, 2)
+        ms4, n4 = kt4["contract"]
+        ach4 = flops / ((ms4 / max(n4, 1)) * 1e-3) / 1e12
+        err4, _, _ = el_error(s, args, g4, w4)
+        out["bf16x3"] = {"value": round(args.walkers * args.steps / dt4, 2),
+                         "unit": "walker-steps/s", "ms_per_step": round(1e3 * dt4 / args.steps, 3),
+                         "contraction_fp32_equivalent_tflops": round(ach4, 2),
+                         "contraction_frac_of_bf16_peak_over_3": round(ach4 / PEAK_TFLOPS["bf16x3"], 4),
+                         "el_error_ha_vs_gpu_fp64_all_walkers": err4}
+        g4.close()
+
     if not args.no_closed_shell and not args.no_compare:
         # the same workload on the closed-shell path (U_up = U_dn stored once; identical results)
         g3, w3, dt3, kt3, e3 = run_gpu(s, args, args.precision, args.steps, 2,
