@@ -56,6 +56,7 @@ struct afqmc_sys_s {
   float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
   int Gp = 0;              // G rounded up to 32
   bool f32_prop = false;   // A-build and propagation on FP32 MFMA (mixed-precision modes)
+  bool prop_wide = false;  // propagation by k_propagate_f32_wide (M > 128 or N_up + N_dn > 64)
   int sf = 1;              // spin factor: 2 in closed-shell mode (only the up block is stored)
   double h0p = 0.0;        // constant of the propagated Hamiltonian (H0 - 1/2 sum lbar^2)
   double* lbar = nullptr;  // [G] mean-field shifts <L_g>_T (zeros without subtraction)
@@ -714,9 +715,11 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     }
     if (S->mt.enabled) S->device_bytes += S->mt.bytes;
   }
-  // FP32 A-build and propagation where k_propagate_f32 covers the shape (M <= 128,
-  // N_up + N_dn <= 64); otherwise the FP64 kernels run in every mode.
-  if (p->precision != AFQMC_FP64 && M <= MFMA_KMAX && S->ntot <= 64) {
+  // FP32 A-build and propagation in the mixed-precision modes: k_propagate_f32 where it
+  // covers the shape (M <= 128, N_up + N_dn <= 64), else k_propagate_f32_wide (M <= 224,
+  // up to 64 orbitals per spin).
+  if (p->precision != AFQMC_FP64 && M <= WIDE_KMAX && std::max(nup_i, ndn_i) <= 64) {
+    S->prop_wide = M > MFMA_KMAX || S->ntot > 64;
     S->f32_prop = true;
     S->Gp = ((G + 31) / 32) * 32;
     std::vector<float> lt((size_t)M * M * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
@@ -820,7 +823,26 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
                          (float)s->s, at<float>(ws, L.y32), s->Lt32, Are, Aim);
       HIPCHK(hipGetLastError());
     }
-    {
+    if (s->prop_wide) {
+      Timer tm(s, KG_PROP);
+      const int Kp = ((M + 15) / 16) * 16;
+      const size_t shm = (size_t)2 * 64 * (Kp + 4) * 4;
+#define PROPW(NKCV)                                                                            \
+  case NKCV:                                                                                   \
+    (void)hipFuncSetAttribute((const void*)k_propagate_f32_wide<NKCV>,                         \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
+    hipLaunchKernelGGL(k_propagate_f32_wide<NKCV>, dim3(nw, 2), dim3(64 * NKCV), shm, s->stream, \
+                       M, s->nup, s->ndn, Kp, s->G > 0 ? s->p.n_taylor : 0, s->Eh32, Are, Aim, \
+                       (cd*)w->U, w->weight);                                                  \
+    break;
+      switch (Kp / 16) {
+        PROPW(1) PROPW(2) PROPW(3) PROPW(4) PROPW(5) PROPW(6) PROPW(7)
+        PROPW(8) PROPW(9) PROPW(10) PROPW(11) PROPW(12) PROPW(13) PROPW(14)
+        default: return AFQMC_E_UNSUPPORTED;
+      }
+#undef PROPW
+      HIPCHK(hipGetLastError());
+    } else {
       Timer tm(s, KG_PROP);
       const int Kp = ((M + 15) / 16) * 16;
       const size_t shm = (size_t)2 * 16 * PR_RB * (Kp + 4) * 4;
@@ -1184,7 +1206,8 @@ int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walker
   const int rc = mfma_plan(S.mt, p->precision, M, S.nup, S.ndn, G, n_det);
   if (rc == AFQMC_OK) S.mt.enabled = true;
   else if (!(p->precision == AFQMC_FP64 && n_det == 1)) return rc;
-  S.f32_prop = p->precision != AFQMC_FP64 && M <= MFMA_KMAX && S.ntot <= 64;
+  S.f32_prop = p->precision != AFQMC_FP64 && M <= WIDE_KMAX &&
+               std::max(S.nup, S.ndn) <= 64;
   S.Gp = S.f32_prop ? ((G + 31) / 32) * 32 : 0;
   const size_t nt = S.ntot, MM = (size_t)M * M, g1 = G > 0 ? G : 1;
   size_t sb = G > 0 ? (size_t)G * MM * 8 : 8;                 // L

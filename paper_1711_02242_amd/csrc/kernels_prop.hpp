@@ -310,3 +310,160 @@ __global__ void __launch_bounds__(256) k_y_to_f32(int nw, int G, int Gp, const c
   Y[(size_t)(2 * w) * Gp + g] = (float)v.re;
   Y[(size_t)(2 * w + 1) * Gp + g] = (float)v.im;
 }
+
+// ---------------------------------------------------------------------------
+// Fused propagation for the wide shapes (M up to 224, up to 64 orbitals per spin):
+// u' = u E_h T_n(A) E_h for the orbitals of one spin of one walker per workgroup
+// (grid: walkers x 2 spins).  As in k_propagate_f32, one wavefront per 16 output
+// columns q and the current term (rows c, FP32 Re/Im planes) in LDS as the A operand;
+// the B operands (columns q of E_h and of A, read as rows since both are symmetric)
+// are streamed from memory one 16-wide K chunk ahead instead of being held in
+// registers; a workgroup of NKC wavefronts gets 512 / ceil(NKC / 4) VGPRs per wave.
+// ---------------------------------------------------------------------------
+template <int NKC>
+__global__ void __launch_bounds__(64 * NKC) k_propagate_f32_wide(
+    int M, int nup, int ndn, int Kp, int n_taylor, const float* __restrict__ Eh32 /*[M][M]*/,
+    const float* __restrict__ Are, const float* __restrict__ Aim, cd* __restrict__ U,
+    const double* __restrict__ weight) {
+  extern __shared__ __attribute__((aligned(16))) float tsm[];
+  constexpr int RB = 4;                         // row blocks of 16 (N_s <= 64)
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s ? ndn : nup, off = s ? nup : 0, ntot = nup + ndn;
+  if (N == 0 || !(weight[w] > 0.0)) return;     // uniform over the workgroup
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ldt = Kp + 4;
+  float* Tr = tsm;                  // [64][ldt]
+  float* Ti = tsm + 16 * RB * ldt;  // [64][ldt]
+  const int j = lane & 15, q4 = lane >> 4;
+  const int qcol = 16 * wave + j;   // output column owned by the lane
+  const bool colok = qcol < M;
+  const size_t MM = (size_t)M * M;
+  const int nrb = (N + 15) / 16;
+  const float* Eq = Eh32 + (size_t)(colok ? qcol : 0) * M;
+  const float* Arq = Are + (size_t)w * MM + (size_t)(colok ? qcol : 0) * M;
+  const float* Aiq = Aim + (size_t)w * MM + (size_t)(colok ? qcol : 0) * M;
+  // B operand of K chunk kc: rows p = 16 kc + 4 q4 + e of column qcol (zero beyond M)
+  auto ld4 = [&](const float* row, int kc) {
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    const int p0 = 16 * kc + 4 * q4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (colok && p0 + e < M) v[e] = row[p0 + e];
+    return v;
+  };
+
+  const cd* Uw = U + ((size_t)w * ntot + off) * M;
+  for (int e = tid; e < 16 * RB * Kp; e += blockDim.x) {
+    const int c = e / Kp, p = e % Kp;
+    cd v = mkc(0.0, 0.0);
+    if (c < N && p < M) v = Uw[(size_t)c * M + p];
+    Tr[c * ldt + p] = (float)v.re;
+    Ti[c * ldt + p] = (float)v.im;
+  }
+  __syncthreads();
+
+  f32x4 yre[RB], yim[RB], cre[RB], cim[RB];
+  // real B (E_h): C = T E_h
+  auto mul_real = [&](const float* Bq) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      cre[rb] = f32x4{};
+      cim[rb] = f32x4{};
+    }
+    f32x4 b = ld4(Bq, 0);
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      const f32x4 bn = kc + 1 < NKC ? ld4(Bq, kc + 1) : b;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= nrb) break;
+        const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+        const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], b[e], cre[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], b[e], cim[rb], 0, 0, 0);
+        }
+      }
+      b = bn;
+    }
+  };
+  auto store_planes = [&](const f32x4* pr, const f32x4* pi) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      if (rb < nrb && qcol < Kp) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Tr[(16 * rb + 4 * q4 + v) * ldt + qcol] = pr[rb][v];
+          Ti[(16 * rb + 4 * q4 + v) * ldt + qcol] = pi[rb][v];
+        }
+      }
+    }
+  };
+
+  // X = U E_h; the first term and Y = X
+  mul_real(Eq);
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    yre[rb] = cre[rb];
+    yim[rb] = cim[rb];
+  }
+  store_planes(cre, cim);
+  __syncthreads();
+  // Taylor terms: T <- T A / n, Y += T
+  for (int n = 1; n <= n_taylor; ++n) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      cre[rb] = f32x4{};
+      cim[rb] = f32x4{};
+    }
+    f32x4 br = ld4(Arq, 0), bi = ld4(Aiq, 0);
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      const f32x4 brn = kc + 1 < NKC ? ld4(Arq, kc + 1) : br;
+      const f32x4 bin = kc + 1 < NKC ? ld4(Aiq, kc + 1) : bi;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= nrb) break;
+        const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+        const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], br[e], cre[rb], 0, 0, 0);
+          cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[e], bi[e], cre[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], bi[e], cim[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], br[e], cim[rb], 0, 0, 0);
+        }
+      }
+      br = brn;
+      bi = bin;
+    }
+    const float inv = 1.0f / (float)n;
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      cre[rb] *= inv;
+      cim[rb] *= inv;
+      yre[rb] += cre[rb];
+      yim[rb] += cim[rb];
+    }
+    store_planes(cre, cim);
+    __syncthreads();
+  }
+  // Y into the planes, then U' = Y E_h
+  store_planes(yre, yim);
+  __syncthreads();
+  mul_real(Eq);
+  cd* Uo = U + ((size_t)w * ntot + off) * M;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    if (rb >= nrb || !colok) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = 16 * rb + 4 * q4 + v;
+      if (c < N) Uo[(size_t)c * M + qcol] = mkc((double)cre[rb][v], (double)cim[rb][v]);
+    }
+  }
+}
