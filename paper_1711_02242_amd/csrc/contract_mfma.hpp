@@ -11,10 +11,19 @@
 // in registers for the whole kernel; the WPB wavefronts of a workgroup (WPB
 // walkers of the same spin, WPB = 4 or 2) stream the shared tiles Lh^g_s (N x M)
 // through double-buffered LDS.  Per g the wave runs the MFMA chain over K = M for the
-// Re and Im halves, then an LDS transpose gives every lane the partner element
-// Omega_ji of each Omega_ij it holds.  Per-g partial products are summed in
+// Re and Im halves, then an LDS transpose through the wave's own planes gives every
+// lane the partner element Omega_ji of each Omega_ij it holds (a wavefront fence, not a
+// workgroup barrier, orders it; one barrier per g guards the shared tile buffers).  Per-g partial products are summed in
 // FP32 and accumulated across g in FP64.
 #pragma once
+
+// Orders a wave's LDS stores before its later LDS loads of other lanes' elements (the
+// per-wave Omega planes): wavefront-scope release / acquire, no workgroup barrier.
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ---------------------------------------------------------------------------
 // The contraction kernel.  Grid: (ceil(nw / WPB), 2 n_det); 64 WPB threads.
@@ -170,7 +179,7 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
               make_float4(cim[4 * v4], cim[4 * v4 + 1], cim[4 * v4 + 2], cim[4 * v4 + 3]);
         }
       }
-      __syncthreads();
+      wave_lds_fence();   // each wave reads back only its own Omega planes
       if (active) {
         float pr = 0.f, pi = 0.f;
 #pragma unroll
@@ -226,7 +235,7 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
         *reinterpret_cast<float4*>(ep_im + col * LDE + 4 * kg) =
             make_float4(cim[0], cim[1], cim[2], cim[3]);
       }
-      __syncthreads();
+      wave_lds_fence();   // each wave reads back only its own Omega planes
       if (active) {
         float pr = 0.f, pi = 0.f;
 #pragma unroll
