@@ -52,7 +52,8 @@ struct afqmc_sys_s {
   double* ht = nullptr;    // [ntot][M]
   unsigned* status = nullptr;
   MfmaTables mt;           // packed low-precision copies for the MFMA contraction
-  float* Lt32 = nullptr;   // [M*M][Gp] FP32 transposed Cholesky tensor (A-build operand)
+  float* Lt32 = nullptr;   // [M(M+1)/2][Gp] FP32 transposed Cholesky tensor, lower triangle
+  int* abpairs = nullptr;  // [M(M+1)/2][2] (q M + p, p M + q) of each packed column
   float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
   int Gp = 0;              // G rounded up to 32
   bool f32_prop = false;   // A-build and propagation on FP32 MFMA (mixed-precision modes)
@@ -288,6 +289,7 @@ void free_sys(afqmc_sys_s* S) {
   hipFree(S->ht);
   hipFree(S->status);
   hipFree(S->Lt32);
+  hipFree(S->abpairs);
   hipFree(S->lbar);
   hipFree(S->Eh32);
   hipFree(S->coef);
@@ -722,11 +724,23 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     S->prop_wide = M > MFMA_KMAX || S->ntot > 64;
     S->f32_prop = true;
     S->Gp = ((G + 31) / 32) * 32;
-    std::vector<float> lt((size_t)M * M * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
-    for (int g = 0; g < G; ++g)
-      for (size_t e = 0; e < (size_t)M * M; ++e) lt[e * S->Gp + g] = (float)L_chol[(size_t)g * M * M + e];
+    // lower triangle of every L^g (L^g is symmetric), one packed row per pair p <= q
+    const size_t MMh = (size_t)M * (M + 1) / 2;
+    std::vector<float> lt(MMh * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
+    std::vector<int> pairs(2 * MMh);
+    {
+      size_t k = 0;
+      for (int q = 0; q < M; ++q)
+        for (int pp = 0; pp <= q; ++pp, ++k) {
+          pairs[2 * k] = q * M + pp;
+          pairs[2 * k + 1] = pp * M + q;
+          for (int g = 0; g < G; ++g)
+            lt[k * S->Gp + g] = (float)L_chol[(size_t)g * M * M + (size_t)q * M + pp];
+        }
+    }
     for (size_t e = 0; e < eh.size(); ++e) eh[e] = (float)Eh[e];
     if ((rc = dev_upload(S, &S->Lt32, lt.data(), lt.size())) ||
+        (rc = dev_upload(S, &S->abpairs, pairs.data(), pairs.size())) ||
         (rc = dev_upload(S, &S->Eh32, eh.data(), eh.size()))) {
       free_sys(S);
       return rc;
@@ -818,9 +832,11 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
       const size_t ne = (size_t)nw * s->Gp;
       hipLaunchKernelGGL(k_y_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s->stream, nw,
                          s->G, s->Gp, at<cd>(ws, L.y), at<float>(ws, L.y32));
-      dim3 grid((2 * nw + AB_BM - 1) / AB_BM, (M * M + AB_BN - 1) / AB_BN);
-      hipLaunchKernelGGL(k_abuild_f32, grid, dim3(256), 0, s->stream, 2 * nw, M * M, s->Gp,
-                         (float)s->s, at<float>(ws, L.y32), s->Lt32, Are, Aim);
+      const int MMh = M * (M + 1) / 2;
+      dim3 grid((2 * nw + AB_BM - 1) / AB_BM, (MMh + AB_BN - 1) / AB_BN);
+      hipLaunchKernelGGL(k_abuild_f32, grid, dim3(256), 0, s->stream, 2 * nw, MMh, M * M, s->Gp,
+                         (float)s->s, at<float>(ws, L.y32), s->Lt32,
+                         reinterpret_cast<const int2*>(s->abpairs), Are, Aim);
       HIPCHK(hipGetLastError());
     }
     if (s->prop_wide) {
@@ -1216,7 +1232,10 @@ int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walker
   sb += n_det * nt * M * 8 + 4;                              // ht, status
   if (S.multi) sb += (size_t)2 * n_det * 8;                  // coefficients
   if (S.mt.enabled) sb += S.mt.bytes;
-  if (S.f32_prop) sb += MM * (S.Gp > 0 ? S.Gp : 1) * 4 + MM * 4;   // L^T, E_h (FP32)
+  if (S.f32_prop) {   // packed L^T, pair table, E_h (FP32)
+    const size_t MMh = (size_t)M * (M + 1) / 2;
+    sb += MMh * (S.Gp > 0 ? S.Gp : 1) * 4 + 2 * MMh * 4 + MM * 4;
+  }
   *system_bytes = sb;
   const size_t nw = (size_t)n_walkers;
   *walker_bytes = layout(&S, nw).total + 256 + nw * nt * M * 16 + nw * (8 * 4 + 16 + 8);

@@ -15,16 +15,20 @@
 
 // ---------------------------------------------------------------------------
 // A-build as a tiled MFMA GEMM:  C[r][col] = sum_k Y[r][k] Lt[col][k]
-//   r = 2w + (0: Re y, 1: Im y),  col = q*M + p,  k = g (padded to Gp, zeros).
-//   Re A_w[col] = -s C[2w+1][col],  Im A_w[col] = s C[2w][col]  (planar FP32 output).
+//   r = 2w + (0: Re y, 1: Im y),  col = packed index of a pair p <= q (A is symmetric, so
+//   only the lower triangle is computed: MM = M(M+1)/2 columns),  k = g (padded to Gp, zeros).
+//   Re A_w[q][p] = Re A_w[p][q] = -s C[2w+1][col],  Im = s C[2w][col]  (planar FP32 output
+//   of MA = M^2 entries per walker; pairs[col] = (q M + p, p M + q)).
 // Tile 128 x 128 per workgroup, K chunks of 32 double-buffered in LDS,
 // 4 wavefronts of 64 x 64 (2 x 2 blocks of v_mfma_f32_32x32x2_f32).
 // ---------------------------------------------------------------------------
 constexpr int AB_BM = 128, AB_BN = 128, AB_BK = 32, AB_LD = AB_BK + 4;
 
-__global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM, int Gp, float s,
+__global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM, int MA, int Gp,
+                                                       float s,
                                                        const float* __restrict__ Y,
                                                        const float* __restrict__ Lt,
+                                                       const int2* __restrict__ pairs,
                                                        float* __restrict__ Are,
                                                        float* __restrict__ Aim) {
   __shared__ __attribute__((aligned(16))) float As[2][AB_BM * AB_LD];
@@ -101,13 +105,19 @@ __global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM
     for (int b = 0; b < 2; ++b) {
       const int cc = c0 + wc + 32 * b + col;
       if (cc >= MM) continue;
+      const int2 pq = pairs[cc];   // (q M + p, p M + q) of the packed column
 #pragma unroll
       for (int v = 0; v < 16; v += 2) {
         const int r = r0 + wr + 32 * a + 8 * (v / 4) + 4 * h + (v % 4);  // even
         if (r >= rows) continue;
         const int w = r >> 1;
-        Are[(size_t)w * MM + cc] = -s * acc[a][b][v + 1];
-        Aim[(size_t)w * MM + cc] = s * acc[a][b][v];
+        const float re = -s * acc[a][b][v + 1], im = s * acc[a][b][v];
+        Are[(size_t)w * MA + pq.x] = re;
+        Aim[(size_t)w * MA + pq.x] = im;
+        if (pq.y != pq.x) {
+          Are[(size_t)w * MA + pq.y] = re;
+          Aim[(size_t)w * MA + pq.y] = im;
+        }
       }
     }
 }
