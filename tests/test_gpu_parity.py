@@ -8,7 +8,7 @@ import pytest
 
 from oracle import afqmc as A
 from synthetic import config_system, gaussian_fields, gen_system, random_walkers
-from tests.parity_helpers import (compare_state, gpu_state, gpu_U_to_oracle, log, make_pair,
+from tests.parity_helpers import (angle_diff, compare_state, gpu_state, gpu_U_to_oracle, log, make_pair,
                                   oracle_U_to_gpu, run_lockstep)
 
 pytestmark = pytest.mark.gpu
@@ -179,3 +179,51 @@ def test_gpu_fp64_beyond_mfma_tile_limits(torch_cuda, case):
     log(f"fp64 large shape {case}")
     worst, *_ = run_lockstep(s, nw, steps, dtau=0.005, label=case)
     log(f"{case} worst {worst}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["large", "medium"])
+def test_full_size_bench_launch_sampled(torch_cuda, precision, case):
+    """Full walker counts: the launch the benchmark times (large: M=128, N=32+32, N_g=800, 1024
+    walkers) and the medium workload (M=64, N=16+16, N_g=320, 512 walkers), fields drawn on the
+    device, QR and comb every 5 steps.  After three steps the state is copied, the fourth step
+    runs on the GPU, and the oracle repeats that step for sampled walkers one by one from the
+    copied state (its own Philox fields for the walkers' ids, force bias from their U)."""
+    import torch
+
+    import paper_1711_02242_amd as afq
+    s = config_system(case)
+    nw, seed, dt = (1024, 0, 0.005) if case == "large" else (512, 0, 0.005)
+    log(f"full-size launch sampled {case} {precision}")
+    gs = afq.System.from_synthetic(s, dtau=dt, precision=precision, qr_period=5, pop_period=5)
+    wk = gs.walkers(nw)
+    gs.init(wk)
+    for _ in range(3):
+        gs.step(wk, seed=seed)
+    before = gpu_state(wk)
+    k = wk.step
+    gs.step(wk, seed=seed)
+    after = gpu_state(wk)
+    gs.close()
+    S = A.setup(s.h0, s.h1, s.L, s.phi_up, s.phi_dn, dt)
+    P = A.Params(dtau=dt, qr_period=5, pop_period=5, w_max=max(100.0, nw / 10.0))
+    sample = np.array([0, nw // 3, (3 * nw) // 4, nw - 1])
+    Uu, Ud = gpu_U_to_oracle(before["U"][sample], s.n_up)
+    wo = A.init_walkers(S, len(sample), Uu, Ud)
+    wo.W = before["W"][sample].copy()
+    wo.walker_id = before["ids"][sample].copy()
+    wo.step = k
+    # the GPU's cached state stands for the walkers' (arg, log|ovlp|, E_L): the oracle's
+    # measurement of the same U agrees to rounding
+    assert angle_diff(wo.arg, before["arg"][sample]).max() < 1e-9
+    x = gaussian_fields(seed, 0, wo.walker_id, k, s.n_chol)
+    A.step(S, P, wo, x, None)
+    Ug_u, Ug_d = gpu_U_to_oracle(after["U"][sample], s.n_up)
+    tolU, tolE = (1e-10, 1e-10) if precision == "fp64" else (2e-5, 1e-4)
+    dU = max(np.abs(Ug_u - wo.U[0]).max(), np.abs(Ug_d - wo.U[1]).max()) / np.abs(wo.U[0]).max()
+    dW = np.abs(after["W"][sample] - wo.W).max() / np.abs(wo.W).max()
+    dA = angle_diff(after["arg"][sample], wo.arg).max()
+    dE = np.abs(after["e"][sample] - wo.e_loc).max()
+    log(f"  dU {dU:.2e} dW {dW:.2e} darg {dA:.2e} dE {dE:.2e} Ha")
+    assert dU < tolU and dW < max(tolU, 1e-8) and dA < max(tolU, 1e-8)
+    assert dE < (tolE * np.abs(wo.e_loc).max() if precision == "fp64" else tolE)
