@@ -87,7 +87,7 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
     return r;
   };
   const size_t M = S->M, G = S->G, nt = S->ntot, nd = S->n_det;
-  L.thetaT = take(nw * nd * nt * M * 16);
+  L.thetaT = take(S->mt.enabled ? 0 : nw * nd * nt * M * 16);   // FP64 VALU contraction only
   L.tcur = take(nw * G * 16);
   L.tpart = take(nw * nd * 2 * G * 16);
   L.exch = take(nw * nd * 2 * 16);
@@ -324,7 +324,8 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
     hipLaunchKernelGGL(k_overlap_mfma<NPAD>, grid, dim3(256), shm, S->stream, S->M, S->nup,     \
                        S->ndn, S->V, S->ht, (const cd*)w->U, w->weight, check_weight,          \
-                       at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet), at<cd>(ws, L.e1),           \
+                       S->mt.enabled ? nullptr : at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet),   \
+                       at<cd>(ws, L.e1),                                                       \
                        at<unsigned>(ws, L.wflag), packed, kind, S->mt.NP, S->mt.KP);          \
   } while (0)
   if (nmax <= 16)

@@ -449,8 +449,8 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
 //   T = V^T U             (16x16 blocks, K = M, U read from global as complex)
 //   [T | I] -> [I | T^-1] (Gauss-Jordan, partial pivoting, log det from the pivots)
 //   Theta^T = (T^-1)^T U^T  (16x16 blocks, K = N, complex product as four real ones)
-// Outputs: Theta^T (FP64), e1 = tr(ht Theta), log det T (complex), singular flags,
-// and optionally the packed MFMA operand of the contraction.
+// Outputs: e1 = tr(ht Theta), log det T (complex), singular flags, and the packed MFMA
+// operand of the contraction or (thetaT != NULL, for the FP64 VALU contraction) Theta^T in FP64.
 // ---------------------------------------------------------------------------
 template <int NPAD>
 __global__ void __launch_bounds__(256) k_overlap_mfma(
@@ -591,7 +591,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
   // ---- Theta^T[c][p] = sum_j Tinv[j][c] U^T[j][p] on MFMA (K = j, padded to NPAD)
   const int CB = (M + 15) / 16;
   const size_t per = (size_t)NP * KP;
-  cd* Tw = thetaT + ((size_t)wd_ * ntot + off) * M;
+  cd* Tw = thetaT ? thetaT + ((size_t)wd_ * ntot + off) * M : nullptr;
   const double* hts = ht + (size_t)off * M;
   double e1re = 0.0, e1im = 0.0;
   for (int t = wave; t < NB * CB; t += 4) {
@@ -614,7 +614,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       const int c = 16 * a + q + 4 * v, p = 16 * b + l16;
       if (c >= N || p >= M) continue;
       const cd th = mkc(cr[v], ci[v]);
-      Tw[(size_t)c * M + p] = th;
+      if (thetaT) Tw[(size_t)c * M + p] = th;   // FP64 copy only for the VALU contraction
       const double hv = hts[(size_t)c * M + p];
       e1re = fma(hv, th.re, e1re);
       e1im = fma(hv, th.im, e1im);
