@@ -45,7 +45,6 @@ struct afqmc_sys_s {
   hipStream_t stream;
   int device;
   // device, library-owned
-  double* L = nullptr;     // [G][M][M]
   double* Eh = nullptr;    // [M][M]
   double* V = nullptr;     // [ntot][M]
   double* Lh = nullptr;    // [G][ntot][M]
@@ -54,6 +53,8 @@ struct afqmc_sys_s {
   MfmaTables mt;           // packed low-precision copies for the MFMA contraction
   float* Lt32 = nullptr;   // [M(M+1)/2][Gp] FP32 transposed Cholesky tensor, lower triangle
   int* abpairs = nullptr;  // [M(M+1)/2][2] (q M + p, p M + q) of each packed column
+  double* Lt64 = nullptr;  // [M(M+1)/2][Gp64] FP64 packed L^T (FP64 A-build)
+  int Gp64 = 0;            // G rounded up to 16
   float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
   int Gp = 0;              // G rounded up to 32
   bool f32_prop = false;   // A-build and propagation on FP32 MFMA (mixed-precision modes)
@@ -282,7 +283,6 @@ void free_sys(afqmc_sys_s* S) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
   }
-  hipFree(S->L);
   hipFree(S->Eh);
   hipFree(S->V);
   hipFree(S->Lh);
@@ -290,6 +290,7 @@ void free_sys(afqmc_sys_s* S) {
   hipFree(S->status);
   hipFree(S->Lt32);
   hipFree(S->abpairs);
+  hipFree(S->Lt64);
   hipFree(S->lbar);
   hipFree(S->Eh32);
   hipFree(S->coef);
@@ -684,8 +685,7 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
   }
 
   int rc;
-  if ((rc = dev_upload(S, &S->L, G ? L_chol : nullptr, (size_t)G * M * M)) ||
-      (rc = dev_upload(S, &S->Eh, Eh.data(), (size_t)M * M)) ||
+  if ((rc = dev_upload(S, &S->Eh, Eh.data(), (size_t)M * M)) ||
       (rc = dev_upload(S, &S->V, Vr.data(), Vr.size())) ||
       (rc = dev_upload(S, &S->lbar, lb.data(), lb.size())) ||
       (rc = dev_upload(S, &S->Lh, Lh.data(), Lh.size())) ||
@@ -697,6 +697,35 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
   if (hipMemset(S->status, 0, sizeof(unsigned)) != hipSuccess) {
     free_sys(S);
     return AFQMC_E_HIP;
+  }
+  // packed pairs (q M + p, p M + q), p <= q, of the symmetric A-build; FP64 packed L^T
+  if (p->precision == AFQMC_FP64 || (p->precision != AFQMC_FP64 && M <= WIDE_KMAX &&
+                                     std::max(nup_i, ndn_i) <= 64)) {
+    const size_t MMh = (size_t)M * (M + 1) / 2;
+    std::vector<int> pairs(2 * MMh);
+    size_t k = 0;
+    for (int q = 0; q < M; ++q)
+      for (int pp = 0; pp <= q; ++pp, ++k) {
+        pairs[2 * k] = q * M + pp;
+        pairs[2 * k + 1] = pp * M + q;
+      }
+    if ((rc = dev_upload(S, &S->abpairs, pairs.data(), pairs.size()))) {
+      free_sys(S);
+      return rc;
+    }
+    if (p->precision == AFQMC_FP64) {
+      S->Gp64 = ((G + 15) / 16) * 16;
+      std::vector<double> lt(MMh * (S->Gp64 > 0 ? S->Gp64 : 1), 0.0);
+      k = 0;
+      for (int q = 0; q < M; ++q)
+        for (int pp = 0; pp <= q; ++pp, ++k)
+          for (int g = 0; g < G; ++g)
+            lt[k * S->Gp64 + g] = L_chol[(size_t)g * M * M + (size_t)q * M + pp];
+      if ((rc = dev_upload(S, &S->Lt64, lt.data(), lt.size()))) {
+        free_sys(S);
+        return rc;
+      }
+    }
   }
   if (multi) {
     S->multi = true;
@@ -728,20 +757,15 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     // lower triangle of every L^g (L^g is symmetric), one packed row per pair p <= q
     const size_t MMh = (size_t)M * (M + 1) / 2;
     std::vector<float> lt(MMh * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
-    std::vector<int> pairs(2 * MMh);
     {
       size_t k = 0;
       for (int q = 0; q < M; ++q)
-        for (int pp = 0; pp <= q; ++pp, ++k) {
-          pairs[2 * k] = q * M + pp;
-          pairs[2 * k + 1] = pp * M + q;
+        for (int pp = 0; pp <= q; ++pp, ++k)
           for (int g = 0; g < G; ++g)
             lt[k * S->Gp + g] = (float)L_chol[(size_t)g * M * M + (size_t)q * M + pp];
-        }
     }
     for (size_t e = 0; e < eh.size(); ++e) eh[e] = (float)Eh[e];
     if ((rc = dev_upload(S, &S->Lt32, lt.data(), lt.size())) ||
-        (rc = dev_upload(S, &S->abpairs, pairs.data(), pairs.size())) ||
         (rc = dev_upload(S, &S->Eh32, eh.data(), eh.size()))) {
       free_sys(S);
       return rc;
@@ -872,10 +896,11 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
   } else {
     if (s->G > 0) {
       Timer tm(s, KG_ABUILD);
-      constexpr int WT = 8;
-      dim3 grid((M * M + 255) / 256, (nw + WT - 1) / WT);
-      hipLaunchKernelGGL(k_abuild_fp64<WT>, grid, dim3(256), 0, s->stream, nw, M, s->G, s->s, s->L,
-                         at<cd>(ws, L.y), at<cd>(ws, L.A));
+      const int MMh = M * (M + 1) / 2;
+      dim3 grid((2 * nw + AB64_B - 1) / AB64_B, (MMh + AB64_B - 1) / AB64_B);
+      hipLaunchKernelGGL(k_abuild_f64mfma, grid, dim3(256), 0, s->stream, nw, s->G, MMh, M * M,
+                         s->Gp64, s->s, reinterpret_cast<const double*>(at<cd>(ws, L.y)), s->Lt64,
+                         reinterpret_cast<const int2*>(s->abpairs), at<cd>(ws, L.A));
       HIPCHK(hipGetLastError());
     }
     Timer tm(s, KG_PROP);
@@ -1227,15 +1252,17 @@ int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walker
                std::max(S.nup, S.ndn) <= 64;
   S.Gp = S.f32_prop ? ((G + 31) / 32) * 32 : 0;
   const size_t nt = S.ntot, MM = (size_t)M * M, g1 = G > 0 ? G : 1;
-  size_t sb = G > 0 ? (size_t)G * MM * 8 : 8;                 // L
-  sb += MM * 8 + n_det * nt * M * 8 + g1 * 8;                 // E_h, V, lbar
+  size_t sb = MM * 8 + n_det * nt * M * 8 + g1 * 8;          // E_h, V, lbar
   sb += (n_det * (size_t)G * nt * M > 0 ? n_det * (size_t)G * nt * M : 1) * 8;  // Lh
   sb += n_det * nt * M * 8 + 4;                              // ht, status
   if (S.multi) sb += (size_t)2 * n_det * 8;                  // coefficients
   if (S.mt.enabled) sb += S.mt.bytes;
-  if (S.f32_prop) {   // packed L^T, pair table, E_h (FP32)
-    const size_t MMh = (size_t)M * (M + 1) / 2;
-    sb += MMh * (S.Gp > 0 ? S.Gp : 1) * 4 + 2 * MMh * 4 + MM * 4;
+  const size_t MMh = (size_t)M * (M + 1) / 2;
+  if (S.f32_prop || p->precision == AFQMC_FP64) sb += 2 * MMh * 4;   // pair table
+  if (S.f32_prop) sb += MMh * (S.Gp > 0 ? S.Gp : 1) * 4 + MM * 4;    // packed L^T, E_h (FP32)
+  if (p->precision == AFQMC_FP64) {                                   // packed L^T (FP64)
+    const size_t gp64 = ((size_t)G + 15) / 16 * 16;
+    sb += MMh * (gp64 > 0 ? gp64 : 1) * 8;
   }
   *system_bytes = sb;
   const size_t nw = (size_t)n_walkers;

@@ -276,48 +276,6 @@ __global__ void __launch_bounds__(256) k_fields(
   if (capped) atomicOr(status, 0x10u);
 }
 
-// ---------------------------------------------------------------------------
-// Propagator exponent A_w = i s sum_g y_wg L^g (Sec. III.D.2), FP64.
-// Thread: one matrix element for WT walkers; y staged in LDS per g-chunk.
-// ---------------------------------------------------------------------------
-template <int WT>
-__global__ void __launch_bounds__(256) k_abuild_fp64(int nw, int M, int G, double s,
-                                                     const double* __restrict__ L,
-                                                     const cd* __restrict__ y,
-                                                     cd* __restrict__ A) {
-  constexpr int GC = 64;
-  __shared__ cd ys[WT][GC];
-  const int MM = M * M;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int w0 = blockIdx.y * WT;
-  double ar[WT], ai[WT];
-#pragma unroll
-  for (int k = 0; k < WT; ++k) ar[k] = ai[k] = 0.0;
-  for (int g0 = 0; g0 < G; g0 += GC) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < WT * GC; i += blockDim.x) {
-      const int k = i / GC, g = g0 + i % GC;
-      ys[k][i % GC] = (w0 + k < nw && g < G) ? y[(size_t)(w0 + k) * G + g] : mkc(0.0, 0.0);
-    }
-    __syncthreads();
-    if (e < MM) {
-      const int gn = min(GC, G - g0);
-      for (int gg = 0; gg < gn; ++gg) {
-        const double l = L[(size_t)(g0 + gg) * MM + e];
-#pragma unroll
-        for (int k = 0; k < WT; ++k) {
-          ar[k] = fma(ys[k][gg].re, l, ar[k]);
-          ai[k] = fma(ys[k][gg].im, l, ai[k]);
-        }
-      }
-    }
-  }
-  if (e < MM) {
-#pragma unroll
-    for (int k = 0; k < WT; ++k)
-      if (w0 + k < nw) A[(size_t)(w0 + k) * MM + e] = mkc(-s * ai[k], s * ar[k]);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Batched complex product out^T[c][i] = scale * sum_k Mat[i][k] in^T[c][k] for one

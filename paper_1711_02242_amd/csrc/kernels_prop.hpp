@@ -477,3 +477,98 @@ __global__ void __launch_bounds__(64 * NKC) k_propagate_f32_wide(
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// FP64 A-build on v_mfma_f64_16x16x4_f64, lower triangle only (A_w is symmetric):
+//   C[r][col] = sum_g Y[r][g] Lt[col][g],  r = 2w + (0: Re y, 1: Im y) read straight from the
+//   interleaved complex y [nw][G],  col = packed pair p <= q,  Lt FP64 [MMh][Gp] (zero beyond G).
+//   A_w[q][p] = A_w[p][q] = (-s C[2w+1][col], s C[2w][col])  (complex128 [nw][M][M]).
+// Tile 64 x 64 per workgroup, K chunks of 16 double-buffered in LDS, 4 waves of 32 x 32
+// (2 x 2 blocks).  Operand lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k;
+// output lane l, item v holds D[l/16 + 4v][l%16], so rows 2w and 2w + 1 of a walker sit in
+// lanes l and l + 16 (same v) and meet through one shuffle.
+// ---------------------------------------------------------------------------
+constexpr int AB64_B = 64, AB64_K = 16, AB64_LD = AB64_K + 2;
+
+__global__ void __launch_bounds__(256) k_abuild_f64mfma(int nw, int G, int MMh, int MA, int Gp,
+                                                        double s, const double* __restrict__ y,
+                                                        const double* __restrict__ Lt,
+                                                        const int2* __restrict__ pairs,
+                                                        cd* __restrict__ A) {
+  __shared__ __attribute__((aligned(16))) double As[2][AB64_B * AB64_LD];
+  __shared__ __attribute__((aligned(16))) double Bs[2][AB64_B * AB64_LD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rows = 2 * nw;
+  const int r0 = blockIdx.x * AB64_B, c0 = blockIdx.y * AB64_B;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int l16 = lane & 15, q = lane >> 4;
+  // each thread moves 4 doubles of A and 4 of B per K chunk: element e = tid + 256 i
+  double pa[4], pb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      const int rr = e >> 4, kk = e & 15;
+      const int r = r0 + rr, c = c0 + rr, g = k0 + kk;
+      pa[i] = (r < rows && g < G) ? y[((size_t)(r >> 1) * G + g) * 2 + (r & 1)] : 0.0;
+      pb[i] = (c < MMh && g < Gp) ? Lt[(size_t)c * Gp + g] : 0.0;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      const int rr = e >> 4, kk = e & 15;
+      As[buf][rr * AB64_LD + kk] = pa[i];
+      Bs[buf][rr * AB64_LD + kk] = pb[i];
+    }
+  };
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nk = (G + AB64_K - 1) / AB64_K;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload((kc + 1) * AB64_K);
+#pragma unroll
+    for (int ks = 0; ks < AB64_K / 4; ++ks) {
+      double fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) fa[a] = As[buf][(wr + 16 * a + l16) * AB64_LD + 4 * ks + q];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) fb[b] = Bs[buf][(wc + 16 * b + l16) * AB64_LD + 4 * ks + q];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    if (kc + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue: lane (q even) holds row 2w's value, lane + 16 row 2w + 1's
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int cc = c0 + wc + 16 * b + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double mine = acc[a][b][v];
+        const double odd = __shfl_down(mine, 16, 64);
+        const int r = r0 + wr + 16 * a + q + 4 * v;   // even for even q
+        if ((q & 1) || cc >= MMh || r >= rows) continue;
+        const int2 pq = pairs[cc];
+        const int w = r >> 1;
+        const cd val = mkc(-s * odd, s * mine);
+        A[(size_t)w * MA + pq.x] = val;
+        if (pq.y != pq.x) A[(size_t)w * MA + pq.y] = val;
+      }
+    }
+}
