@@ -904,6 +904,27 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
       HIPCHK(hipGetLastError());
     }
     Timer tm(s, KG_PROP);
+    if (M <= WIDE_KMAX && std::max(s->nup, s->ndn) <= 64) {
+      // FP64 MFMA propagation, one workgroup per (walker, spin, 32-row block)
+      const int Kp = ((M + 15) / 16) * 16;
+      const size_t shm = (size_t)2 * 32 * (Kp + 2) * 8;
+      const dim3 grid(nw, 2, (std::max(s->nup, s->ndn) + 31) / 32);
+#define PROP64(NKCV)                                                                           \
+  case NKCV:                                                                                   \
+    (void)hipFuncSetAttribute((const void*)k_propagate_f64<NKCV>,                              \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
+    hipLaunchKernelGGL(k_propagate_f64<NKCV>, grid, dim3(64 * NKCV), shm, s->stream, M, s->nup,  \
+                       s->ndn, Kp, s->G > 0 ? s->p.n_taylor : 0, s->Eh, at<cd>(ws, L.A),       \
+                       (cd*)w->U, w->weight);                                                  \
+    break;
+      switch (Kp / 16) {
+        PROP64(1) PROP64(2) PROP64(3) PROP64(4) PROP64(5) PROP64(6) PROP64(7)
+        PROP64(8) PROP64(9) PROP64(10) PROP64(11) PROP64(12) PROP64(13) PROP64(14)
+        default: return AFQMC_E_UNSUPPORTED;
+      }
+#undef PROP64
+      HIPCHK(hipGetLastError());
+    } else {
     dim3 grid((M + 63) / 64, (nt + 31) / 32, nw);
     cd* U = (cd*)w->U;
     cd* X0 = at<cd>(ws, L.X0);
@@ -922,6 +943,7 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
     hipLaunchKernelGGL((k_zmatmul_fp64<0, true>), grid, dim3(256), 0, s->stream, M, nt,
                        (const void*)s->Eh, Y, U, nullptr, 1.0, w->weight);
     HIPCHK(hipGetLastError());
+    }
   }
   // 4. periodic re-orthonormalization
   const bool qr_due = s->p.qr_period > 0 && (k + 1) % s->p.qr_period == 0;

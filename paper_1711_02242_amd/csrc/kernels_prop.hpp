@@ -572,3 +572,150 @@ __global__ void __launch_bounds__(256) k_abuild_f64mfma(int nw, int G, int MMh, 
       }
     }
 }
+
+// ---------------------------------------------------------------------------
+// FP64 propagation on v_mfma_f64_16x16x4_f64: u' = u E_h T_n(A) E_h for up to 32 orbitals
+// (one row block) of one spin of one walker per workgroup (grid: walkers x 2 spins x row
+// blocks), one wavefront per 16 output columns q.  The current term (Re / Im planes) sits
+// in LDS as the A operand; the B operands (rows q of the symmetric A_w, complex128, and of
+// E_h) are streamed per 16-wide K chunk.  Inside a chunk lane group q4 = lane / 16 takes
+// k = 16 kc + 4 q4 + e for its four MFMAs e, on both operands, so each lane's operands are
+// contiguous (the sum over k is unchanged).  Output lane l, item v: row l/16 + 4v, column l%16.
+// ---------------------------------------------------------------------------
+template <int NKC>
+__global__ void __launch_bounds__(64 * NKC) k_propagate_f64(
+    int M, int nup, int ndn, int Kp, int n_taylor, const double* __restrict__ Eh /*[M][M]*/,
+    const cd* __restrict__ A /*[nw][M][M]*/, cd* __restrict__ U,
+    const double* __restrict__ weight) {
+  extern __shared__ __attribute__((aligned(16))) double dsm[];
+  constexpr int RB = 2;                          // 16-row blocks per workgroup (32 rows)
+  const int w = blockIdx.x, s = blockIdx.y, rblk = blockIdx.z;
+  const int N = s ? ndn : nup, off = (s ? nup : 0) + 32 * rblk, ntot = nup + ndn;
+  const int nrows = min(32, N - 32 * rblk);
+  if (nrows <= 0 || !(weight[w] > 0.0)) return;  // uniform over the workgroup
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ldt = Kp + 2;
+  double* Tr = dsm;                 // [32][ldt]
+  double* Ti = dsm + 32 * ldt;      // [32][ldt]
+  const int j = lane & 15, q4 = lane >> 4;
+  const int qcol = 16 * wave + j;
+  const bool colok = qcol < M;
+  const size_t MM = (size_t)M * M;
+  const int nrb = (nrows + 15) / 16;
+  const double* Ehq = Eh + (size_t)(colok ? qcol : 0) * M;
+  const cd* Aq = A + (size_t)w * MM + (size_t)(colok ? qcol : 0) * M;
+
+  const cd* Uw = U + ((size_t)w * ntot + off) * M;
+  for (int e = tid; e < 32 * Kp; e += blockDim.x) {
+    const int c = e / Kp, p = e % Kp;
+    cd v = mkc(0.0, 0.0);
+    if (c < nrows && p < M) v = Uw[(size_t)c * M + p];
+    Tr[c * ldt + p] = v.re;
+    Ti[c * ldt + p] = v.im;
+  }
+  __syncthreads();
+
+  f64x4 yre[RB], yim[RB], cre[RB], cim[RB];
+  auto zero = [&](f64x4* a) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) a[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  };
+  // real B (E_h): C = T E_h
+  auto mul_real = [&]() {
+    zero(cre);
+    zero(cim);
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      double b[4];
+      const int p0 = 16 * kc + 4 * q4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[e] = (colok && p0 + e < M) ? Ehq[p0 + e] : 0.0;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= nrb) break;
+        const double* tr = &Tr[(16 * rb + j) * ldt + p0];
+        const double* ti = &Ti[(16 * rb + j) * ldt + p0];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[e], b[e], cre[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ti[e], b[e], cim[rb], 0, 0, 0);
+        }
+      }
+    }
+  };
+  auto store_planes = [&](const f64x4* pr, const f64x4* pi) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      if (rb < nrb && qcol < Kp) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Tr[(16 * rb + q4 + 4 * v) * ldt + qcol] = pr[rb][v];
+          Ti[(16 * rb + q4 + 4 * v) * ldt + qcol] = pi[rb][v];
+        }
+      }
+    }
+  };
+
+  mul_real();   // X = U E_h: the first term and Y = X
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    yre[rb] = cre[rb];
+    yim[rb] = cim[rb];
+  }
+  store_planes(cre, cim);
+  __syncthreads();
+  for (int n = 1; n <= n_taylor; ++n) {
+    zero(cre);
+    zero(cim);
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      double br[4], bi[4];
+      const int p0 = 16 * kc + 4 * q4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const cd a = (colok && p0 + e < M) ? Aq[p0 + e] : mkc(0.0, 0.0);
+        br[e] = a.re;
+        bi[e] = a.im;
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= nrb) break;
+        const double* tr = &Tr[(16 * rb + j) * ldt + p0];
+        const double* ti = &Ti[(16 * rb + j) * ldt + p0];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[e], br[e], cre[rb], 0, 0, 0);
+          cre[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ti[e], bi[e], cre[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(tr[e], bi[e], cim[rb], 0, 0, 0);
+          cim[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ti[e], br[e], cim[rb], 0, 0, 0);
+        }
+      }
+    }
+    const double inv = 1.0 / (double)n;
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      cre[rb] *= inv;
+      cim[rb] *= inv;
+      yre[rb] += cre[rb];
+      yim[rb] += cim[rb];
+    }
+    store_planes(cre, cim);
+    __syncthreads();
+  }
+  store_planes(yre, yim);   // U' = Y E_h
+  __syncthreads();
+  mul_real();
+  cd* Uo = U + ((size_t)w * ntot + off) * M;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    if (rb >= nrb || !colok) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = 16 * rb + q4 + 4 * v;
+      if (c < nrows) Uo[(size_t)c * M + qcol] = mkc(cre[rb][v], cim[rb][v]);
+    }
+  }
+}
