@@ -318,7 +318,7 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
   const int kind = !S->mt.enabled ? 0
                    : S->mt.precision == AFQMC_FP64 ? 3
                    : S->mt.precision == AFQMC_BF16X3 ? 2 : 1;
-  const size_t shm = (size_t)nmax * (2 * nmax + 1) * 16 + (size_t)nmax * 16 + 64;
+  const size_t shm = (size_t)nmax * (2 * nmax + 1) * 16 + 64;   // [T | I] and 8 doubles
 #define OVL(NPAD)                                                                              \
   do {                                                                                         \
     (void)hipFuncSetAttribute((const void*)k_overlap_mfma<NPAD>,                               \

@@ -483,10 +483,10 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
   if (check_weight && !(weight[w] > 0.0)) return;
   const int lda = 2 * N + 1;
   cd* Ag = reinterpret_cast<cd*>(smem_raw);          // [N][2N+1]
-  cd* fac = Ag + (size_t)N * lda;                     // [N]
-  double* red = reinterpret_cast<double*>(fac + N);  // [8]
+  double* red = reinterpret_cast<double*>(Ag + (size_t)N * lda);  // [8]
   __shared__ int s_piv, s_sing, s_nswap;
   __shared__ double s_la, s_ar;
+  __shared__ cd s_pk;
   const int l16 = lane & 15, q = lane >> 4;
   const cd* Uw = U + ((size_t)w * ntot + off) * M;
   const double* Vs = V + (size_t)off * M;
@@ -522,7 +522,12 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
     s_ar = 0.0;
   }
   __syncthreads();
-  // ---- Gauss-Jordan with partial pivoting
+  // ---- Gauss-Jordan with partial pivoting, three barriers per pivot k:
+  //   (1) wave 0 finds the pivot row and records the pivot value;
+  //   (2) rows k and piv are exchanged and the new row k is divided by the pivot;
+  //   (3) every other row i loses A[i][k] times row k.
+  // Columns left of k are never read again, so (2) starts at column k and (3) at k + 1;
+  // column k itself is not eliminated, which lets (3) read its multipliers A[i][k] in place.
   for (int k = 0; k < N; ++k) {
     if (tid < 64) {
       double best = -1.0;
@@ -546,33 +551,29 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       }
       if (lane == 0) {
         s_piv = bi;
+        s_pk = Ag[bi * lda + k];
         if (!(best > 0.0)) s_sing = 1;
         if (bi != k) s_nswap += 1;
+        if (best > 0.0) {
+          s_la += log(hypot(s_pk.re, s_pk.im));
+          s_ar += atan2(s_pk.im, s_pk.re);
+        }
       }
     }
     __syncthreads();
     if (s_sing) break;
     const int piv = s_piv;
-    if (piv != k) {
-      for (int j = tid; j < 2 * N; j += blockDim.x) {
-        const cd tmp = Ag[k * lda + j];
-        Ag[k * lda + j] = Ag[piv * lda + j];
-        Ag[piv * lda + j] = tmp;
-      }
+    const cd pk = s_pk;
+    for (int j = k + tid; j < 2 * N; j += blockDim.x) {
+      const cd rk = Ag[k * lda + j], rp = Ag[piv * lda + j];
+      Ag[k * lda + j] = cdiv(rp, pk);
+      if (piv != k) Ag[piv * lda + j] = rk;
     }
     __syncthreads();
-    const cd pk = Ag[k * lda + k];
-    if (tid < N) fac[tid] = Ag[tid * lda + k];
-    if (tid == 0) {
-      s_la += log(hypot(pk.re, pk.im));
-      s_ar += atan2(pk.im, pk.re);
-    }
-    __syncthreads();
-    for (int j = tid; j < 2 * N; j += blockDim.x) Ag[k * lda + j] = cdiv(Ag[k * lda + j], pk);
-    __syncthreads();
-    for (int e = tid; e < N * 2 * N; e += blockDim.x) {
-      const int i = e / (2 * N), j = e % (2 * N);
-      if (i != k) cfms(Ag[i * lda + j], fac[i], Ag[k * lda + j]);
+    const int ncol = 2 * N - (k + 1);
+    for (int e = tid; e < N * ncol; e += blockDim.x) {
+      const int i = e / ncol, j = k + 1 + e % ncol;
+      if (i != k) cfms(Ag[i * lda + j], Ag[i * lda + k], Ag[k * lda + j]);
     }
     __syncthreads();
   }
