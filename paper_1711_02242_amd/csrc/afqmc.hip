@@ -949,8 +949,16 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
   const bool qr_due = s->p.qr_period > 0 && (k + 1) % s->p.qr_period == 0;
   if (qr_due) {
     Timer tm(s, KG_QR);
-    hipLaunchKernelGGL(k_mgs, dim3(nw, 2), dim3(256), 0, s->stream, M, s->nup, s->ndn, (cd*)w->U,
-                       w->weight, s->status, at<double>(ws, L.logR));
+    const size_t shm = (size_t)std::max(s->nup, s->ndn) * M * 16;
+    if (shm <= 128 * 1024) {
+      (void)hipFuncSetAttribute((const void*)k_mgs<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm);
+      hipLaunchKernelGGL(k_mgs<true>, dim3(nw, 2), dim3(256), shm, s->stream, M, s->nup, s->ndn,
+                         (cd*)w->U, w->weight, s->status, at<double>(ws, L.logR));
+    } else {
+      hipLaunchKernelGGL(k_mgs<false>, dim3(nw, 2), dim3(256), 0, s->stream, M, s->nup, s->ndn,
+                         (cd*)w->U, w->weight, s->status, at<double>(ws, L.logR));
+    }
     HIPCHK(hipGetLastError());
   }
   // 5-6. overlap, Theta, local energy of the new determinants

@@ -355,10 +355,14 @@ __global__ void __launch_bounds__(256) k_zmatmul_fp64(int M, int ntot, const voi
 // column k is normalized, then its projection is removed from every later
 // column.  Rows of U (orbital-major) are updated in place in global memory.
 // ---------------------------------------------------------------------------
+template <bool IN_LDS>
 __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __restrict__ U,
                                              const double* __restrict__ weight,
                                              unsigned* __restrict__ status,
                                              double* __restrict__ logR /*[nw][2]*/) {
+  // IN_LDS: the N x M block is staged in LDS (dynamic, N M complex), orthonormalized there and
+  // written back once; otherwise it is processed in place in global memory.
+  extern __shared__ __attribute__((aligned(16))) unsigned char mgs_smem[];
   __shared__ cd dots[64];
   __shared__ double s_norm;
   const int w = blockIdx.x, s = blockIdx.y;
@@ -370,8 +374,13 @@ __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __rest
     return;
   }
   if (!(weight[w] > 0.0)) return;
-  cd* Uw = U + ((size_t)w * ntot + off) * M;
+  cd* Ug = U + ((size_t)w * ntot + off) * M;
   const int tid = threadIdx.x, lane = tid % AFQMC_WAVE, wid = tid / AFQMC_WAVE;
+  cd* Uw = IN_LDS ? reinterpret_cast<cd*>(mgs_smem) : Ug;
+  if (IN_LDS) {
+    for (int e = tid; e < N * M; e += blockDim.x) Uw[e] = Ug[e];
+    __syncthreads();
+  }
   double lr = 0.0;  // sum_k log r_kk: QR divides <Phi_T|Psi> by det R (Theorem 1.5)
   const int nwave = blockDim.x / AFQMC_WAVE;
   for (int k = 0; k < N; ++k) {
@@ -412,6 +421,8 @@ __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __rest
       __syncthreads();
     }
   }
+  if (IN_LDS)
+    for (int e = tid; e < N * M; e += blockDim.x) Ug[e] = Uw[e];
   if (tid == 0) logR[2 * w + s] = lr;
 }
 
