@@ -216,14 +216,19 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
 /* Tile shapes of the local-energy contraction (the dominant kernel).  The register-resident
  * FP32 / BF16x3 kernel takes W = 4 or 2 walkers per workgroup (W = 2 gives small walker
  * populations twice the workgroups); the wide kernel takes one walker per workgroup and splits
- * Theta's columns over its wavefronts.  Every variant computes the same quantities.
+ * Theta's columns over its wavefronts; the flattened kernel stacks the N-row blocks of q
+ * consecutive Cholesky vectors and puts Re and Im Theta side by side, so N is padded to a
+ * multiple of 16 once per q blocks instead of once per block and plane (N up to 64, M up to
+ * 224).  Every variant computes the same quantities.
  *   AFQMC_TILE_DEFAULT  W = 4 where the shape fits it (N <= 32, M <= 128), else wide
  *   AFQMC_TILE_W4, AFQMC_TILE_W2, AFQMC_TILE_WIDE  (wide needs N_P >= 32, i.e. N > 16 or M > 128)
+ *   AFQMC_TILE_FLAT  (any FP32 / BF16x3 shape)
  * The FP64 mode has one contraction kernel per shape and accepts only the default. */
 #define AFQMC_TILE_DEFAULT 0
 #define AFQMC_TILE_W4 1
 #define AFQMC_TILE_W2 2
 #define AFQMC_TILE_WIDE 3
+#define AFQMC_TILE_FLAT 4
 
 /* Autotuner: times every variant valid for the system's shape on these walkers (initialized
  * or measured; one untimed and three timed launches each, on the system's stream, writing only

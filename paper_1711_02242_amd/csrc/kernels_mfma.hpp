@@ -38,7 +38,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int MFMA_KMAX = 128;   // K limit of the register-resident contraction kernels
 constexpr int WIDE_KMAX = 224;   // K limit of the wide (workgroup-per-walker) kernel
 // Contraction kernel variants (tile shapes) the autotuner chooses among.
-enum { TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_COUNT = 4 };
+enum { TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_FLAT = 4, TILE_COUNT = 5 };
 
 struct MfmaTables {
   bool enabled = false;
@@ -164,6 +164,7 @@ inline void mfma_free_tables(MfmaTables& t) {
 
 #include "contract_mfma.hpp"
 #include "contract_wide.hpp"
+#include "contract_flat.hpp"
 
 inline size_t mfma_contract_lds_bytes(const MfmaTables& t, int wpb) {
   const bool bf = t.precision == AFQMC_BF16X3;
@@ -182,6 +183,9 @@ inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
     case TILE_W4:
     case TILE_W2: return !t.wide;
     case TILE_WIDE: return t.NP >= 32 && t.KP <= WIDE_KMAX;
+    case TILE_FLAT:
+      return t.KP <= WIDE_KMAX && t.NP <= 64 &&
+             flat_launch(t.nup, t.ndn, t.G, t.precision == AFQMC_BF16X3).lds <= FLAT_LDS_CAP;
     default: return false;
   }
 }
@@ -374,6 +378,47 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   }
   const bool bf = t.precision == AFQMC_BF16X3;
   if (!mfma_tile_valid(t, tile)) tile = TILE_DEFAULT;
+  if (tile == TILE_FLAT) {
+    const FlatLaunch f = flat_launch(t.nup, t.ndn, G, bf);
+    dim3 grid(nw, 2 * n_det);
+#define LAUNCH_FLAT_KR(BFV, KM, RTV)                                                              \
+  hipLaunchKernelGGL((k_contract_mfma_flat<KM, BFV, RTV>), grid, dim3(64 * f.waves), f.lds, st,  \
+                     nw, G, t.nup, t.ndn, t.NP, t.KP, f.qup, f.qdn, f.LDR, (const void*)t.Lp,     \
+                     thetaP, weight, tpart, exch)
+  // one instantiation per row-tile count (1 .. 7; BF16x3 1 .. 4)
+#define LAUNCH_FLAT_K(BFV, KM)                                                                    \
+  do {                                                                                            \
+    switch (f.RT) {                                                                               \
+      case 1: LAUNCH_FLAT_KR(BFV, KM, 1); break;                                                  \
+      case 2: LAUNCH_FLAT_KR(BFV, KM, 2); break;                                                  \
+      case 3: LAUNCH_FLAT_KR(BFV, KM, 3); break;                                                  \
+      case 4: LAUNCH_FLAT_KR(BFV, KM, 4); break;                                                  \
+      case 5: LAUNCH_FLAT_KR(BFV, KM, BFV ? 4 : 5); break;                                        \
+      case 6: LAUNCH_FLAT_KR(BFV, KM, BFV ? 4 : 6); break;                                        \
+      default: LAUNCH_FLAT_KR(BFV, KM, BFV ? 4 : 7); break;                                       \
+    }                                                                                             \
+  } while (0)
+  // and per K chunk count (K_P = 32 .. 224 in steps of 32)
+#define LAUNCH_FLAT(BFV)                                                                          \
+  do {                                                                                            \
+    constexpr int KCH_ = BFV ? 32 : 16;                                                           \
+    switch (t.KP / KCH_) {                                                                        \
+      case 32 / KCH_: LAUNCH_FLAT_K(BFV, 32 / KCH_); break;                                       \
+      case 64 / KCH_: LAUNCH_FLAT_K(BFV, 64 / KCH_); break;                                       \
+      case 96 / KCH_: LAUNCH_FLAT_K(BFV, 96 / KCH_); break;                                       \
+      case 128 / KCH_: LAUNCH_FLAT_K(BFV, 128 / KCH_); break;                                     \
+      case 160 / KCH_: LAUNCH_FLAT_K(BFV, 160 / KCH_); break;                                     \
+      case 192 / KCH_: LAUNCH_FLAT_K(BFV, 192 / KCH_); break;                                     \
+      default: LAUNCH_FLAT_K(BFV, 224 / KCH_); break;                                             \
+    }                                                                                             \
+  } while (0)
+    if (bf) LAUNCH_FLAT(true);
+    else LAUNCH_FLAT(false);
+#undef LAUNCH_FLAT
+#undef LAUNCH_FLAT_K
+#undef LAUNCH_FLAT_KR
+    return hipGetLastError();
+  }
   if (t.wide || tile == TILE_WIDE) {
     dim3 grid(nw, 2 * n_det);
 #define LAUNCH_WIDE_K(NPV, BFV, KM)                                                             \

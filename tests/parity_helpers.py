@@ -29,9 +29,10 @@ def oracle_U_to_gpu(Uu: np.ndarray, Ud: np.ndarray) -> np.ndarray:
 
 def make_pair(s, nw: int, *, dtau: float, precision: str = "fp64", qr_period: int = 5,
               pop_period: int = 5, n_taylor: int = 6, U=None, weight_mode: str = "phaseless",
-              mean_field: bool = False, closed_shell: bool = False, trial=None):
+              mean_field: bool = False, closed_shell: bool = False, trial=None, tile=None):
     """Oracle and GPU system on the same inputs.  ``trial`` = (coeffs, ups, dns) selects a
-    multi-determinant trial instead of the system's single determinant."""
+    multi-determinant trial instead of the system's single determinant; ``tile`` forces a
+    contraction variant."""
     import paper_1711_02242_amd as afq
     P = A.Params(dtau=dtau, n_taylor=n_taylor, qr_period=qr_period, pop_period=pop_period,
                  weight_mode=weight_mode)
@@ -45,6 +46,8 @@ def make_pair(s, nw: int, *, dtau: float, precision: str = "fp64", qr_period: in
         coeffs, ups, dns = trial
         S = A.setup_multi(s.h0, s.h1, s.L, coeffs, ups, dns, dtau, mean_field=mean_field)
         gs = afq.System.multidet(s.h0, s.h1, s.L, coeffs, np.array(ups), np.array(dns), **kw)
+    if tile is not None:
+        gs.set_tile(tile)
     wk = gs.walkers(nw)
     gs.init(wk)
     if U is None:
@@ -103,11 +106,12 @@ def run_lockstep(s, nw: int, steps: int, *, dtau: float, precision: str = "fp64"
                  explicit_fields: bool = True, seed: int = 0, rtol: float = 1e-10,
                  qr_period: int = 5, pop_period: int = 5, check_every: int = 1, U=None,
                  label: str = "", weight_mode: str = "phaseless", mean_field: bool = False,
-                 closed_shell: bool = False, trial=None):
+                 closed_shell: bool = False, trial=None, tile=None):
     import torch
     S, P, wo, gs, wk = make_pair(s, nw, dtau=dtau, precision=precision, qr_period=qr_period,
                                  pop_period=pop_period, U=U, weight_mode=weight_mode,
-                                 mean_field=mean_field, closed_shell=closed_shell, trial=trial)
+                                 mean_field=mean_field, closed_shell=closed_shell, trial=trial,
+                                 tile=tile)
     compare_state(S, wo, gpu_state(wk), s.n_up, rtol, f"{label} init")
     worst = {}
     for k in range(steps):
