@@ -219,16 +219,19 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
  * Theta's columns over its wavefronts; the flattened kernel stacks the N-row blocks of q
  * consecutive Cholesky vectors and puts Re and Im Theta side by side, so N is padded to a
  * multiple of 16 once per q blocks instead of once per block and plane (N up to 64, M up to
- * 224).  Every variant computes the same quantities.
+ * 224); the stacked-row kernel stacks the rows the same way but keeps Re and Im Theta as two
+ * operands of 16 columns (N padded to a multiple of 16, half the operand traffic per flop).
+ * Every variant computes the same quantities.
  *   AFQMC_TILE_DEFAULT  W = 4 where the shape fits it (N <= 32, M <= 128), else wide
  *   AFQMC_TILE_W4, AFQMC_TILE_W2, AFQMC_TILE_WIDE  (wide needs N_P >= 32, i.e. N > 16 or M > 128)
- *   AFQMC_TILE_FLAT  (any FP32 / BF16x3 shape)
+ *   AFQMC_TILE_FLAT, AFQMC_TILE_STACK  (any FP32 / BF16x3 shape)
  * The FP64 mode has one contraction kernel per shape and accepts only the default. */
 #define AFQMC_TILE_DEFAULT 0
 #define AFQMC_TILE_W4 1
 #define AFQMC_TILE_W2 2
 #define AFQMC_TILE_WIDE 3
 #define AFQMC_TILE_FLAT 4
+#define AFQMC_TILE_STACK 5
 
 /* Autotuner: times every variant valid for the system's shape on these walkers (initialized
  * or measured; one untimed and three timed launches each, on the system's stream, writing only

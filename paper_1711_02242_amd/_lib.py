@@ -26,7 +26,7 @@ EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walk
            "afqmc_batch_create", "afqmc_batch_step", "afqmc_batch_destroy", "afqmc_autotune",
            "afqmc_set_tile", "afqmc_get_tile", "afqmc_energy_enqueue", "afqmc_footprint_bytes"]
 
-TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4}
+TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5}
 
 
 class Params(C.Structure):

@@ -38,7 +38,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int MFMA_KMAX = 128;   // K limit of the register-resident contraction kernels
 constexpr int WIDE_KMAX = 224;   // K limit of the wide (workgroup-per-walker) kernel
 // Contraction kernel variants (tile shapes) the autotuner chooses among.
-enum { TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_FLAT = 4, TILE_COUNT = 5 };
+enum {
+  TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_FLAT = 4, TILE_STACK = 5,
+  TILE_COUNT = 6
+};
 
 struct MfmaTables {
   bool enabled = false;
@@ -184,8 +187,12 @@ inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
     case TILE_W2: return !t.wide;
     case TILE_WIDE: return t.NP >= 32 && t.KP <= WIDE_KMAX;
     case TILE_FLAT:
-      return t.KP <= WIDE_KMAX && t.NP <= 64 &&
-             flat_launch(t.nup, t.ndn, t.G, t.precision == AFQMC_BF16X3).lds <= FLAT_LDS_CAP;
+    case TILE_STACK: {
+      if (t.KP > WIDE_KMAX || t.NP > 64) return false;
+      const FlatLaunch f =
+          flat_launch(t.nup, t.ndn, t.G, t.precision == AFQMC_BF16X3, tile == TILE_STACK);
+      return f.ok && f.lds <= FLAT_LDS_CAP;
+    }
     default: return false;
   }
 }
@@ -378,14 +385,25 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   }
   const bool bf = t.precision == AFQMC_BF16X3;
   if (!mfma_tile_valid(t, tile)) tile = TILE_DEFAULT;
-  if (tile == TILE_FLAT) {
-    const FlatLaunch f = flat_launch(t.nup, t.ndn, G, bf);
+  if (tile == TILE_FLAT || tile == TILE_STACK) {
+    const bool stk = tile == TILE_STACK;
+    const FlatLaunch f = flat_launch(t.nup, t.ndn, G, bf, stk);
     dim3 grid(nw, 2 * n_det);
 #define LAUNCH_FLAT_KR(BFV, KM, RTV)                                                              \
-  hipLaunchKernelGGL((k_contract_mfma_flat<KM, BFV, RTV>), grid, dim3(64 * f.waves), f.lds, st,  \
-                     nw, G, t.nup, t.ndn, t.NP, t.KP, f.qup, f.qdn, f.LDR, (const void*)t.Lp,     \
-                     thetaP, weight, tpart, exch)
-  // one instantiation per row-tile count (1 .. 7; BF16x3 1 .. 4)
+  do {                                                                                            \
+    if (stk)                                                                                      \
+      hipLaunchKernelGGL((k_contract_mfma_stack<KM, BFV, ((RTV) > (BFV ? 3 : STACK_MAX_RT)        \
+                                                              ? (BFV ? 3 : STACK_MAX_RT)          \
+                                                              : (RTV))>),                         \
+                         grid, dim3(64 * f.waves), f.lds, st, nw, G, t.nup, t.ndn, t.NP, t.KP,    \
+                         f.qup, f.qdn, f.LDR, (const void*)t.Lp, thetaP, weight, tpart, exch);    \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_contract_mfma_flat<KM, BFV, (RTV)>), grid, dim3(64 * f.waves), f.lds, \
+                         st, nw, G, t.nup, t.ndn, t.NP, t.KP, f.qup, f.qdn, f.LDR,                \
+                         (const void*)t.Lp, thetaP, weight, tpart, exch);                         \
+  } while (0)
+  // one instantiation per row-tile count (flat 1 .. 7, BF16x3 1 .. 4; stack 1 .. 7, BF16x3
+  // 1 .. 3)
 #define LAUNCH_FLAT_K(BFV, KM)                                                                    \
   do {                                                                                            \
     switch (f.RT) {                                                                               \

@@ -1,6 +1,7 @@
-"""The flattened contraction variant (tile "flat": the N-row blocks of q consecutive Cholesky
-vectors stacked, [Re Theta | Im Theta] side by side) against the FP64 oracle, on shapes that
-exercise its group boundaries: a tail group shorter than q, unequal spins (different q per
+"""The stacked-row contraction variants against the FP64 oracle: tile "flat" (the N-row blocks
+of q consecutive Cholesky vectors stacked, [Re Theta | Im Theta] side by side in 16-column
+blocks) and tile "stack" (the same rows, Re and Im Theta as two 16-column operands), on shapes
+that exercise their group boundaries: a tail group shorter than q, unequal spins (different q per
 spin), an empty spin, N below and above 16, no Cholesky vectors, the wide shapes, and a
 multi-determinant trial.  Static: per-walker E_L within 1e-4 Ha.  Dynamic: lockstep runs, in
 which the force-bias traces of every Cholesky vector drive the propagation (a trace written
@@ -34,16 +35,32 @@ SHAPES = {
 }
 
 
+TILES = ["flat", "stack"]
+
+
+def _supported(tile, precision, s):
+    """The stacked-row BF16x3 kernel holds at most 3 row tiles (N <= 48)."""
+    return not (tile == "stack" and precision == "bf16x3" and max(s.n_up, s.n_dn) > 48)
+
+
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("shape", list(SHAPES))
-def test_flat_static_local_energy(shape, precision):
+def test_flat_static_local_energy(shape, precision, tile):
     import torch
+
+    import paper_1711_02242_amd as afq
     make, nw = SHAPES[shape]
     s = make()
-    log(f"flat static {precision} {shape} M={s.M} N={s.n_up}+{s.n_dn} G={s.n_chol}")
+    log(f"{tile} static {precision} {shape} M={s.M} N={s.n_up}+{s.n_dn} G={s.n_chol}")
+    if not _supported(tile, precision, s):
+        gs = afq.System.from_synthetic(s, dtau=0.005, precision=precision)
+        with pytest.raises(afq.AfqmcError):
+            gs.set_tile(tile)
+        return
     U = random_walkers(s, nw, seed=99, amplitude=0.4)
-    S, P, wo, gs, wk = make_pair(s, nw, dtau=0.005, precision=precision, U=U, tile="flat")
-    assert gs.tile == "flat"
+    S, P, wo, gs, wk = make_pair(s, nw, dtau=0.005, precision=precision, U=U, tile=tile)
+    assert gs.tile == tile
     st = gpu_state(wk)
     err = np.abs(st["e"] - wo.e_loc).max()
     log(f"  max |dE_L| = {err:.3e} Ha")
@@ -56,10 +73,11 @@ def test_flat_static_local_energy(shape, precision):
     assert np.abs(st["e"] - e_def).max() < 2e-5
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("case", ["ragged_tail", "open_shell", "empty_spin", "n17_m70",
                                   "n34_m136", "no_cholesky"])
-def test_flat_dynamic_drift(case, precision):
+def test_flat_dynamic_drift(case, precision, tile):
     if case == "no_cholesky":
         s, nw = gen_system(9, 2, 0, seed=8), 5
         steps, dt = 10, 0.05
@@ -67,33 +85,35 @@ def test_flat_dynamic_drift(case, precision):
         make, nw = SHAPES[case]
         s = make()
         steps, dt = (12, 0.01) if s.M <= 40 else (5, 0.005)
-    log(f"flat dynamic {precision} {case}")
+    log(f"{tile} dynamic {precision} {case}")
     worst, gs, wk, S, wo = run_lockstep(s, nw, steps, dtau=dt, precision=precision, rtol=1e-4,
-                                        label=f"flat-{case}-{precision}", tile="flat")
+                                        label=f"{tile}-{case}-{precision}", tile=tile)
     st = gpu_state(wk)
     alive = wo.W > 0
     assert np.abs(st["e"][alive] - wo.e_loc[alive]).max() < EL_TOL
     log(f"  worst {worst}")
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_flat_multidet_lockstep(precision):
+def test_flat_multidet_lockstep(precision, tile):
     s = config_system("tiny")
     trial = noci_trial(s, 4, seed=3)
-    log(f"flat multidet lockstep {precision}")
+    log(f"{tile} multidet lockstep {precision}")
     worst, *_ = run_lockstep(s, 16, 30, dtau=0.01, precision=precision, rtol=1e-4,
-                             label=f"flat-md-{precision}", trial=trial, tile="flat")
+                             label=f"{tile}-md-{precision}", trial=trial, tile=tile)
     log(f"  worst {worst}")
 
 
-def test_flat_is_deterministic():
+@pytest.mark.parametrize("tile", TILES)
+def test_flat_is_deterministic(tile):
     """No atomics: two launches on the same walkers give the same bits."""
     import torch
 
     import paper_1711_02242_amd as afq
     s = gen_system(86, 21, 100, seed=13)
     gs = afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
-    gs.set_tile("flat")
+    gs.set_tile(tile)
     wk = gs.walkers(64)
     gs.init(wk)
     Uu, Ud = random_walkers(s, 64, seed=4, amplitude=0.4)
@@ -110,5 +130,6 @@ def test_flat_refused_in_fp64():
     import paper_1711_02242_amd as afq
     s = config_system("tiny")
     gs = afq.System.from_synthetic(s, dtau=0.01, precision="fp64")
-    with pytest.raises(afq.AfqmcError):
-        gs.set_tile("flat")
+    for tile in TILES:
+        with pytest.raises(afq.AfqmcError):
+            gs.set_tile(tile)

@@ -1,4 +1,4 @@
-"""Contraction tile variants (walkers per workgroup, wide and flattened kernels) and the autotuner: every
+"""Contraction tile variants (walkers per workgroup, wide, flattened and stacked-row kernels) and the autotuner: every
 variant meets the parity bar against the FP64 oracle, and the variants agree with each other."""
 
 import numpy as np
@@ -33,7 +33,7 @@ def test_every_tile_meets_the_bar(shape, precision):
     gs.init(wk)
     wk.U.copy_(torch.from_numpy(oracle_U_to_gpu(Uu, Ud)))
     energies = {}
-    for tile in ("w4", "w2", "wide", "flat"):
+    for tile in ("w4", "w2", "wide", "flat", "stack"):
         if tile == "wide" and max(s.n_up, s.n_dn) <= 16:
             with pytest.raises(afq.AfqmcError):
                 gs.set_tile(tile)
@@ -58,7 +58,7 @@ def test_autotune_picks_a_valid_tile_and_reuses_it():
     gs.init(wk)
     tile, ms = gs.autotune(wk, reuse=False)
     log(f"autotune: {tile} {ms:.3f} ms")
-    assert tile in ("w4", "w2", "wide", "flat") and ms > 0 and gs.tile == tile
+    assert tile in ("w4", "w2", "wide", "flat", "stack") and ms > 0 and gs.tile == tile
     gs2 = afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
     wk2 = gs2.walkers(64)
     gs2.init(wk2)
