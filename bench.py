@@ -344,11 +344,17 @@ def main():
     avg_s = (ms_c / max(n_c, 1)) * 1e-3
     achieved = flops / avg_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    # attainable rate of the same MFMA instruction family (register-only microbenchmark, run
+    # after the timed region): the clock the device holds under MFMA load shows here
+    import paper_1711_02242_amd as afq
+    att = afq.mfma_peak(args.precision) / (3.0 if args.precision == "bf16x3" else 1.0)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": recorded_traffic(args.precision),
                 "traffic_unit": "bytes/launch",
                 "kernel": "local-energy contraction", "avg_launch_ms": round(ms_c / max(n_c, 1), 4),
-                "flops_per_launch": flops}
+                "flops_per_launch": flops, "attainable": round(att, 2),
+                "frac_attainable": round(achieved / att, 4),
+                "attainable_method": "afqmc_mfma_peak: register-only MFMA chains on every SIMD"}
     kernels_ms = {k: round(v[0] / max(args.steps, 1), 4) for k, v in kt.items()}
     eprint(f"bench: {ms_step:.3f} ms/step, {value:.1f} walker-steps/s; per-step kernel ms {kernels_ms}")
     eprint(f"bench: E_mix = {e[0] / e[2]:.8f}, alive {e[3]}, status {e[4]:#x}")
@@ -390,6 +396,8 @@ def main():
                          "unit": "walker-steps/s", "ms_per_step": round(1e3 * dt4 / args.steps, 3),
                          "contraction_fp32_equivalent_tflops": round(ach4, 2),
                          "contraction_frac_of_bf16_peak_over_3": round(ach4 / PEAK_TFLOPS["bf16x3"], 4),
+                         "contraction_frac_of_attainable_bf16_over_3":
+                             round(ach4 / (afq.mfma_peak("bf16x3") / 3.0), 4),
                          "el_error_ha_vs_gpu_fp64_all_walkers": err4}
         g4.close()
 

@@ -302,6 +302,21 @@ AFQMC_API int afqmc_energy_enqueue(afqmc_sys s, const afqmc_walkers* w, double* 
 AFQMC_API int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walkers,
                                     size_t* system_bytes, size_t* walker_bytes);
 
+/* Attainable dense MFMA rate (a diagnostic beside the datasheet peaks): launches, on
+ * hip_stream, workgroups whose wavefronts (as many as fit at once) each run MFMA instructions
+ * of one kind into four accumulators on register operands only, once untimed and three times
+ * timed with HIP events, and returns the fastest timed launch's rate in *tflops (dense
+ * TFLOP/s; synchronizes the stream).
+ *   AFQMC_FP32    v_mfma_f32_32x32x2_f32    (datasheet 157.3)
+ *   AFQMC_FP64    v_mfma_f64_16x16x4_f64    (datasheet 78.6)
+ *   AFQMC_BF16X3  v_mfma_f32_32x32x16_bf16  (datasheet 2500; a BF16x3 product takes three)
+ * out_dev: caller-owned device memory of at least AFQMC_MFMA_PEAK_BYTES bytes, overwritten
+ * (one double per workgroup keeps the chains live).  AFQMC_E_ARG for a missing or short
+ * buffer, AFQMC_E_UNSUPPORTED for another precision, AFQMC_E_HIP on a launch failure. */
+#define AFQMC_MFMA_PEAK_BYTES 16384
+AFQMC_API int afqmc_mfma_peak(int32_t precision, void* out_dev, size_t out_bytes,
+                              void* hip_stream, double* tflops);
+
 /* Read and clear the sticky status word (synchronizes the stream). */
 AFQMC_API int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear);
 

@@ -7,4 +7,4 @@ calls raise.
 """
 
 from ._lib import AfqmcError, EXPORTS, KERNEL_GROUPS, LIB_PATH, PRECISIONS, load  # noqa: F401
-from .afqmc import Batch, System, Walkers, modified_cholesky  # noqa: F401
+from .afqmc import Batch, System, Walkers, mfma_peak, modified_cholesky  # noqa: F401

@@ -24,9 +24,11 @@ EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walk
            "afqmc_kernel_timing", "afqmc_kernel_time", "afqmc_destroy", "afqmc_error_string",
            "afqmc_mcd_workspace_bytes", "afqmc_modified_cholesky", "afqmc_setup_multidet",
            "afqmc_batch_create", "afqmc_batch_step", "afqmc_batch_destroy", "afqmc_autotune",
-           "afqmc_set_tile", "afqmc_get_tile", "afqmc_energy_enqueue", "afqmc_footprint_bytes"]
+           "afqmc_set_tile", "afqmc_get_tile", "afqmc_energy_enqueue", "afqmc_footprint_bytes",
+           "afqmc_mfma_peak"]
 
 TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5}
+MFMA_PEAK_BYTES = 16384   # AFQMC_MFMA_PEAK_BYTES
 
 
 class Params(C.Structure):
@@ -96,6 +98,8 @@ def load(path: str | None = None) -> C.CDLL:
                            C.c_int),
         "afqmc_set_tile": ([C.c_void_p, C.c_int32], C.c_int),
         "afqmc_energy_enqueue": ([C.c_void_p, P(WalkersC), C.c_void_p], C.c_int),
+        "afqmc_mfma_peak": ([C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_double)],
+                            C.c_int),
         "afqmc_footprint_bytes": ([P(Params), C.c_int32, C.c_int32, P(C.c_size_t),
                                    P(C.c_size_t)], C.c_int),
         "afqmc_get_tile": ([C.c_void_p, P(C.c_int32)], C.c_int),

@@ -330,3 +330,16 @@ def modified_cholesky(eri, delta: float, max_vectors: int | None = None, stream=
                                         C.c_void_p(_stream_handle(stream))),
             "afqmc_modified_cholesky")
     return out[: n.value], bool(conv.value)
+
+
+def mfma_peak(precision: str = "fp32", stream=None) -> float:
+    """Attainable dense MFMA rate in TFLOP/s (``afqmc_mfma_peak``): fp32 -> 32x32x2 FP32,
+    fp64 -> 16x16x4 FP64, bf16x3 -> 32x32x16 BF16 (one product; a BF16x3 product takes three)."""
+    torch = _torch()
+    lib = L.load()
+    buf = torch.empty(L.MFMA_PEAK_BYTES // 8, dtype=torch.float64, device="cuda")
+    out = C.c_double()
+    L.check(lib.afqmc_mfma_peak(L.PRECISIONS[precision], C.c_void_p(int(buf.data_ptr())),
+                                L.MFMA_PEAK_BYTES, C.c_void_p(_stream_handle(stream)),
+                                C.byref(out)), "afqmc_mfma_peak")
+    return out.value

@@ -20,6 +20,9 @@
 #include "kernels_mfma.hpp"
 #include "kernels_prop.hpp"
 #include "kernels_mcd.hpp"
+#include "kernels_peak.hpp"
+
+static_assert(PEAK_MAX_BLOCKS * sizeof(double) <= AFQMC_MFMA_PEAK_BYTES, "peak scratch size");
 
 namespace {
 
@@ -1380,6 +1383,53 @@ int afqmc_modified_cholesky(const double* eri, int32_t M, double delta, int32_t 
   if (!h.done) return AFQMC_E_STATE;
   *n_vectors = h.count;
   if (converged) *converged = h.count < max_vectors || h.dmax < delta ? 1 : 0;
+  return AFQMC_OK;
+}
+
+int afqmc_mfma_peak(int32_t precision, void* out_dev, size_t out_bytes, void* hip_stream,
+                    double* tflops) {
+  if (!out_dev || !tflops || out_bytes < (size_t)AFQMC_MFMA_PEAK_BYTES) return AFQMC_E_ARG;
+  if (precision < AFQMC_FP64 || precision > AFQMC_BF16X3) return AFQMC_E_UNSUPPORTED;
+  const int kind = precision == AFQMC_FP32 ? 0 : precision == AFQMC_FP64 ? 1 : 2;
+  const int per_iter = kind == 0 ? peak_mfmas_per_iter<0>() : kind == 1 ? peak_mfmas_per_iter<1>()
+                                                                         : peak_mfmas_per_iter<2>();
+  // as many waves as fit at once (FP64: 3 per SIMD, else 4), 49152 (BF16 98304) instructions
+  // each: about 4 ms per launch at the datasheet rates (157.3, 78.6 and 2500 TFLOP/s)
+  const int blocks = kind == 1 ? 3 * PEAK_MAX_BLOCKS / 4 : PEAK_MAX_BLOCKS;
+  const int iters = (kind == 2 ? 98304 : 49152) / per_iter;
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* out = (double*)out_dev;
+  auto launch = [&]() {
+    if (kind == 0)
+      hipLaunchKernelGGL(k_mfma_peak<0>, dim3(blocks), dim3(256), 0, st, iters, out);
+    else if (kind == 1)
+      hipLaunchKernelGGL(k_mfma_peak<1>, dim3(blocks), dim3(256), 0, st, iters, out);
+    else
+      hipLaunchKernelGGL(k_mfma_peak<2>, dim3(blocks), dim3(256), 0, st, iters, out);
+    return hipGetLastError();
+  };
+  constexpr int TIMED = 3;  // the fastest of three timed launches after an untimed one
+  hipEvent_t ev[TIMED + 1] = {};
+  int rc = AFQMC_OK;
+  for (int i = 0; i <= TIMED && rc == AFQMC_OK; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) rc = AFQMC_E_HIP;
+  if (rc == AFQMC_OK && launch() != hipSuccess) rc = AFQMC_E_HIP;
+  for (int i = 0; i <= TIMED && rc == AFQMC_OK; ++i) {
+    if (hipEventRecord(ev[i], st) != hipSuccess) rc = AFQMC_E_HIP;
+    if (rc == AFQMC_OK && i < TIMED && launch() != hipSuccess) rc = AFQMC_E_HIP;
+  }
+  float best = 0.f;
+  if (rc == AFQMC_OK && hipEventSynchronize(ev[TIMED]) != hipSuccess) rc = AFQMC_E_HIP;
+  for (int i = 0; i < TIMED && rc == AFQMC_OK; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) rc = AFQMC_E_HIP;
+    else if (best == 0.f || ms < best) best = ms;
+  }
+  for (int i = 0; i <= TIMED; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  if (rc) return rc;
+  const double flops = (double)blocks * 4 * per_iter * (double)iters * peak_flops_per_mfma(kind);
+  *tflops = best > 0.f ? flops / ((double)best * 1e-3) / 1e12 : 0.0;
   return AFQMC_OK;
 }
 

@@ -117,3 +117,24 @@ int main(void) {
             if k.startswith(key + "."):
                 field = k.split(".", 1)[1]
                 assert getattr(struct, field).offset == int(v), k
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    tiles = {m.group(1).lower(): int(m.group(2))
+             for m in re.finditer(r"#define AFQMC_TILE_(\w+) (\d+)", text)}
+    assert tiles == L.TILES
+    assert int(re.search(r"#define AFQMC_MFMA_PEAK_BYTES (\d+)", text).group(1)) == \
+        L.MFMA_PEAK_BYTES
+
+
+def test_mfma_peak_argument_checks_precede_device_work():
+    lib = pkg.load()
+    t = C.c_double()
+    assert lib.afqmc_mfma_peak(1, None, L.MFMA_PEAK_BYTES, None, C.byref(t)) == -1
+    assert lib.afqmc_mfma_peak(1, C.c_void_p(256), L.MFMA_PEAK_BYTES - 8, None, C.byref(t)) == -1
+    assert lib.afqmc_mfma_peak(1, C.c_void_p(256), L.MFMA_PEAK_BYTES, None, None) == -1
+    # an unknown precision is refused before anything touches the (fake) device pointer
+    unsupported = int(re.search(r"AFQMC_E_UNSUPPORTED = (-\d+)", open(HEADER).read()).group(1))
+    assert lib.afqmc_mfma_peak(7, C.c_void_p(256), L.MFMA_PEAK_BYTES, None,
+                               C.byref(t)) == unsupported
