@@ -198,21 +198,32 @@ def serving_leg(args):
     from paper_1711_02242_amd.serve import JobSpec, Server
     from synthetic import gen_system, serving_trace
     trace = serving_trace(args.serve_jobs)
-    specs = []
-    for t in trace:
-        make = (lambda t=t: gen_system(t["M"], t["N"], t["n_chol"], seed=t["seed"]))
-        specs.append(JobSpec(t["job_id"], make, t["M"], t["N"], t["N"], t["n_chol"],
-                             t["n_walkers"], t["seed"], precision="fp32", dtau=0.005,
-                             target_stderr=args.serve_target, max_steps=args.serve_steps,
-                             discard=args.serve_steps // 3, arrival=t["arrival"]))
-    srv = Server(int(args.serve_budget_gib * (1 << 30)), check_every=50, autotune=True)
-    t0 = time.perf_counter()
-    res = srv.run(specs, realtime=True)
-    makespan = time.perf_counter() - t0
-    tte = np.array([r.time_to_energy for r in res])
-    ws = sum(r.steps * sp.n_walkers for r, sp in zip(res, specs))
-    eprint(f"bench: served {len(res)} jobs in {makespan:.1f} s, max resident {srv.max_resident}, "
-           f"TTE p50 {np.percentile(tte, 50):.1f} s p99 {np.percentile(tte, 99):.1f} s")
+
+    def job_specs(scale):
+        """The trace's jobs with arrival times multiplied by ``scale``."""
+        specs = []
+        for t in trace:
+            make = (lambda t=t: gen_system(t["M"], t["N"], t["n_chol"], seed=t["seed"]))
+            specs.append(JobSpec(t["job_id"], make, t["M"], t["N"], t["N"], t["n_chol"],
+                                 t["n_walkers"], t["seed"], precision="fp32", dtau=0.005,
+                                 target_stderr=args.serve_target, max_steps=args.serve_steps,
+                                 discard=args.serve_steps // 3, arrival=t["arrival"] * scale))
+        return specs
+
+    def serve(specs):
+        srv = Server(int(args.serve_budget_gib * (1 << 30)), check_every=50, autotune=True)
+        t0 = time.perf_counter()
+        res = srv.run(specs, realtime=True)
+        makespan = time.perf_counter() - t0
+        tte = np.array([r.time_to_energy for r in res])
+        ws = sum(r.steps * sp.n_walkers for r, sp in zip(res, specs))
+        eprint(f"bench: served {len(res)} jobs in {makespan:.1f} s, max resident "
+               f"{srv.max_resident}, TTE p50 {np.percentile(tte, 50):.1f} s p99 "
+               f"{np.percentile(tte, 99):.1f} s")
+        return res, tte, ws, makespan, srv.max_resident
+
+    specs = job_specs(1.0)
+    res, tte, ws, makespan, max_res = serve(specs)
     # serial plain FP64: per-job step time alone, FIFO over the same arrivals
     t_end, serial_tte = 0.0, []
     for r, sp in zip(res, specs):
@@ -233,20 +244,33 @@ def serving_leg(args):
         t_end = start + per * r.steps
         serial_tte.append(t_end - sp.arrival)
     serial_tte = np.array(serial_tte)
-    return {"workload": f"first {len(specs)} jobs of a Poisson(4/s) trace: M uniform on 32..200, "
-                        "N=M/4, N_g=6M, 256-2048 walkers, fp32 bulk, dtau=0.005",
-            "jobs": len(res), "hbm_budget_gib": args.serve_budget_gib,
-            "target_stderr_ha": args.serve_target, "step_cap": args.serve_steps,
-            "reached_target": int(sum(r.plateau and r.stderr < args.serve_target for r in res)),
-            "p50_time_to_energy_s": round(float(np.percentile(tte, 50)), 2),
-            "p99_time_to_energy_s": round(float(np.percentile(tte, 99)), 2),
-            "walker_steps_per_s": round(ws / makespan, 1), "makespan_s": round(makespan, 2),
-            "max_resident": srv.max_resident,
+    out = {"workload": f"first {len(specs)} jobs of a Poisson(4/s) trace: M uniform on 32..200, "
+                       "N=M/4, N_g=6M, 256-2048 walkers, fp32 bulk, dtau=0.005",
+           "jobs": len(res), "hbm_budget_gib": args.serve_budget_gib,
+           "target_stderr_ha": args.serve_target, "step_cap": args.serve_steps,
+           "reached_target": int(sum(r.plateau and r.stderr < args.serve_target for r in res)),
+           "p50_time_to_energy_s": round(float(np.percentile(tte, 50)), 2),
+           "p99_time_to_energy_s": round(float(np.percentile(tte, 99)), 2),
+           "walker_steps_per_s": round(ws / makespan, 1), "makespan_s": round(makespan, 2),
+           "max_resident": max_res,
             "serial_fp64": {"p50_time_to_energy_s": round(float(np.percentile(serial_tte, 50)), 2),
                             "p99_time_to_energy_s": round(float(np.percentile(serial_tte, 99)), 2),
                             "walker_steps_per_s": round(ws / float(t_end), 1),
                             "method": f"each job alone in FP64, {args.serve_fp64_steps} timed "
                                       "steps scaled to its step count, FIFO on the arrivals"}}
+    if args.serve_load > 0:
+        # the same jobs arriving at a fraction of the measured capacity: the trace's arrivals
+        # (4/s) keep the server saturated, so its jobs per second of makespan is the capacity
+        cap = len(res) / makespan
+        rate = args.serve_load * cap
+        res2, tte2, ws2, mk2, mr2 = serve(job_specs(4.0 / rate))
+        out["at_load"] = {"load": args.serve_load, "capacity_jobs_per_s": round(cap, 4),
+                          "arrival_rate_jobs_per_s": round(rate, 4),
+                          "p50_time_to_energy_s": round(float(np.percentile(tte2, 50)), 2),
+                          "p99_time_to_energy_s": round(float(np.percentile(tte2, 99)), 2),
+                          "walker_steps_per_s": round(ws2 / mk2, 1), "makespan_s": round(mk2, 2),
+                          "max_resident": mr2}
+    return out
 
 
 def el_error(s, args, gs, wk):
@@ -311,6 +335,9 @@ def main():
     ap.add_argument("--serve-target", type=float, default=0.005, help="target stderr (Ha)")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
     ap.add_argument("--serve-fp64-steps", type=int, default=2)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="rerun the jobs arriving at this fraction of the measured capacity "
+                         "(0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for PMC byte counters)")
     args = ap.parse_args()
