@@ -131,7 +131,14 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
   for (int g = 0; g < G; ++g) {
     unsigned char* Acur = (g & 1) ? Abuf1 : Abuf0;
     unsigned char* Anext = (g & 1) ? Abuf0 : Abuf1;
-    if (g + 1 < G) AFQMC_GLOAD(g + 1);
+    // FP32: the next tile's loads are unconditional (the last g re-reads its own tile), so
+    // the waits placed before the MFMAs do not stall on them (3 % faster); BF16x3 keeps the
+    // conditional form, which measures 3 % faster there
+    if constexpr (BF16) {
+      if (g + 1 < G) AFQMC_GLOAD(g + 1);
+    } else {
+      AFQMC_GLOAD(g + 1 < G ? g + 1 : g);
+    }
     const unsigned char* arow = Acur + ((size_t)col * lda + kofs) * ESZ;
     if constexpr (NP == 32) {
       f32x16 cre = {}, cim = {};
