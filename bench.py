@@ -38,22 +38,36 @@ def contraction_flops(M, nup, ndn, G, n_walkers):
     return 4.0 * G * M * (nup * nup + ndn * ndn) * n_walkers
 
 
-def recorded_traffic(precision):
-    """HBM bytes per launch of the contraction from the committed PMC summary, or None when
-    there is none for this precision or the kernel source changed since it was taken."""
+def recorded_figure(precision, name, key, cast=float):
+    """A figure of the FP32 contraction from a committed counter summary under profiles/, or
+    None when there is none for this precision or the kernel source changed since it was
+    taken (the summary records the source's sha256)."""
     import hashlib
     if precision != "fp32":
         return None
-    path = os.path.join(ROOT, "profiles", "contract_fp32_M128_N32_G800_W1024_traffic.md")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
-                      if line.startswith(("traffic_bytes_per_launch", "kernel_source", "source_sha256")))
+                      if line.startswith((key, "kernel_source", "source_sha256")))
         src = open(os.path.join(ROOT, fields["kernel_source"].strip()), "rb").read()
         if hashlib.sha256(src).hexdigest() != fields["source_sha256"].strip():
             return None
-        return int(fields["traffic_bytes_per_launch"])
+        return cast(fields[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def recorded_traffic(precision):
+    """HBM bytes per launch of the contraction (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return recorded_figure(precision, "contract_fp32_M128_N32_G800_W1024_traffic.md",
+                           "traffic_bytes_per_launch", int)
+
+
+def recorded_mfma_busy(precision):
+    """Fraction of the contraction's active cycles the matrix cores are busy
+    (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE and the SIMDs)."""
+    return recorded_figure(precision, "mfma_util_M128_N32_G800_W1024.md",
+                           "mfma_busy_fp32_contraction", float)
 
 
 def run_gpu(s, args, precision, steps, warmup, timed_kernels=True, closed_shell=False):
@@ -381,6 +395,7 @@ def main():
                 "kernel": "local-energy contraction", "avg_launch_ms": round(ms_c / max(n_c, 1), 4),
                 "flops_per_launch": flops, "attainable": round(att, 2),
                 "frac_attainable": round(achieved / att, 4),
+                "mfma_busy_rocprof": recorded_mfma_busy(args.precision),
                 "attainable_method": "afqmc_mfma_peak: register-only MFMA chains on every SIMD"}
     kernels_ms = {k: round(v[0] / max(args.steps, 1), 4) for k, v in kt.items()}
     eprint(f"bench: {ms_step:.3f} ms/step, {value:.1f} walker-steps/s; per-step kernel ms {kernels_ms}")
