@@ -70,7 +70,8 @@ def recorded_mfma_busy(precision):
                            "mfma_busy_fp32_contraction", float)
 
 
-def run_gpu(s, args, precision, steps, warmup, timed_kernels=True, closed_shell=False):
+def run_gpu(s, args, precision, steps, warmup, timed_kernels=True, closed_shell=False,
+            per_step=None):
     import torch
 
     import paper_1711_02242_amd as afq
@@ -83,12 +84,21 @@ def run_gpu(s, args, precision, steps, warmup, timed_kernels=True, closed_shell=
     torch.cuda.synchronize()
     if timed_kernels:
         gs.kernel_timing(True)
+    # per-step HIP events on the stream the steps run on (the current torch stream)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] \
+        if per_step is not None else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    if evs:
+        evs[0].record()
+    for i in range(steps):
         gs.step(wk, seed=args.seed)
+        if evs:
+            evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if evs:
+        per_step.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
     kt = {}
     if timed_kernels:
         import paper_1711_02242_amd._lib as L
@@ -120,10 +130,25 @@ def cpu_baseline(s, args):
         x = gaussian_fields(args.seed, 0, wk.walker_id, k, s.n_chol)
         A.step(S, P, wk, x, comb_uniform(args.seed, 0, k))
     dt = time.perf_counter() - t0
-    return {"value": nw * nsteps / dt, "unit": "walker-steps/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"{nw} walkers x {nsteps} steps of the same workload (NumPy FP64, "
-                      f"{dt:.1f} s)"}
+    out = {"value": nw * nsteps / dt, "unit": "walker-steps/s", "cores": int(cores),
+           "kind": "oracle", "cpu_count": os.cpu_count(),
+           "sample": f"{nw} walkers x {nsteps} steps of the same workload (NumPy FP64, "
+                     f"{dt:.1f} s)"}
+    # the same oracle on one thread, on a smaller sample
+    try:
+        from threadpoolctl import threadpool_limits
+        nw1 = max(1, min(4, nw))
+        w1 = A.init_walkers(S, nw1)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            x = gaussian_fields(args.seed, 0, w1.walker_id, 0, s.n_chol)
+            A.step(S, P, w1, x, comb_uniform(args.seed, 0, 0))
+            d1 = time.perf_counter() - t0
+        out["one_thread"] = {"value": nw1 / d1, "unit": "walker-steps/s",
+                             "sample": f"{nw1} walkers x 1 step ({d1:.1f} s)"}
+    except ImportError:
+        pass
+    return out
 
 
 def batch_leg(args):
@@ -363,6 +388,7 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from synthetic import config_system
     torch.cuda.set_device(0)
@@ -377,7 +403,9 @@ def main():
     eprint(f"bench: M={s.M} N={s.n_up}+{s.n_dn} G={s.n_chol} walkers={args.walkers} "
            f"precision={args.precision} steps={args.steps} warmup={args.warmup}")
 
-    gs, wk, dt, kt, e = run_gpu(s, args, args.precision, args.steps, args.warmup)
+    step_ms = []
+    gs, wk, dt, kt, e = run_gpu(s, args, args.precision, args.steps, args.warmup,
+                                per_step=step_ms)
     ms_step = 1e3 * dt / args.steps
     value = args.walkers * args.steps / dt
     ms_c, n_c = kt["contract"]
@@ -411,6 +439,10 @@ def main():
                       "M": s.M, "n_up": s.n_up, "n_dn": s.n_dn, "n_chol": s.n_chol,
                       "n_walkers": args.walkers, "precision": args.precision},
            "roofline": roofline, "kernel_ms_per_step": kernels_ms,
+           "step_ms": {"median": round(float(np.median(step_ms)), 4),
+                       "p90": round(float(np.percentile(step_ms, 90)), 4),
+                       "min": round(min(step_ms), 4), "max": round(max(step_ms), 4),
+                       "note": "HIP events per step; every 5th step adds the QR and the comb"},
            "e_mix": e[0] / e[2]}
 
     if args.precision != "fp64" and not args.no_compare:
