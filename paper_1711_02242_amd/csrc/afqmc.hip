@@ -2,6 +2,7 @@
 // layout, and the launch sequence of one walker step (arXiv:1711.02242, Sec. III.E).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -25,6 +26,22 @@
 static_assert(PEAK_MAX_BLOCKS * sizeof(double) <= AFQMC_MFMA_PEAK_BYTES, "peak scratch size");
 
 namespace {
+// Order of the packed pairs (q, p), p <= q, of the symmetric A-build: 16 x 16 blocks of the
+// lower triangle, block row by block row, each block row by row.  A workgroup's tile of
+// consecutive packed columns then covers a few whole rows of a block, so the mirrored stores
+// A[p][q] of a tile fill the same short row segments as its direct stores A[q][p] and reach
+// memory as whole segments (a plain row-by-row order spreads them over a column of A).
+inline std::vector<std::pair<int, int>> pair_order(int M) {
+  constexpr int B = 16;
+  std::vector<std::pair<int, int>> o;
+  o.reserve((size_t)M * (M + 1) / 2);
+  for (int qb = 0; qb < M; qb += B)
+    for (int pb = 0; pb <= qb; pb += B)
+      for (int q = qb; q < std::min(qb + B, M); ++q)
+        for (int pp = pb; pp < std::min(pb + B, M) && pp <= q; ++pp) o.emplace_back(q, pp);
+  return o;
+}
+
 
 enum { KG_CONTRACT = 0, KG_OVERLAP, KG_FIELDS, KG_ABUILD, KG_PROP, KG_QR, KG_WEIGHT, KG_COMB,
        KG_ASSEMBLE, KG_COUNT };
@@ -705,13 +722,13 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
   if (p->precision == AFQMC_FP64 || (p->precision != AFQMC_FP64 && M <= WIDE_KMAX &&
                                      std::max(nup_i, ndn_i) <= 64)) {
     const size_t MMh = (size_t)M * (M + 1) / 2;
+    const std::vector<std::pair<int, int>> order = pair_order(M);
     std::vector<int> pairs(2 * MMh);
-    size_t k = 0;
-    for (int q = 0; q < M; ++q)
-      for (int pp = 0; pp <= q; ++pp, ++k) {
-        pairs[2 * k] = q * M + pp;
-        pairs[2 * k + 1] = pp * M + q;
-      }
+    for (size_t k = 0; k < MMh; ++k) {
+      const int q = order[k].first, pp = order[k].second;
+      pairs[2 * k] = q * M + pp;
+      pairs[2 * k + 1] = pp * M + q;
+    }
     if ((rc = dev_upload(S, &S->abpairs, pairs.data(), pairs.size()))) {
       free_sys(S);
       return rc;
@@ -719,11 +736,10 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     if (p->precision == AFQMC_FP64) {
       S->Gp64 = ((G + 15) / 16) * 16;
       std::vector<double> lt(MMh * (S->Gp64 > 0 ? S->Gp64 : 1), 0.0);
-      k = 0;
-      for (int q = 0; q < M; ++q)
-        for (int pp = 0; pp <= q; ++pp, ++k)
-          for (int g = 0; g < G; ++g)
-            lt[k * S->Gp64 + g] = L_chol[(size_t)g * M * M + (size_t)q * M + pp];
+      for (size_t k = 0; k < MMh; ++k)
+        for (int g = 0; g < G; ++g)
+          lt[k * S->Gp64 + g] =
+              L_chol[(size_t)g * M * M + (size_t)order[k].first * M + order[k].second];
       if ((rc = dev_upload(S, &S->Lt64, lt.data(), lt.size()))) {
         free_sys(S);
         return rc;
@@ -761,11 +777,11 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     const size_t MMh = (size_t)M * (M + 1) / 2;
     std::vector<float> lt(MMh * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
     {
-      size_t k = 0;
-      for (int q = 0; q < M; ++q)
-        for (int pp = 0; pp <= q; ++pp, ++k)
-          for (int g = 0; g < G; ++g)
-            lt[k * S->Gp + g] = (float)L_chol[(size_t)g * M * M + (size_t)q * M + pp];
+      const std::vector<std::pair<int, int>> order = pair_order(M);
+      for (size_t k = 0; k < MMh; ++k)
+        for (int g = 0; g < G; ++g)
+          lt[k * S->Gp + g] =
+              (float)L_chol[(size_t)g * M * M + (size_t)order[k].first * M + order[k].second];
     }
     for (size_t e = 0; e < eh.size(); ++e) eh[e] = (float)Eh[e];
     if ((rc = dev_upload(S, &S->Lt32, lt.data(), lt.size())) ||
