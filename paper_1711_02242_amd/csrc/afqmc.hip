@@ -26,13 +26,13 @@
 static_assert(PEAK_MAX_BLOCKS * sizeof(double) <= AFQMC_MFMA_PEAK_BYTES, "peak scratch size");
 
 namespace {
-// Order of the packed pairs (q, p), p <= q, of the symmetric A-build: 16 x 16 blocks of the
+// Order of the packed pairs (q, p), p <= q, of the symmetric A-build: 8 x 8 blocks of the
 // lower triangle, block row by block row, each block row by row.  A workgroup's tile of
 // consecutive packed columns then covers a few whole rows of a block, so the mirrored stores
 // A[p][q] of a tile fill the same short row segments as its direct stores A[q][p] and reach
 // memory as whole segments (a plain row-by-row order spreads them over a column of A).
 inline std::vector<std::pair<int, int>> pair_order(int M) {
-  constexpr int B = 16;
+  constexpr int B = 8;
   std::vector<std::pair<int, int>> o;
   o.reserve((size_t)M * (M + 1) / 2);
   for (int qb = 0; qb < M; qb += B)
