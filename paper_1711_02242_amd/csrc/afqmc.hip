@@ -905,11 +905,28 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
     } else {
       Timer tm(s, KG_PROP);
       const int Kp = ((M + 15) / 16) * 16;
-      const size_t shm = (size_t)2 * 16 * PR_RB * (Kp + 4) * 4;
-      (void)hipFuncSetAttribute((const void*)k_propagate_f32,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL(k_propagate_f32, dim3(nw), dim3(64 * (Kp / 16)), shm, s->stream, M, nt, Kp,
-                         s->G > 0 ? s->p.n_taylor : 0, s->Eh32, Are, Aim, (cd*)w->U, w->weight);
+      const int nrb = (nt + 15) / 16;
+      if (Kp > 128 || nrb > PR_RB) return AFQMC_E_UNSUPPORTED;
+      const size_t shm = (size_t)2 * 16 * nrb * (Kp + 4) * 4;
+      const int nt_ = s->G > 0 ? s->p.n_taylor : 0;
+      // one instantiation per (K chunks of 16, row blocks of 16)
+#define PROP_KR(NKCV, NRBV)                                                                    \
+  case NRBV:                                                                                   \
+    (void)hipFuncSetAttribute((const void*)k_propagate_f32<NKCV, NRBV>,                        \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
+    hipLaunchKernelGGL((k_propagate_f32<NKCV, NRBV>), dim3(nw), dim3(64 * NKCV), shm,          \
+                       s->stream, M, nt, Kp, nt_, s->Eh32, Are, Aim, (cd*)w->U, w->weight);    \
+    break;
+#define PROP_K(NKCV)                                                                           \
+  case NKCV:                                                                                   \
+    switch (nrb) { PROP_KR(NKCV, 1) PROP_KR(NKCV, 2) PROP_KR(NKCV, 3) PROP_KR(NKCV, 4) }       \
+    break;
+      if (nrb > 0) switch (Kp / 16) {
+        PROP_K(1) PROP_K(2) PROP_K(3) PROP_K(4) PROP_K(5) PROP_K(6) PROP_K(7) PROP_K(8)
+        default: return AFQMC_E_UNSUPPORTED;
+      }
+#undef PROP_K
+#undef PROP_KR
       HIPCHK(hipGetLastError());
     }
   } else {

@@ -13,8 +13,9 @@
 // through double-buffered LDS.  Per g the wave runs the MFMA chain over K = M for the
 // Re and Im halves, then an LDS transpose through the wave's own planes gives every
 // lane the partner element Omega_ji of each Omega_ij it holds (a wavefront fence, not a
-// workgroup barrier, orders it; one barrier per g guards the shared tile buffers).  Per-g partial products are summed in
-// FP32 and accumulated across g in FP64.
+// workgroup barrier, orders it; one barrier per g guards the shared tile buffers).
+// Per-g partial products are summed in FP32 and accumulated across g in FP64; tr Omega
+// is summed over the lanes by DPP row shifts (no LDS round trips).
 #pragma once
 
 // Orders a wave's LDS stores before its later LDS loads of other lanes' elements (the
@@ -25,12 +26,81 @@ __device__ inline void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sum of v over each 16-lane row, left in the row's last lane (lanes 15, 31, 47, 63): four
+// DPP shifts within the row, out-of-row sources read as zero.
+__device__ __forceinline__ float dpp_row_sum(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xF, 0xF, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xF, 0xF, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xF, 0xF, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xF, 0xF, true));
+  return v;
+}
+// After dpp_row_sum: adds the last lane of rows 0 and 2 into rows 1 and 3 (DPP row_bcast:15),
+// so lane 31 holds the sum over lanes 0..31 and lane 63 the sum over lanes 32..63.
+__device__ __forceinline__ float dpp_half_sum(float v) {
+  v = dpp_row_sum(v);
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+  return v;
+}
+
+// One K chunk of Omega = Lh Theta for the Re and Im halves.  FP32: a holds four K values of
+// one row of Lh (one per MFMA step), br / bi four K values of one column of Re / Im Theta.
+// BF16x3: a / al the hi / lo bf16 of eight K values, br / brl and bi / bil likewise; the
+// three products hi.hi + hi.lo + lo.hi.
+template <int NP, bool BF16, typename Acc>
+__device__ __forceinline__ void contract_chunk(u32x4 ah, u32x4 al, u32x4 brh, u32x4 brl,
+                                               u32x4 bih, u32x4 bil, Acc& cre, Acc& cim) {
+  if constexpr (!BF16) {
+    const f32x4 a = __builtin_bit_cast(f32x4, ah);
+    const f32x4 br = __builtin_bit_cast(f32x4, brh);
+    const f32x4 bi = __builtin_bit_cast(f32x4, bih);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if constexpr (NP == 32) {
+        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a[k], br[k], cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a[k], bi[k], cim, 0, 0, 0);
+      } else {
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], br[k], cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bi[k], cim, 0, 0, 0);
+      }
+    }
+  } else {
+    const bf16x8 h = __builtin_bit_cast(bf16x8, ah), l = __builtin_bit_cast(bf16x8, al);
+    const bf16x8 rh = __builtin_bit_cast(bf16x8, brh), rl = __builtin_bit_cast(bf16x8, brl);
+    const bf16x8 ih = __builtin_bit_cast(bf16x8, bih), il = __builtin_bit_cast(bf16x8, bil);
+    if constexpr (NP == 32) {
+      cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, rh, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, ih, cim, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, rl, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, il, cim, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, rh, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h, ih, cim, 0, 0, 0);
+    } else {
+      cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, rh, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, ih, cim, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, rl, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, il, cim, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, rh, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, ih, cim, 0, 0, 0);
+    }
+  }
+}
+
+// K values per register chunk of the contraction kernel: FP32 4 MFMA steps (2 or 4 K each),
+// BF16x3 one step (16 or 32 K).
+template <int NP, bool BF16>
+constexpr int contract_kch() {
+  return BF16 ? (NP == 32 ? 16 : 32) : (NP == 32 ? 8 : 16);
+}
+
 // ---------------------------------------------------------------------------
-// The contraction kernel.  Grid: (ceil(nw / WPB), 2 n_det); 64 WPB threads.
+// The contraction kernel.  Grid: (ceil(nw / WPB), 2 n_det); 64 WPB threads.  NK = K_P / KCH
+// register chunks of K (compile time: no per-chunk branches, and the A fragment of chunk
+// c + 1 is read from LDS while the MFMAs of chunk c run).
 // ---------------------------------------------------------------------------
-template <int NP, bool BF16, int WPB>
+template <int NP, bool BF16, int WPB, int NK>
 __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
-    int nw, int G, int nup, int ndn, int KP, const void* __restrict__ Lp_,
+    int nw, int G, int nup, int ndn, int KP_arg, const void* __restrict__ Lp_,
     const void* __restrict__ thp_, const double* __restrict__ weight, cd* __restrict__ tpart,
     cd* __restrict__ exch) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -53,9 +123,12 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
   // element sizes: fp32 tiles are floats; bf16 tiles are 2-byte values, hi and lo planes.
   constexpr int ESZ = BF16 ? 2 : 4;
   constexpr int PLANES = BF16 ? 2 : 1;
-  const int lda = KP + (BF16 ? 8 : 4);                 // LDS row stride in elements (16 B pad)
-  const size_t tile_elems = (size_t)NP * KP * PLANES;  // one g in global memory
-  const int tile_lds_bytes = NP * lda * ESZ * PLANES;
+  constexpr int KCH = contract_kch<NP, BF16>();
+  constexpr int KP = NK * KCH;                          // K_P (the launcher passes it as KP_arg)
+  (void)KP_arg;
+  constexpr int lda = KP + (BF16 ? 8 : 4);              // LDS row stride in elements (16 B pad)
+  constexpr size_t tile_elems = (size_t)NP * KP * PLANES;  // one g in global memory
+  constexpr int tile_lds_bytes = NP * lda * ESZ * PLANES;
   unsigned char* Abuf0 = smem;
   unsigned char* Abuf1 = smem + tile_lds_bytes;
   constexpr int LDE = NP + 4;
@@ -67,9 +140,9 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
       reinterpret_cast<const unsigned char*>(Lp_) + ((size_t)dd * 2 + s) * G * tile_elems * ESZ;
 
   // ---- copy of one g-tile global -> LDS, 16 bytes per thread per chunk
-  const int chunks_per_row = KP * ESZ / 16;
-  const int nchunks = NP * PLANES * chunks_per_row;
-  constexpr int MAXCH = (32 * MFMA_KMAX * 4 / 16 + NT - 1) / NT;  // 4 (WPB 4), 8 (WPB 2)
+  constexpr int chunks_per_row = KP * ESZ / 16;
+  constexpr int nchunks = NP * PLANES * chunks_per_row;
+  constexpr int MAXCH = (nchunks + NT - 1) / NT;   // 16-byte chunks per thread
   u32x4 pre[MAXCH];
 #define AFQMC_GLOAD(G_)                                                                        \
   do {                                                                                         \
@@ -83,7 +156,7 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
   do {                                                                                         \
     _Pragma("unroll") for (int c_ = 0; c_ < MAXCH; ++c_) {                                     \
       const int ch_ = tid + c_ * NT;                                                           \
-      if (ch_ < nchunks) {                                                                     \
+      if ((c_ + 1) * NT <= nchunks || ch_ < nchunks) {                                         \
         const int row_ = ch_ / chunks_per_row;                                                 \
         const int col_ = (ch_ % chunks_per_row) * (16 / ESZ);                                  \
         *reinterpret_cast<u32x4*>((DST_) + ((size_t)row_ * lda + col_) * ESZ) = pre[c_];       \
@@ -92,181 +165,140 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
   } while (0)
 
   // ---- Theta operand into registers
-  const int KCH = BF16 ? (NP == 32 ? 16 : 32) : (NP == 32 ? 8 : 16);  // K per register chunk
-  const int nk = KP / KCH;
-  constexpr int MAXK = BF16 ? (NP == 32 ? 8 : 4) : (NP == 32 ? 16 : 8);
   constexpr int LGRP = NP == 32 ? 32 : 16;  // lanes per K group
   const int col = lane % LGRP;              // row i of A / column j of B
   const int kg = lane / LGRP;               // K group of the lane
   const int kofs = BF16 ? 8 * kg : 4 * kg;  // element offset of the lane inside a K chunk
 
-  u32x4 bre[MAXK], bim[MAXK];   // fp32: 4 floats;  bf16: 8 bf16 (hi)
-  u32x4 bre_lo[BF16 ? MAXK : 1], bim_lo[BF16 ? MAXK : 1];
+  u32x4 bre[NK], bim[NK];   // fp32: 4 floats;  bf16: 8 bf16 (hi)
+  u32x4 bre_lo[BF16 ? NK : 1], bim_lo[BF16 ? NK : 1];
   if (active) {
     const size_t per = (size_t)NP * KP;
     const unsigned char* tb = reinterpret_cast<const unsigned char*>(thp_) +
                               ((size_t)wd * 2 + s) * 2 * PLANES * per * ESZ;
 #pragma unroll
-    for (int c = 0; c < MAXK; ++c) {
-      if (c < nk) {
-        const size_t off = ((size_t)col * KP + c * KCH + kofs) * ESZ;
-        bre[c] = *reinterpret_cast<const u32x4*>(tb + off);
-        if (BF16) {
-          bre_lo[BF16 ? c : 0] = *reinterpret_cast<const u32x4*>(tb + per * ESZ + off);
-          bim[c] = *reinterpret_cast<const u32x4*>(tb + 2 * per * ESZ + off);
-          bim_lo[BF16 ? c : 0] = *reinterpret_cast<const u32x4*>(tb + 3 * per * ESZ + off);
-        } else {
-          bim[c] = *reinterpret_cast<const u32x4*>(tb + per * ESZ + off);
-        }
+    for (int c = 0; c < NK; ++c) {
+      const size_t off = ((size_t)col * KP + c * KCH + kofs) * ESZ;
+      bre[c] = *reinterpret_cast<const u32x4*>(tb + off);
+      if constexpr (BF16) {
+        bre_lo[c] = *reinterpret_cast<const u32x4*>(tb + per * ESZ + off);
+        bim[c] = *reinterpret_cast<const u32x4*>(tb + 2 * per * ESZ + off);
+        bim_lo[c] = *reinterpret_cast<const u32x4*>(tb + 3 * per * ESZ + off);
+      } else {
+        bim[c] = *reinterpret_cast<const u32x4*>(tb + per * ESZ + off);
       }
     }
   }
 
+  using Acc = typename std::conditional<NP == 32, f32x16, f32x4>::type;
+  constexpr int NV = NP == 32 ? 16 : 4;   // accumulator elements per lane
   double xr = 0.0, xi = 0.0;
   if (G > 0) {
     AFQMC_GLOAD(0);
     AFQMC_LSTORE(Abuf0);
   }
+  // every global load so far (Theta, the first tile) complete here: otherwise the waits for
+  // the Theta registers land inside the g loop, where they also wait for the next tile
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
   __syncthreads();
   for (int g = 0; g < G; ++g) {
     unsigned char* Acur = (g & 1) ? Abuf1 : Abuf0;
     unsigned char* Anext = (g & 1) ? Abuf0 : Abuf1;
     // FP32: the next tile's loads are unconditional (the last g re-reads its own tile), so
-    // the waits placed before the MFMAs do not stall on them (3 % faster); BF16x3 keeps the
-    // conditional form, which measures 3 % faster there
+    // the waits placed before the MFMAs do not stall on them; BF16x3 keeps the conditional
+    // form, which measures faster there
     if constexpr (BF16) {
       if (g + 1 < G) AFQMC_GLOAD(g + 1);
     } else {
       AFQMC_GLOAD(g + 1 < G ? g + 1 : g);
     }
     const unsigned char* arow = Acur + ((size_t)col * lda + kofs) * ESZ;
-    if constexpr (NP == 32) {
-      f32x16 cre = {}, cim = {};
-      if (active) {
+    const size_t lo_ofs = (size_t)NP * lda * ESZ;   // bf16: lo plane of the tile
+    Acc cre = {}, cim = {};
+    if (active) {
+      if constexpr (WPB == 4) {
+        // A fragment of chunk c + 1 read while chunk c's MFMAs run; the scheduling barrier
+        // keeps the compiler from regrouping the reads (it pairs chunks and waits at once)
+        u32x4 ah = *reinterpret_cast<const u32x4*>(arow);
+        u32x4 al = BF16 ? *reinterpret_cast<const u32x4*>(arow + lo_ofs) : ah;
 #pragma unroll
-        for (int c = 0; c < MAXK; ++c) {
-          if (c < nk) {
-            if constexpr (!BF16) {
-              const f32x4 a = *reinterpret_cast<const f32x4*>(arow + (size_t)c * KCH * ESZ);
-              const f32x4 br = __builtin_bit_cast(f32x4, bre[c]);
-              const f32x4 bi = __builtin_bit_cast(f32x4, bim[c]);
-              cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, br.x, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bi.x, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, br.y, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bi.y, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, br.z, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bi.z, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, br.w, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bi.w, cim, 0, 0, 0);
-            } else {
-              const bf16x8 ah = __builtin_bit_cast(
-                  bf16x8, *reinterpret_cast<const u32x4*>(arow + (size_t)c * KCH * ESZ));
-              const bf16x8 al = __builtin_bit_cast(
-                  bf16x8, *reinterpret_cast<const u32x4*>(arow + ((size_t)NP * lda + c * KCH) * ESZ));
-              const bf16x8 brh = __builtin_bit_cast(bf16x8, bre[c]);
-              const bf16x8 brl = __builtin_bit_cast(bf16x8, bre_lo[BF16 ? c : 0]);
-              const bf16x8 bih = __builtin_bit_cast(bf16x8, bim[c]);
-              const bf16x8 bil = __builtin_bit_cast(bf16x8, bim_lo[BF16 ? c : 0]);
-              cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, brh, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bih, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brl, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bil, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brh, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bih, cim, 0, 0, 0);
-            }
+        for (int c = 0; c < NK; ++c) {
+          u32x4 nh = ah, nl = al;
+          if (c + 1 < NK) {
+            nh = *reinterpret_cast<const u32x4*>(arow + (size_t)(c + 1) * KCH * ESZ);
+            if constexpr (BF16)
+              nl = *reinterpret_cast<const u32x4*>(arow + lo_ofs + (size_t)(c + 1) * KCH * ESZ);
           }
+          contract_chunk<NP, BF16>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
+                                   bim_lo[BF16 ? c : 0], cre, cim);
+          __builtin_amdgcn_sched_barrier(0);
+          ah = nh;
+          al = nl;
         }
-        // column-major store of Omega: lane holds column j = col, rows 8*(v/4) + 4*kg + v%4
+      } else {
+        // two walkers per workgroup hold twice the tile-copy registers: no room for a
+        // second A fragment
 #pragma unroll
-        for (int v4 = 0; v4 < 4; ++v4) {
-          const int r0 = 8 * v4 + 4 * kg;
-          *reinterpret_cast<float4*>(ep_re + col * LDE + r0) =
-              make_float4(cre[4 * v4], cre[4 * v4 + 1], cre[4 * v4 + 2], cre[4 * v4 + 3]);
-          *reinterpret_cast<float4*>(ep_im + col * LDE + r0) =
-              make_float4(cim[4 * v4], cim[4 * v4 + 1], cim[4 * v4 + 2], cim[4 * v4 + 3]);
+        for (int c = 0; c < NK; ++c) {
+          const u32x4 ah = *reinterpret_cast<const u32x4*>(arow + (size_t)c * KCH * ESZ);
+          const u32x4 al =
+              BF16 ? *reinterpret_cast<const u32x4*>(arow + lo_ofs + (size_t)c * KCH * ESZ) : ah;
+          contract_chunk<NP, BF16>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
+                                   bim_lo[BF16 ? c : 0], cre, cim);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
-      wave_lds_fence();   // each wave reads back only its own Omega planes
-      if (active) {
-        float pr = 0.f, pi = 0.f;
+      // column-major store of Omega: lane holds column j = col, rows
+      // 8*(v/4) + 4*kg + v%4 (32 x 32) or 4*kg + v (16 x 16)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int i = 8 * (v / 4) + 4 * kg + (v % 4);
-          const float R = cre[v], I = cim[v];
-          const float Rt = ep_re[i * LDE + col], It = ep_im[i * LDE + col];
-          pr += R * Rt - I * It;
-          pi += R * It + I * Rt;
-        }
-        xr += (double)pr;
-        xi += (double)pi;
-      }
-    } else {
-      f32x4 cre = {}, cim = {};
-      if (active) {
-#pragma unroll
-        for (int c = 0; c < MAXK; ++c) {
-          if (c < nk) {
-            if constexpr (!BF16) {
-              const f32x4 a = *reinterpret_cast<const f32x4*>(arow + (size_t)c * KCH * ESZ);
-              const f32x4 br = __builtin_bit_cast(f32x4, bre[c]);
-              const f32x4 bi = __builtin_bit_cast(f32x4, bim[c]);
-              cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, br.x, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bi.x, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, br.y, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bi.y, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, br.z, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bi.z, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, br.w, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bi.w, cim, 0, 0, 0);
-            } else {
-              const bf16x8 ah = __builtin_bit_cast(
-                  bf16x8, *reinterpret_cast<const u32x4*>(arow + (size_t)c * KCH * ESZ));
-              const bf16x8 al = __builtin_bit_cast(
-                  bf16x8, *reinterpret_cast<const u32x4*>(arow + ((size_t)NP * lda + c * KCH) * ESZ));
-              const bf16x8 brh = __builtin_bit_cast(bf16x8, bre[c]);
-              const bf16x8 brl = __builtin_bit_cast(bf16x8, bre_lo[BF16 ? c : 0]);
-              const bf16x8 bih = __builtin_bit_cast(bf16x8, bim[c]);
-              const bf16x8 bil = __builtin_bit_cast(bf16x8, bim_lo[BF16 ? c : 0]);
-              cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, brh, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bih, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brl, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bil, cim, 0, 0, 0);
-              cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brh, cre, 0, 0, 0);
-              cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bih, cim, 0, 0, 0);
-            }
-          }
-        }
-        // lane holds column j = col, rows 4*kg + v
-        *reinterpret_cast<float4*>(ep_re + col * LDE + 4 * kg) =
-            make_float4(cre[0], cre[1], cre[2], cre[3]);
-        *reinterpret_cast<float4*>(ep_im + col * LDE + 4 * kg) =
-            make_float4(cim[0], cim[1], cim[2], cim[3]);
-      }
-      wave_lds_fence();   // each wave reads back only its own Omega planes
-      if (active) {
-        float pr = 0.f, pi = 0.f;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 4 * kg + v;
-          const float R = cre[v], I = cim[v];
-          const float Rt = ep_re[i * LDE + col], It = ep_im[i * LDE + col];
-          pr += R * Rt - I * It;
-          pi += R * It + I * Rt;
-        }
-        xr += (double)pr;
-        xi += (double)pi;
+      for (int v4 = 0; v4 < NV / 4; ++v4) {
+        const int r0 = (NP == 32 ? 8 * v4 : 0) + 4 * kg;
+        *reinterpret_cast<float4*>(ep_re + col * LDE + r0) =
+            make_float4(cre[4 * v4], cre[4 * v4 + 1], cre[4 * v4 + 2], cre[4 * v4 + 3]);
+        *reinterpret_cast<float4*>(ep_im + col * LDE + r0) =
+            make_float4(cim[4 * v4], cim[4 * v4 + 1], cim[4 * v4 + 2], cim[4 * v4 + 3]);
       }
     }
+    wave_lds_fence();   // each wave reads back only its own Omega planes
     if (active) {
-      // trace: lanes [0, NP) read Re Omega_jj, lanes [NP, 2NP) read Im Omega_jj
-      float d = 0.f;
-      if (lane < NP) d = ep_re[lane * LDE + lane];
-      else if (lane < 2 * NP) d = ep_im[(lane - NP) * LDE + (lane - NP)];
+      // the diagonal (lanes [0, NP): Re Omega_jj, lanes [NP, 2NP): Im) and the partner
+      // element Omega_ji of every Omega_ij the lane holds; with four walkers per workgroup
+      // all are read before any is used (two per workgroup leave no registers for that)
+      const int dl = lane < 2 * NP ? lane : 2 * NP - 1;
+      float d = dl < NP ? ep_re[dl * (LDE + 1)] : ep_im[(dl - NP) * (LDE + 1)];
+      float pr = 0.f, pi = 0.f;
+      if constexpr (WPB == 4) {
+        float Rt[NV], It[NV];
 #pragma unroll
-      for (int o = NP / 2; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+        for (int v = 0; v < NV; ++v) {
+          const int i = (NP == 32 ? 8 * (v / 4) : 0) + 4 * kg + (v % 4);
+          Rt[v] = ep_re[i * LDE + col];
+          It[v] = ep_im[i * LDE + col];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const float R = cre[v], I = cim[v];
+          pr += R * Rt[v] - I * It[v];
+          pi += R * It[v] + I * Rt[v];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int i = (NP == 32 ? 8 * (v / 4) : 0) + 4 * kg + (v % 4);
+          const float R = cre[v], I = cim[v];
+          const float Rt = ep_re[i * LDE + col], It = ep_im[i * LDE + col];
+          pr += R * Rt - I * It;
+          pi += R * It + I * Rt;
+        }
+      }
+      xr += (double)pr;
+      xi += (double)pi;
+      // trace: Re in lane NP - 1, Im in lane 2 NP - 1
+      d = NP == 32 ? dpp_half_sum(d) : dpp_row_sum(d);
       double* tp = reinterpret_cast<double*>(tpart + ((size_t)wd * 2 + s) * G + g);
-      if (lane == 0) tp[0] = (double)d;
-      if (lane == NP) tp[1] = (double)d;
+      if (lane == NP - 1) tp[0] = (double)d;
+      if (lane == 2 * NP - 1) tp[1] = (double)d;
     }
     if (g + 1 < G) AFQMC_LSTORE(Anext);
     __syncthreads();
@@ -279,4 +311,3 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
 #undef AFQMC_GLOAD
 #undef AFQMC_LSTORE
 }
-

@@ -26,6 +26,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -474,14 +475,28 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
     return hipGetLastError();
   }
   const int wpb = tile == TILE_W2 ? 2 : 4;
+  // the kernels are instantiated for K_P = 32, 64, 96, 128
+  if (t.KP % 32 != 0 || t.KP < 32 || t.KP > MFMA_KMAX) return hipErrorInvalidValue;
   const size_t shm = mfma_contract_lds_bytes(t, wpb);
   dim3 grid((nw + wpb - 1) / wpb, 2 * n_det);
+#define LAUNCH_CONTRACT_K(NPV, BFV, WPBV, NKV)                                                  \
+  do {                                                                                          \
+    (void)hipFuncSetAttribute((const void*)k_contract_mfma<NPV, BFV, WPBV, NKV>,                \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);            \
+    hipLaunchKernelGGL((k_contract_mfma<NPV, BFV, WPBV, NKV>), grid, dim3(64 * WPBV), shm, st,  \
+                       nw, G, t.nup, t.ndn, t.KP, (const void*)t.Lp, thetaP, weight, tpart,     \
+                       exch);                                                                   \
+  } while (0)
+  // one instantiation per K chunk count (K_P = 32 .. 128 in steps of 32)
 #define LAUNCH_CONTRACT(NPV, BFV, WPBV)                                                         \
   do {                                                                                          \
-    (void)hipFuncSetAttribute((const void*)k_contract_mfma<NPV, BFV, WPBV>,                     \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);            \
-    hipLaunchKernelGGL((k_contract_mfma<NPV, BFV, WPBV>), grid, dim3(64 * WPBV), shm, st, nw,   \
-                       G, t.nup, t.ndn, t.KP, (const void*)t.Lp, thetaP, weight, tpart, exch);  \
+    constexpr int KCH_ = contract_kch<NPV, BFV>();                                              \
+    switch (t.KP / KCH_) {                                                                      \
+      case 32 / KCH_: LAUNCH_CONTRACT_K(NPV, BFV, WPBV, 32 / KCH_); break;                      \
+      case 64 / KCH_: LAUNCH_CONTRACT_K(NPV, BFV, WPBV, 64 / KCH_); break;                      \
+      case 96 / KCH_: LAUNCH_CONTRACT_K(NPV, BFV, WPBV, 96 / KCH_); break;                      \
+      default: LAUNCH_CONTRACT_K(NPV, BFV, WPBV, 128 / KCH_); break;                            \
+    }                                                                                           \
   } while (0)
   if (wpb == 4) {
     if (t.NP == 32) {
@@ -501,6 +516,7 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
     }
   }
 #undef LAUNCH_CONTRACT
+#undef LAUNCH_CONTRACT_K
   return hipGetLastError();
 }
 

@@ -40,6 +40,9 @@ __global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM
   const int col = lane & 31, h = lane >> 5;
   // each thread moves 4 float4 of A and 4 of B per K chunk
   f32x4 pa[4], pb[4];
+  // rows past the walkers and columns past the packed triangle re-read row / column 0: they
+  // only feed accumulator rows / columns the epilogue never stores (zeroing them here would
+  // make every chunk wait for its loads before the MFMAs of the previous chunk)
 #define AB_GLOAD(K0_)                                                                    \
   do {                                                                                   \
     _Pragma("unroll") for (int c_ = 0; c_ < 4; ++c_) {                                   \
@@ -47,12 +50,8 @@ __global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM
       const int rr_ = e_ >> 3, kk_ = (e_ & 7) * 4;                                       \
       const int gr_ = r0 + rr_, gc_ = c0 + rr_;                                          \
       const int sr_ = gr_ < rows ? gr_ : 0, sc_ = gc_ < MM ? gc_ : 0;                     \
-      f32x4 va_ = *reinterpret_cast<const f32x4*>(Y + (size_t)sr_ * Gp + (K0_) + kk_);   \
-      f32x4 vb_ = *reinterpret_cast<const f32x4*>(Lt + (size_t)sc_ * Gp + (K0_) + kk_);  \
-      if (gr_ >= rows) va_ = f32x4{0.f, 0.f, 0.f, 0.f};                                  \
-      if (gc_ >= MM) vb_ = f32x4{0.f, 0.f, 0.f, 0.f};                                    \
-      pa[c_] = va_;                                                                      \
-      pb[c_] = vb_;                                                                      \
+      pa[c_] = *reinterpret_cast<const f32x4*>(Y + (size_t)sr_ * Gp + (K0_) + kk_);      \
+      pb[c_] = *reinterpret_cast<const f32x4*>(Lt + (size_t)sc_ * Gp + (K0_) + kk_);     \
     }                                                                                    \
   } while (0)
 #define AB_LSTORE(BUF_)                                                                  \
@@ -133,8 +132,11 @@ __global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM
 // ---------------------------------------------------------------------------
 constexpr int PR_RB = 4;  // row blocks of 16 (ntot <= 64)
 
-__global__ void __launch_bounds__(512, 1) k_propagate_f32(
-    int M, int ntot, int Kp, int n_taylor, const float* __restrict__ Eh32 /*[M][M]*/,
+// NKC = K_P / 16 wavefronts (K chunks of 16), NRB = ceil(ntot / 16) row blocks: both compile
+// time, so the chunk loops carry no branches and the LDS reads can run ahead of the MFMAs.
+template <int NKC, int NRB>
+__global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
+    int M, int ntot, int Kp_arg, int n_taylor, const float* __restrict__ Eh32 /*[M][M]*/,
     const float* __restrict__ Are, const float* __restrict__ Aim, cd* __restrict__ U,
     const double* __restrict__ weight) {
   extern __shared__ __attribute__((aligned(16))) float tsm[];
@@ -142,17 +144,15 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
   if (!(weight[w] > 0.0)) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int nwave = blockDim.x >> 6;
-  const int ldt = Kp + 4;
-  const int RP = 16 * PR_RB;
+  constexpr int Kp = 16 * NKC;
+  (void)Kp_arg;
+  constexpr int ldt = Kp + 4;
+  constexpr int RP = 16 * NRB;   // term rows held in LDS
   float* Tr = tsm;             // [RP][ldt]
   float* Ti = tsm + RP * ldt;  // [RP][ldt]
   const int j = lane & 15, q4 = lane >> 4;
   const int qcol = 16 * wave + j;  // output column owned by the lane
   const int MM = M * M;
-  const int nkc = Kp / 16;
-  constexpr int KCMAX = 8;  // Kp <= 128
-  const int nrb = (ntot + 15) / 16;
 
   // load U rows (FP64 complex) into the term planes, zero padding
   const cd* Uw = U + (size_t)w * ntot * M;
@@ -163,18 +163,24 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
     Tr[c * ldt + p] = (float)v.re;
     Ti[c * ldt + p] = (float)v.im;
   }
-  // B operands: lane holds rows q = qcol, k = 16*kc + 4*q4 .. +3
-  f32x4 be[KCMAX], bar_[KCMAX], bai[KCMAX];
+  // B operands: lane holds rows q = qcol, k = 16*kc + 4*q4 .. +3 (16-byte loads where the
+  // four are inside the row and aligned)
+  f32x4 be[NKC], bar_[NKC], bai[NKC];
   const bool colok = qcol < M;
 #pragma unroll
-  for (int kc = 0; kc < KCMAX; ++kc) {
+  for (int kc = 0; kc < NKC; ++kc) {
     be[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
     bar_[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
     bai[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (kc < nkc && colok) {
+    const int p0 = 16 * kc + 4 * q4;
+    if (colok && (M & 3) == 0 && p0 + 4 <= M) {
+      be[kc] = *reinterpret_cast<const f32x4*>(Eh32 + (size_t)qcol * M + p0);
+      bar_[kc] = *reinterpret_cast<const f32x4*>(Are + (size_t)w * MM + (size_t)qcol * M + p0);
+      bai[kc] = *reinterpret_cast<const f32x4*>(Aim + (size_t)w * MM + (size_t)qcol * M + p0);
+    } else if (colok) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int p = 16 * kc + 4 * q4 + e;
+        const int p = p0 + e;
         if (p < M) {
           be[kc][e] = Eh32[(size_t)qcol * M + p];
           bar_[kc][e] = Are[(size_t)w * MM + (size_t)qcol * M + p];
@@ -185,19 +191,17 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
   }
   __syncthreads();
 
-  f32x4 yre[PR_RB], yim[PR_RB], cre[PR_RB], cim[PR_RB];
+  f32x4 yre[NRB], yim[NRB], cre[NRB], cim[NRB];
   // X = U E_h  (real B operand)
 #pragma unroll
-  for (int rb = 0; rb < PR_RB; ++rb) {
+  for (int rb = 0; rb < NRB; ++rb) {
     cre[rb] = f32x4{};
     cim[rb] = f32x4{};
   }
 #pragma unroll
-  for (int kc = 0; kc < KCMAX; ++kc) {
-    if (kc >= nkc) break;
+  for (int kc = 0; kc < NKC; ++kc) {
 #pragma unroll
-    for (int rb = 0; rb < PR_RB; ++rb) {
-      if (rb >= nrb) break;
+    for (int rb = 0; rb < NRB; ++rb) {
       const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
       const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
 #pragma unroll
@@ -210,10 +214,10 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
   __syncthreads();
   // write X back as the first term, Y = X
 #pragma unroll
-  for (int rb = 0; rb < PR_RB; ++rb) {
+  for (int rb = 0; rb < NRB; ++rb) {
     yre[rb] = cre[rb];
     yim[rb] = cim[rb];
-    if (rb < nrb && qcol < Kp) {
+    if (qcol < Kp) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         Tr[(16 * rb + 4 * q4 + v) * ldt + qcol] = cre[rb][v];
@@ -225,16 +229,14 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
   // Taylor terms: T <- T A / n, Y += T
   for (int n = 1; n <= n_taylor; ++n) {
 #pragma unroll
-    for (int rb = 0; rb < PR_RB; ++rb) {
+    for (int rb = 0; rb < NRB; ++rb) {
       cre[rb] = f32x4{};
       cim[rb] = f32x4{};
     }
 #pragma unroll
-    for (int kc = 0; kc < KCMAX; ++kc) {
-      if (kc >= nkc) break;
+    for (int kc = 0; kc < NKC; ++kc) {
 #pragma unroll
-      for (int rb = 0; rb < PR_RB; ++rb) {
-        if (rb >= nrb) break;
+      for (int rb = 0; rb < NRB; ++rb) {
         const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
         const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
 #pragma unroll
@@ -249,12 +251,12 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
     const float inv = 1.0f / (float)n;
     __syncthreads();
 #pragma unroll
-    for (int rb = 0; rb < PR_RB; ++rb) {
+    for (int rb = 0; rb < NRB; ++rb) {
       cre[rb] *= inv;
       cim[rb] *= inv;
       yre[rb] += cre[rb];
       yim[rb] += cim[rb];
-      if (rb < nrb && qcol < Kp) {
+      if (qcol < Kp) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           Tr[(16 * rb + 4 * q4 + v) * ldt + qcol] = cre[rb][v];
@@ -266,8 +268,8 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
   }
   // Y into the planes, then U' = Y E_h
 #pragma unroll
-  for (int rb = 0; rb < PR_RB; ++rb) {
-    if (rb < nrb && qcol < Kp) {
+  for (int rb = 0; rb < NRB; ++rb) {
+    if (qcol < Kp) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         Tr[(16 * rb + 4 * q4 + v) * ldt + qcol] = yre[rb][v];
@@ -277,16 +279,14 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
   }
   __syncthreads();
 #pragma unroll
-  for (int rb = 0; rb < PR_RB; ++rb) {
+  for (int rb = 0; rb < NRB; ++rb) {
     cre[rb] = f32x4{};
     cim[rb] = f32x4{};
   }
 #pragma unroll
-  for (int kc = 0; kc < KCMAX; ++kc) {
-    if (kc >= nkc) break;
+  for (int kc = 0; kc < NKC; ++kc) {
 #pragma unroll
-    for (int rb = 0; rb < PR_RB; ++rb) {
-      if (rb >= nrb) break;
+    for (int rb = 0; rb < NRB; ++rb) {
       const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
       const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
 #pragma unroll
@@ -298,15 +298,14 @@ __global__ void __launch_bounds__(512, 1) k_propagate_f32(
   }
   cd* Uo = U + (size_t)w * ntot * M;
 #pragma unroll
-  for (int rb = 0; rb < PR_RB; ++rb) {
-    if (rb >= nrb || !colok) continue;
+  for (int rb = 0; rb < NRB; ++rb) {
+    if (!colok) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int c = 16 * rb + 4 * q4 + v;
       if (c < ntot) Uo[(size_t)c * M + qcol] = mkc((double)cre[rb][v], (double)cim[rb][v]);
     }
   }
-  (void)nwave;
 }
 
 // Fields for the FP32 A-build: Y[2w][g] = Re y, Y[2w+1][g] = Im y, zero for g >= G (< Gp).
