@@ -104,6 +104,39 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// DPP sums over lanes (fixed order, deterministic).  dpp_row_sum: the sum over each 16-lane row,
+// left in the row's last lane (lanes 15, 31, 47, 63): four shifts within the row, out-of-row
+// sources read as zero.  dpp_half_sum: then the last lane of rows 0 and 2 added into rows 1
+// and 3 (row_bcast:15), so lane 31 holds the sum over lanes 0..31 and lane 63 over 32..63.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               ROW_MASK, 0xF, BOUND));
+}
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_f(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK,
+                                                            0xF, BOUND);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL,
+                                                            ROW_MASK, 0xF, BOUND);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T dpp_row_sum(T v) {
+  v += dpp_f<0x111, 0xF, true>(v);   // row_shr:1
+  v += dpp_f<0x112, 0xF, true>(v);   // row_shr:2
+  v += dpp_f<0x114, 0xF, true>(v);   // row_shr:4
+  v += dpp_f<0x118, 0xF, true>(v);   // row_shr:8
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T dpp_half_sum(T v) {
+  v = dpp_row_sum(v);
+  v += dpp_f<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
+  return v;
+}
+
 // Sum over the block of one double per thread; every thread gets the result.
 // `red` must hold blockDim.x / 64 doubles.  Contains __syncthreads().
 __device__ inline double block_sum(double v, double* red) {

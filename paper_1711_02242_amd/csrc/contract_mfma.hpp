@@ -26,23 +26,6 @@ __device__ inline void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum of v over each 16-lane row, left in the row's last lane (lanes 15, 31, 47, 63): four
-// DPP shifts within the row, out-of-row sources read as zero.
-__device__ __forceinline__ float dpp_row_sum(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xF, 0xF, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xF, 0xF, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xF, 0xF, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xF, 0xF, true));
-  return v;
-}
-// After dpp_row_sum: adds the last lane of rows 0 and 2 into rows 1 and 3 (DPP row_bcast:15),
-// so lane 31 holds the sum over lanes 0..31 and lane 63 the sum over lanes 32..63.
-__device__ __forceinline__ float dpp_half_sum(float v) {
-  v = dpp_row_sum(v);
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
-  return v;
-}
-
 // One K chunk of Omega = Lh Theta for the Re and Im halves.  FP32: a holds four K values of
 // one row of Lh (one per MFMA step), br / bi four K values of one column of Re / Im Theta.
 // BF16x3: a / al the hi / lo bf16 of eight K values, br / brl and bi / bil likewise; the

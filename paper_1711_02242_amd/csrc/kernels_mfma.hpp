@@ -208,20 +208,22 @@ inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
 // buffered in LDS with a register prefetch two g ahead, which keeps two
 // workgroups per CU.  Per g each wave writes its Omega plane (Re or Im) to LDS;
 // the Re wave then accumulates sum_ij (R_ij R_ji - I_ij I_ji) and the Im wave
-// 2 sum_ij I_ij R_ji, both in FP64.
+// 2 sum_ij I_ij R_ji, both in FP64.  NK = K_P / 8 register chunks of K (compile time: no
+// per-chunk branches); tr Omega is summed over the lanes by DPP row shifts.
 // ---------------------------------------------------------------------------
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-template <int NP>
+template <int NP, int NK>
 __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
-    int nw, int G, int nup, int ndn, int KP, const double* __restrict__ Lp,
+    int nw, int G, int nup, int ndn, int KP_arg, const double* __restrict__ Lp,
     const double* __restrict__ thp, const double* __restrict__ weight, cd* __restrict__ tpart,
     cd* __restrict__ exch) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   constexpr int NB = NP / 16;
-  constexpr int KMAX = MFMA_KMAX;
-  constexpr int NCH = KMAX / 8;               // K chunks of 8 held per lane as 4 x f64x2
+  constexpr int NCH = NK;                     // K chunks of 8 held per lane as 4 x f64x2
+  constexpr int KP = 8 * NK;                  // K_P (the launcher passes it as KP_arg)
+  (void)KP_arg;
   constexpr int LDE = NP + 1;
   const int s = blockIdx.y & 1, d = blockIdx.y >> 1, n_det = gridDim.y >> 1;
   const int N = s ? ndn : nup;
@@ -239,12 +241,11 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
     return;
   }
   const bool active = (w < nw) && (weight[w] > 0.0);
-  const int lda = KP + 2;
+  constexpr int lda = KP + 2;
   double* At = reinterpret_cast<double*>(smem);                       // [NP][KP + 2]
   double* ep = At + (size_t)NP * lda + (size_t)pair * 2 * NP * LDE;   // this pair's planes
   double* epR = ep;
   double* epI = ep + NP * LDE;
-  const int nk = KP / 8;
   const int j16 = lane & 15, q = lane >> 4;
 
   // B operand: lane holds Theta_part[16 b + j16][8 c + 2 q + {0, 1}]
@@ -255,14 +256,13 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
-        if (c < nk)
-          breg[b][c] = *reinterpret_cast<const f64x2*>(tb + (size_t)(16 * b + j16) * KP + 8 * c + 2 * q);
+        breg[b][c] = *reinterpret_cast<const f64x2*>(tb + (size_t)(16 * b + j16) * KP + 8 * c + 2 * q);
   }
 
   // tile staging: NP * KP doubles as 16-byte chunks
-  const int chunks_per_row = KP / 2;
-  const int nchunks = NP * chunks_per_row;
-  constexpr int MAXCH = (32 * KMAX / 2 + 255) / 256;  // 8
+  constexpr int chunks_per_row = KP / 2;
+  constexpr int nchunks = NP * chunks_per_row;
+  constexpr int MAXCH = (nchunks + 255) / 256;   // 16-byte chunks per thread
   u32x4 pre[MAXCH];
   const double* Lbase = Lp + (size_t)s * G * NP * KP;
 #define F64_GLOAD(G_)                                                                          \
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
   do {                                                                                         \
     _Pragma("unroll") for (int c_ = 0; c_ < MAXCH; ++c_) {                                     \
       const int ch_ = tid + c_ * 256;                                                          \
-      if (ch_ < nchunks) {                                                                     \
+      if ((c_ + 1) * 256 <= nchunks || ch_ < nchunks) {                                        \
         const int row_ = ch_ / chunks_per_row, col_ = (ch_ % chunks_per_row) * 2;              \
         *reinterpret_cast<u32x4*>(At + (size_t)row_ * lda + col_) = pre[c_];                   \
       }                                                                                        \
@@ -289,6 +289,9 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
     F64_GLOAD(0);
     F64_LSTORE();
   }
+  // every global load so far (Theta, the first tile) complete here: otherwise the waits for
+  // the Theta registers land inside the g loop, where they also wait for the prefetched tiles
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
   __syncthreads();
   if (G > 1) F64_GLOAD(1);
   for (int g = 0; g < G; ++g) {
@@ -300,19 +303,17 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
     if (active) {
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        if (c < nk) {
-          f64x2 af[NB];
+        f64x2 af[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+          af[a] = *reinterpret_cast<const f64x2*>(At + (size_t)(16 * a + j16) * lda + 8 * c + 2 * q);
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
 #pragma unroll
           for (int a = 0; a < NB; ++a)
-            af[a] = *reinterpret_cast<const f64x2*>(At + (size_t)(16 * a + j16) * lda + 8 * c + 2 * q);
 #pragma unroll
-          for (int e = 0; e < 2; ++e)
-#pragma unroll
-            for (int a = 0; a < NB; ++a)
-#pragma unroll
-              for (int b = 0; b < NB; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][e], breg[b][c][e], acc[a][b], 0, 0, 0);
-        }
+            for (int b = 0; b < NB; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][e], breg[b][c][e], acc[a][b], 0, 0, 0);
       }
       // this wave's plane, column-major: element (row r, col c) at [c * LDE + r]
       double* pl = part ? epI : epR;
@@ -345,12 +346,13 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
             }
           }
       xacc += pr;
-      double dg = 0.0;
-      if (lane < NP) dg = part ? epI[lane * LDE + lane] : epR[lane * LDE + lane];
-      dg = wave_sum(dg);
-      if (lane == 0) reinterpret_cast<double*>(tpart + ((size_t)wd * 2 + s) * G + g)[part] = dg;
+      const int dl = lane < NP ? lane : NP - 1;
+      double dg = part ? epI[dl * LDE + dl] : epR[dl * LDE + dl];
+      if (lane >= NP) dg = 0.0;
+      dg = NP == 32 ? dpp_half_sum(dg) : dpp_row_sum(dg);   // lane NP - 1
+      if (lane == NP - 1) reinterpret_cast<double*>(tpart + ((size_t)wd * 2 + s) * G + g)[part] = dg;
     }
-    if (g + 2 < G) F64_GLOAD(g + 2);
+    F64_GLOAD(g + 2 < G ? g + 2 : G - 1);   // unconditional: the waits stay exact
     __syncthreads();
   }
 #undef F64_GLOAD
@@ -371,17 +373,29 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   if (t.precision == AFQMC_FP64) {
     const size_t shm = mfma_f64_contract_lds_bytes(t);
     dim3 grid((nw + 1) / 2, 2 * n_det);
-    if (t.NP == 32) {
-      (void)hipFuncSetAttribute((const void*)k_contract_f64mfma<32>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL(k_contract_f64mfma<32>, grid, dim3(256), shm, st, nw, G, t.nup, t.ndn, t.KP,
-                         (const double*)t.Lp, (const double*)thetaP, weight, tpart, exch);
-    } else {
-      (void)hipFuncSetAttribute((const void*)k_contract_f64mfma<16>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      hipLaunchKernelGGL(k_contract_f64mfma<16>, grid, dim3(256), shm, st, nw, G, t.nup, t.ndn, t.KP,
-                         (const double*)t.Lp, (const double*)thetaP, weight, tpart, exch);
-    }
+    // one instantiation per K chunk count (K_P = 32 .. 128 in steps of 32)
+    if (t.KP % 32 != 0 || t.KP < 32 || t.KP > MFMA_KMAX) return hipErrorInvalidValue;
+#define LAUNCH_F64(NPV, NKV)                                                                   \
+  do {                                                                                         \
+    (void)hipFuncSetAttribute((const void*)k_contract_f64mfma<NPV, NKV>,                       \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
+    hipLaunchKernelGGL((k_contract_f64mfma<NPV, NKV>), grid, dim3(256), shm, st, nw, G, t.nup, \
+                       t.ndn, t.KP, (const double*)t.Lp, (const double*)thetaP, weight, tpart, \
+                       exch);                                                                  \
+  } while (0)
+#define LAUNCH_F64_NP(NPV)                                                                     \
+  do {                                                                                         \
+    switch (t.KP / 8) {                                                                        \
+      case 4: LAUNCH_F64(NPV, 4); break;                                                       \
+      case 8: LAUNCH_F64(NPV, 8); break;                                                       \
+      case 12: LAUNCH_F64(NPV, 12); break;                                                     \
+      default: LAUNCH_F64(NPV, 16); break;                                                     \
+    }                                                                                          \
+  } while (0)
+    if (t.NP == 32) LAUNCH_F64_NP(32);
+    else LAUNCH_F64_NP(16);
+#undef LAUNCH_F64_NP
+#undef LAUNCH_F64
     return hipGetLastError();
   }
   const bool bf = t.precision == AFQMC_BF16X3;
