@@ -71,6 +71,13 @@ def load(path: str | None = None) -> C.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise AfqmcError(f"{p} is missing: build it with `python -m paper_1711_02242_amd.build`")
+    # torch ships its own HIP runtime (soname libamdhip64.so.7) and loads it by file name: loaded
+    # first, it is the one the library binds to.  Loaded after the library, it would come in as
+    # a second HIP runtime, and the streams and memory torch hands over would be foreign to ours.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(p)
     P = C.POINTER
     sig = {

@@ -137,6 +137,14 @@ __device__ __forceinline__ T dpp_half_sum(T v) {
   return v;
 }
 
+// Sum over all 64 lanes, returned to every lane: the two half sums of dpp_half_sum read from
+// lanes 31 and 63.
+__device__ __forceinline__ float dpp_wave_sum(float v) {
+  v = dpp_half_sum(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 31)) +
+         __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
 // Sum over the block of one double per thread; every thread gets the result.
 // `red` must hold blockDim.x / 64 doubles.  Contains __syncthreads().
 __device__ inline double block_sum(double v, double* red) {

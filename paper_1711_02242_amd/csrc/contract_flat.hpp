@@ -20,7 +20,7 @@
 //   own Re Omega_ij:  Re += R_ij R_ji,  Im += R_ij I_ji
 //   own Im Omega_ij:  Re -= I_ij I_ji,  Im += I_ij R_ji
 // which sums tr(Omega Omega) over the group in FP32 (accumulated across groups in FP64);
-// the waves reduce the diagonals tr Omega^g by butterflies into an LDS row of traces that
+// the waves reduce the diagonals tr Omega^g by DPP lane sums into an LDS row of traces that
 // is written out once at the end (no atomics: the result is the same on every run).  Rows
 // are read in place from the padded [g][N_P][K_P] table of the other kernels; rows past a
 // group's end read a valid row and are never used.
@@ -231,11 +231,8 @@ __global__ void __launch_bounds__(512) k_contract_mfma_flat(
         dr = ep[lane * LDR + gl * N + lane];
         di = ep[(N + lane) * LDR + gl * N + lane];
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        dr += __shfl_xor(dr, o, 64);
-        di += __shfl_xor(di, o, 64);
-      }
+      dr = dpp_wave_sum(dr);
+      di = dpp_wave_sum(di);
       if (lane == 0) {
         tr[2 * (k * q + gl)] = dr;
         tr[2 * (k * q + gl) + 1] = di;
@@ -455,11 +452,8 @@ __global__ void __launch_bounds__(256) k_contract_mfma_stack(
         dr = ep_re[lane * LDR + gl * N + lane];
         di = ep_im[lane * LDR + gl * N + lane];
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        dr += __shfl_xor(dr, o, 64);
-        di += __shfl_xor(di, o, 64);
-      }
+      dr = dpp_wave_sum(dr);
+      di = dpp_wave_sum(di);
       if (lane == 0) {
         tr[2 * (k * q + gl)] = dr;
         tr[2 * (k * q + gl) + 1] = di;

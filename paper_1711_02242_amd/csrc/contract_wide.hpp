@@ -191,8 +191,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma_wide(
       // trace: wave 0 sums Re Omega_jj, wave 1 Im Omega_jj
       const float* epp = wave == 0 ? ep_re : ep_im;
       float d = lane < NPW ? epp[lane * LDE + lane] : 0.f;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+      d = dpp_wave_sum(d);
       if (lane == 0) reinterpret_cast<double*>(tpart + ((size_t)wd * 2 + s) * G + g)[wave] = (double)d;
     }
     __syncthreads();  // Omega reads done before the next g writes it

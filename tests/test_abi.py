@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -138,3 +139,17 @@ def test_mfma_peak_argument_checks_precede_device_work():
     unsupported = int(re.search(r"AFQMC_E_UNSUPPORTED = (-\d+)", open(HEADER).read()).group(1))
     assert lib.afqmc_mfma_peak(7, C.c_void_p(256), L.MFMA_PEAK_BYTES, None,
                                C.byref(t)) == unsupported
+
+
+def test_library_binds_to_a_single_hip_runtime():
+    """Loading the library first (torch not yet imported) still maps one HIP runtime: torch
+    carries its own copy, and a second one would make torch's streams foreign to the library."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1711_02242_amd import _lib as L\n"
+            "L.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
