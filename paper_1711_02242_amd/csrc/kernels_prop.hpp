@@ -154,14 +154,24 @@ __global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
   const int qcol = 16 * wave + j;  // output column owned by the lane
   const int MM = M * M;
 
-  // load U rows (FP64 complex) into the term planes, zero padding
+  // load U rows (FP64 complex) into the term planes, zero padding: all loads of a thread go
+  // out before the first store (padding positions read a valid element and store zero)
   const cd* Uw = U + (size_t)w * ntot * M;
-  for (int e = tid; e < RP * Kp; e += blockDim.x) {
-    const int c = e / Kp, p = e % Kp;
-    cd v = mkc(0.0, 0.0);
-    if (c < ntot && p < M) v = Uw[(size_t)c * M + p];
-    Tr[c * ldt + p] = (float)v.re;
-    Ti[c * ldt + p] = (float)v.im;
+  {
+    constexpr int NT = 64 * NKC, NIT = RP * Kp / NT;   // = 4 NRB
+    cd uv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = tid + it * NT, c = e / Kp, p = e % Kp;
+      uv[it] = Uw[(size_t)(c < ntot ? c : 0) * M + (p < M ? p : 0)];
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = tid + it * NT, c = e / Kp, p = e % Kp;
+      const bool ok = c < ntot && p < M;
+      Tr[c * ldt + p] = ok ? (float)uv[it].re : 0.f;
+      Ti[c * ldt + p] = ok ? (float)uv[it].im : 0.f;
+    }
   }
   // B operands: lane holds rows q = qcol, k = 16*kc + 4*q4 .. +3 (16-byte loads where the
   // four are inside the row and aligned)
