@@ -98,11 +98,6 @@ __device__ inline double u64_unit(uint64_t r) {
 // ---------------------------------------------------------------------------
 // Wavefront / block reductions (fixed order -> deterministic results).
 // ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = AFQMC_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, AFQMC_WAVE);
-  return v;
-}
 
 // DPP sums over lanes (fixed order, deterministic).  dpp_row_sum: the sum over each 16-lane row,
 // left in the row's last lane (lanes 15, 31, 47, 63): four shifts within the row, out-of-row
@@ -143,6 +138,19 @@ __device__ __forceinline__ float dpp_wave_sum(float v) {
   v = dpp_half_sum(v);
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 31)) +
          __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Sum over the 64 lanes of a wavefront (every lane active), the same value in every lane:
+// DPP row sums, then the two half sums read from lanes 31 and 63.
+__device__ inline double wave_sum(double v) {
+  v = dpp_half_sum(v);
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  const uint64_t a = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 31) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane(lo, 31);
+  const uint64_t b = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 63) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane(lo, 63);
+  return __builtin_bit_cast(double, a) + __builtin_bit_cast(double, b);
 }
 
 // Sum over the block of one double per thread; every thread gets the result.
