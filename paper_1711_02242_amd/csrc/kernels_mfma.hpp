@@ -589,14 +589,25 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
     const int a = t / NB, b = t % NB;
     f64x4 tr = {0.0, 0.0, 0.0, 0.0}, ti = {0.0, 0.0, 0.0, 0.0};
     const int ri = 16 * a + l16, cj = 16 * b + l16;
-    const bool rok = ri < N, cok = cj < N;
-#pragma unroll 8
-    for (int k0 = 0; k0 < M; k0 += 4) {
-      const int k = k0 + q;
-      const double va = (rok && k < M) ? Vs[(size_t)ri * M + k] : 0.0;
-      const cd ub = (cok && k < M) ? Uw[(size_t)cj * M + k] : mkc(0.0, 0.0);
-      tr = __builtin_amdgcn_mfma_f64_16x16x4f64(va, ub.re, tr, 0, 0, 0);
-      ti = __builtin_amdgcn_mfma_f64_16x16x4f64(va, ub.im, ti, 0, 0, 0);
+    // rows / columns past N read row 0 (their outputs are never stored); K past M reads the
+    // last column and is zeroed on the V side.  Four K steps of loads go out before their
+    // MFMAs, so the global latency is paid once per four steps (eight cost a wave per SIMD).
+    const int rr = ri < N ? ri : 0, cc = cj < N ? cj : 0;
+    for (int k0 = 0; k0 < M; k0 += 16) {
+      double va[4];
+      cd ub[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + q, kk = k < M ? k : M - 1;
+        va[u] = Vs[(size_t)rr * M + kk];
+        ub[u] = Uw[(size_t)cc * M + kk];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double av = k0 + 4 * u + q < M ? va[u] : 0.0;
+        tr = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ub[u].re, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ub[u].im, ti, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -700,15 +711,36 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
     f64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
     const int c_in = 16 * a + l16;   // A row (output row c)
     const int p_in = 16 * b + l16;   // B column (output column p)
+    // U loads four K steps at a time ahead of their MFMAs; rows j past N and columns past M
+    // read valid elements (T^-1 is zero there on the A side, such outputs are never stored)
+    const int pp = p_in < M ? p_in : M - 1;
+    // h~ entries of the tile's outputs, loaded ahead as well up to N_P = 32 (beyond, the
+    // registers would cost a wave per SIMD)
+    constexpr bool HPRE = NPAD <= 32;
+    double hvv[4];
 #pragma unroll
-    for (int k0 = 0; k0 < NPAD; k0 += 4) {
-      const int j = k0 + q;
-      const cd tv = (j < N && c_in < N) ? Ag[j * lda + N + c_in] : mkc(0.0, 0.0);
-      const cd uv = (j < N && p_in < M) ? Uw[(size_t)j * M + p_in] : mkc(0.0, 0.0);
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uv.re, cr, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-tv.im, uv.im, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uv.im, ci, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.im, uv.re, ci, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) {
+      const int c = 16 * a + q + 4 * v;
+      hvv[v] = HPRE ? hts[(size_t)(c < N ? c : N - 1) * M + pp] : 0.0;
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < NPAD; k0 += 16) {
+      cd uvv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = k0 + 4 * u + q;
+        uvv[u] = Uw[(size_t)(j < N ? j : N - 1) * M + pp];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = k0 + 4 * u + q;
+        const cd tv = (j < N && c_in < N) ? Ag[j * lda + N + c_in] : mkc(0.0, 0.0);
+        const cd uv = uvv[u];
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uv.re, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-tv.im, uv.im, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uv.im, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.im, uv.re, ci, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -716,7 +748,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       if (c >= N || p >= M) continue;
       const cd th = mkc(cr[v], ci[v]);
       if (thetaT) Tw[(size_t)c * M + p] = th;   // FP64 copy only for the VALU contraction
-      const double hv = hts[(size_t)c * M + p];
+      const double hv = HPRE ? hvv[v] : hts[(size_t)c * M + p];
       e1re = fma(hv, th.re, e1re);
       e1im = fma(hv, th.im, e1im);
       if (packed_kind == 3) {
