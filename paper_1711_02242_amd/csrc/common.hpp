@@ -153,6 +153,45 @@ __device__ inline double wave_sum(double v) {
   return __builtin_bit_cast(double, a) + __builtin_bit_cast(double, b);
 }
 
+// Largest value over the 64 lanes (every lane active), ties to the smallest index; the result
+// in every lane.  The order (value descending, index ascending) is total, so the outcome does
+// not depend on the combination order: DPP row shifts, row_bcast:15, then lanes 31 and 63.
+// Sources outside the row (or rows left out by the mask) read as (-inf, INT_MAX).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_argmax_step(double& best, int& idx) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, best);
+  const uint64_t ninf = __builtin_bit_cast(uint64_t, -__builtin_inf());
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)ninf, (int)(uint32_t)u,
+                                                            CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+      (int)(uint32_t)(ninf >> 32), (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(0x7fffffff, idx, CTRL, ROW_MASK, 0xF, false);
+  const double ob = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  if (ob > best || (ob == best && oi < idx)) {
+    best = ob;
+    idx = oi;
+  }
+}
+__device__ inline void wave_argmax(double& best, int& idx) {
+  dpp_argmax_step<0x111, 0xF>(best, idx);   // row_shr:1
+  dpp_argmax_step<0x112, 0xF>(best, idx);   // row_shr:2
+  dpp_argmax_step<0x114, 0xF>(best, idx);   // row_shr:4
+  dpp_argmax_step<0x118, 0xF>(best, idx);   // row_shr:8
+  dpp_argmax_step<0x142, 0xA>(best, idx);   // row_bcast:15 into rows 1 and 3
+  const uint64_t u = __builtin_bit_cast(uint64_t, best);
+  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  const double b31 = __builtin_bit_cast(
+      double, ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 31) << 32) |
+                  (uint32_t)__builtin_amdgcn_readlane(lo, 31));
+  const double b63 = __builtin_bit_cast(
+      double, ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 63) << 32) |
+                  (uint32_t)__builtin_amdgcn_readlane(lo, 63));
+  const int i31 = __builtin_amdgcn_readlane(idx, 31), i63 = __builtin_amdgcn_readlane(idx, 63);
+  const bool hi_wins = b63 > b31 || (b63 == b31 && i63 < i31);
+  best = hi_wins ? b63 : b31;
+  idx = hi_wins ? i63 : i31;
+}
+
 // Sum over the block of one double per thread; every thread gets the result.
 // `red` must hold blockDim.x / 64 doubles.  Contains __syncthreads().
 __device__ inline double block_sum(double v, double* red) {

@@ -642,15 +642,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
           bi = i;
         }
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      wave_argmax(best, bi);
       if (lane == 0) {
         s_piv = bi;
         s_pk = Ag[bi * lda + k];
