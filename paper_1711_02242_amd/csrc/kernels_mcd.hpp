@@ -58,14 +58,7 @@ __global__ void __launch_bounds__(1024) k_mcd_pivot(int MM, double delta, int n,
     }
   }
   // wave then block argmax, ties -> smallest index
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ob = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(idx, o, 64);
-    if (ob > best || (ob == best && oi < idx)) {
-      best = ob;
-      idx = oi;
-    }
-  }
+  wave_argmax(best, idx);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
     bv[wid] = best;
