@@ -18,9 +18,13 @@ reason, in the design notes of the repository):
 * the weight uses the local energy of the walker before the move (eq:if_rle,
   importance function expanded around the current walker) and
   max(0, cos dtheta) with dtheta the phase of the overlap ratio;
-* local-energy cap |E_L - E_T| <= sqrt(C/dtau), force-bias modulus cap,
-  weight cap (eq:cap, App. B.1), with the trial energy E_T in place of the
-  growth-phase average;
+* local-energy cap |E_L - Ebar| <= sqrt(C/dtau), force-bias modulus cap,
+  weight cap (eq:cap, App. B.1); the centre Ebar is the weighted average of the
+  local energy over the latest population-control block of a growth phase and
+  is frozen afterwards;
+* the trial energy E_T of the importance function starts at E_L(Phi_T, Phi_T)
+  and is reset to the growth estimate (eq:corsam, App. B.2) at the same block
+  ends during the growth phase, then frozen;
 * comb resampling to a fixed population for the branching step (Sec. III.D.4).
 """
 
@@ -208,10 +212,11 @@ def modified_gram_schmidt(U: np.ndarray):
 # Phaseless weight (eq:if_rle, eq:weight_update_2, eq:cap)
 # --------------------------------------------------------------------------
 
-def capped_energy(e_re, E_T: float, dtau: float, C: float):
-    """Re E_L bounded to E_T +- sqrt(C/dtau) (eq:cap with E_T for the reference energy)."""
+def capped_energy(e_re, e_bar: float, dtau: float, C: float):
+    """Re E_L bounded to e_bar +- sqrt(C/dtau) (eq:cap); e_bar is the growth-phase average
+    of the local energy (App. B.1)."""
     half = math.sqrt(C / dtau)
-    return np.clip(e_re, E_T - half, E_T + half)
+    return np.clip(e_re, e_bar - half, e_bar + half)
 
 
 def wrap_angle(a):
@@ -221,9 +226,10 @@ def wrap_angle(a):
     return np.where(w == -np.pi, np.pi, w)
 
 
-def phaseless_weight(W, e_loc_old, arg_old, arg_new, dtau, E_T, C, w_max):
-    """W' = min(w_max, W exp(-dtau (Re E_L^cap(old) - E_T)) max(0, cos(arg_new - arg_old)))."""
-    e_cap = capped_energy(np.real(e_loc_old), E_T, dtau, C)
+def phaseless_weight(W, e_loc_old, arg_old, arg_new, dtau, E_T, C, w_max, e_bar=None):
+    """W' = min(w_max, W exp(-dtau (Re E_L^cap(old) - E_T)) max(0, cos(arg_new - arg_old))),
+    the local energy capped around e_bar (eq:cap; E_T when e_bar is not given)."""
+    e_cap = capped_energy(np.real(e_loc_old), E_T if e_bar is None else e_bar, dtau, C)
     proj = np.maximum(0.0, np.cos(np.asarray(arg_new) - np.asarray(arg_old)))
     Wn = W * np.exp(-dtau * (e_cap - E_T)) * proj
     return np.minimum(Wn, w_max)
@@ -235,13 +241,15 @@ def mean_field_log_factor(S, x, xbar) -> complex:
     return complex(-1j * math.sqrt(S.dtau) * np.sum((x - xbar) * S.lbar))
 
 
-def hybrid_log_importance(S, x, xbar, log_ovlp_old: complex, log_ovlp_new: complex) -> complex:
+def hybrid_log_importance(S, x, xbar, log_ovlp_old: complex, log_ovlp_new: complex,
+                          E_T: float | None = None) -> complex:
     """log I(x, xbar; Psi) of eq:hybrid-wt:
     log[<Psi_T|B(x - xbar)|Psi>/<Psi_T|Psi>] + x.xbar - xbar.xbar/2, where the overlap ratio is
     that of the propagated and the old determinant (times the mean-field c-number) and B
-    carries exp(-dtau (H0' - E_T))."""
+    carries exp(-dtau (H0' - E_T)) (E_T: the trial energy in use, S.E_T when not given)."""
+    e_t = S.E_T if E_T is None else E_T
     return (log_ovlp_new - log_ovlp_old + mean_field_log_factor(S, x, xbar)
-            - S.dtau * (S.h0_prop - S.E_T)
+            - S.dtau * (S.h0_prop - e_t)
             + complex(np.sum(x * xbar) - 0.5 * np.sum(xbar * xbar)))
 
 
@@ -288,9 +296,31 @@ class Params:
     w_max: float | None = None
     fb_cap: float = 1.0
     weight_mode: str = WEIGHT_PHASELESS
+    n_growth: int = 200
 
     def wmax(self, n_walkers: int) -> float:
         return self.w_max if self.w_max is not None else max(100.0, n_walkers / 10.0)
+
+
+@dataclass
+class Growth:
+    """Trial energy and local-energy cap centre of a walker population (App. B.1, B.2).
+
+    Both start at the trial energy.  During the growth phase (steps k < n_growth) the sums
+    below are accumulated over the steps of each population-control block; at the block's
+    last step (the comb step)
+      E_T   <- E_T - (1/dtau) log( sum_k T_{k+1} / sum_k T_k )            (eq:corsam)
+      e_bar <- sum_k sum_w W_{k+1} Re E_L(Psi_{k+1}) / sum_k sum_w W_{k+1}
+    with T_k the total weight before step k and T_{k+1} after its weight update (before the
+    comb), sums over the live walkers.  After the growth phase both stay fixed.  eq:corsam
+    prints the logarithm of the growth ratio alone; the expansion of eq:whycorsam,
+    log I = -dtau (E_L - E_T), gives it the factor -1/dtau used here."""
+    E_T: float
+    e_bar: float
+    num: float = 0.0      # sum over the block of the total weight after each step
+    den: float = 0.0      # sum over the block of the total weight before each step
+    swe: float = 0.0      # sum over the block of sum_w W Re E_L (uncapped)
+    sw: float = 0.0       # sum over the block of sum_w W
 
 
 @dataclass
@@ -304,6 +334,7 @@ class Walkers:
     walker_id: np.ndarray  # (n_w,) int64
     step: int = 0
     theta: np.ndarray | None = None   # (n_w,) walker phase; stays 0 except in free projection
+    growth: "Growth | None" = None    # trial energy and cap centre of the population (App. B)
 
     @property
     def n(self):
@@ -347,7 +378,8 @@ def init_walkers(S, n_walkers: int, U_up=None, U_dn=None) -> Walkers:
     for w in range(n):
         arg[w], logabs[w], e[w], t[w] = _measure_any(S, U_up[w], U_dn[w])
     return Walkers(U=[U_up, U_dn], W=np.ones(n), arg=arg, logabs=logabs, e_loc=e, t=t,
-                   walker_id=np.arange(n, dtype=np.int64), step=0, theta=np.zeros(n))
+                   walker_id=np.arange(n, dtype=np.int64), step=0, theta=np.zeros(n),
+                   growth=Growth(E_T=S.E_T, e_bar=S.E_T))
 
 
 def step(S, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
@@ -364,6 +396,10 @@ def step(S, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
     wmax = P.wmax(n)
     do_qr = P.qr_period > 0 and (k + 1) % P.qr_period == 0
     do_pop = P.pop_period > 0 and (k + 1) % P.pop_period == 0
+    gr = wk.growth
+    in_growth = P.weight_mode != WEIGHT_FREE and P.n_growth > 0 and k < P.n_growth
+    if in_growth:
+        gr.den += float(np.sum(wk.W[wk.W > 0]))
     for w in range(n):
         if not wk.W[w] > 0.0:
             continue
@@ -381,10 +417,10 @@ def step(S, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
         if P.weight_mode == WEIGHT_PHASELESS:
             dphase = mean_field_log_factor(S, x[w], xbar).imag
             wk.W[w] = phaseless_weight(wk.W[w], wk.e_loc[w], wk.arg[w], arg_new + dphase, P.dtau,
-                                       S.E_T, P.el_cap_C, wmax)
+                                       gr.E_T, P.el_cap_C, wmax, gr.e_bar)
         else:
             logI = hybrid_log_importance(S, x[w], xbar, complex(wk.logabs[w], wk.arg[w]),
-                                         complex(logabs_new + log_r, arg_new))
+                                         complex(logabs_new + log_r, arg_new), gr.E_T)
             if P.weight_mode == WEIGHT_HYBRID:
                 proj = max(0.0, math.cos(arg_new - wk.arg[w]
                                          + mean_field_log_factor(S, x[w], xbar).imag))
@@ -398,6 +434,17 @@ def step(S, P: Params, wk: Walkers, x: np.ndarray, u_comb: float | None = None,
         wk.logabs[w] = logabs_new
         wk.e_loc[w] = e_new
         wk.t[w] = t_new
+    if in_growth:
+        live = wk.W > 0
+        gr.num += float(np.sum(wk.W[live]))
+        gr.swe += float(np.sum(wk.W[live] * wk.e_loc.real[live]))
+        gr.sw += float(np.sum(wk.W[live]))
+        if do_pop:
+            if gr.num > 0.0 and gr.den > 0.0:
+                gr.E_T = gr.E_T - math.log(gr.num / gr.den) / P.dtau
+            if gr.sw > 0.0:
+                gr.e_bar = gr.swe / gr.sw
+            gr.num = gr.den = gr.swe = gr.sw = 0.0
     if do_pop:
         if u_comb is None:
             raise ValueError("population control is due: u_comb is required")
@@ -425,8 +472,9 @@ def free_projection_energy(wk: Walkers) -> complex:
 
 def mixed_energy(S: Setup, P: Params, wk: Walkers):
     """Mixed estimator sum_w W_w Re E_L^cap(Psi_w) / sum_w W_w (eq:localenergy, theta = 0)
-    plus the raw sums: (E_mix, sum W Re E_cap, sum W Im E_L, sum W, n_alive)."""
-    e_cap = capped_energy(wk.e_loc.real, S.E_T, P.dtau, P.el_cap_C)
+    plus the raw sums: (E_mix, sum W Re E_cap, sum W Im E_L, sum W, n_alive), the local
+    energy capped around the population's current centre (eq:cap)."""
+    e_cap = capped_energy(wk.e_loc.real, wk.growth.e_bar, P.dtau, P.el_cap_C)
     sw = float(np.sum(wk.W))
     swe = float(np.sum(wk.W * e_cap))
     swi = float(np.sum(wk.W * wk.e_loc.imag))

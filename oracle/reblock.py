@@ -45,7 +45,7 @@ def reblock_converged(x, w, discard: int = 200, min_blocks: int = 16, ratio: flo
     prev = None
     while x.size // L >= min_blocks:
         X, S, err, nb = reblock(x, w, L)
-        if prev is not None and err < ratio * prev[1]:
+        if prev is not None and err <= ratio * prev[1]:
             return X, err, L, True
         prev = (X, err, L)
         L *= 2

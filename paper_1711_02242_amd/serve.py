@@ -59,7 +59,7 @@ def energy_estimate(x, w, discard: int, min_blocks: int = 16, ratio: float = 1.1
     block, last = 1, None
     while len(x) // block >= min_blocks:
         mean, _, err, _ = blocked_error(x, w, block)
-        if last is not None and err < ratio * last[1]:
+        if last is not None and err <= ratio * last[1]:
             return mean, err, block, True
         last = (mean, err, block)
         block *= 2

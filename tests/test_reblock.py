@@ -43,3 +43,13 @@ def test_correlated_series_needs_blocking():
     true = np.sqrt(1 / (1 - phi ** 2)) * np.sqrt((1 + phi) / (1 - phi)) / np.sqrt(n)
     assert err > 3 * naive
     assert abs(err - true) < 0.25 * true
+
+
+def test_zero_variance_series_reaches_plateau():
+    """A constant series has zero error at every block length: the plateau rule (error growth
+    below the ratio on doubling, App. C) must accept it instead of doubling forever."""
+    x = np.full(512, -12.5)
+    m, err, L, ok = reblock_converged(x, np.ones(512), discard=0)
+    assert ok and err == 0.0 and m == -12.5 and L == 2
+    m, err, L, ok = reblock_converged(x, np.linspace(1.0, 2.0, 512), discard=0)
+    assert ok and err < 1e-12 and abs(m + 12.5) < 1e-12

@@ -35,3 +35,14 @@ def test_footprint_grows_with_walkers_and_size():
     assert footprint(mk(64, 512, "fp64")) > 0
     with pytest.raises(Exception):
         footprint(mk(240, 256))       # beyond the MFMA kernels in a mixed-precision mode
+
+
+def test_zero_variance_series_retires():
+    """A constant per-step estimate (zero error at every block length) reaches the plateau, so a
+    job whose estimator has stopped moving can retire at its target."""
+    from paper_1711_02242_amd.serve import energy_estimate
+    x = np.full(600, -3.25)
+    w = np.ones(600)
+    mean, err, block, plateau = energy_estimate(x, w, 100)
+    assert plateau and err == 0.0 and mean == -3.25
+    assert np.allclose(energy_estimate(x, w, 100), R.reblock_converged(x, w, 100), rtol=0)
