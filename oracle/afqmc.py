@@ -25,7 +25,8 @@ reason, in the design notes of the repository):
 * the trial energy E_T of the importance function starts at E_L(Phi_T, Phi_T)
   and is reset to the growth estimate (eq:corsam, App. B.2) at the same block
   ends during the growth phase, then frozen;
-* comb resampling to a fixed population for the branching step (Sec. III.D.4).
+* comb resampling to a fixed population for the branching step (Sec. III.D.4),
+  every copy's weight reset to 1.
 """
 
 from __future__ import annotations
@@ -263,7 +264,11 @@ def comb(W: np.ndarray, u: float):
     Positions (u + j) * (sum W / n), j = 0..n-1, fall into the half-open
     cumulative-weight intervals [C_{i-1}, C_i) of the walkers in index order;
     walker j of the new population copies the walker whose interval holds
-    position j, and every new weight is sum W / n.  Returns (parent, W_new).
+    position j, and every new weight is 1.  The copies stand for the population
+    with equal weights; a common factor of all weights leaves the mixed estimate
+    unchanged, and resetting it to 1 keeps the weight cap w_max relative to the
+    mean weight however far the total has drifted since the last growth-phase
+    update of E_T (App. B.1, B.2).  Returns (parent, W_new).
     """
     n = W.size
     C = np.cumsum(W)
@@ -274,7 +279,7 @@ def comb(W: np.ndarray, u: float):
     parent = np.searchsorted(C, pos, side="right")
     last_alive = int(np.nonzero(W > 0)[0][-1])
     parent = np.minimum(parent, last_alive)
-    return parent.astype(np.int64), np.full(n, total / n)
+    return parent.astype(np.int64), np.ones(n)
 
 
 # --------------------------------------------------------------------------
