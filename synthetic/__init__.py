@@ -24,5 +24,5 @@ from .fields import (  # noqa: F401
     philox_u64,
     u64_to_unit,
 )
-from .trials import excitation_trial, noci_trial, occupation_det  # noqa: F401
+from .trials import excitation_trial, noci_trial, occupation_det, rhf_trial  # noqa: F401
 from .workloads import batch_workload, serving_trace  # noqa: F401
