@@ -82,6 +82,7 @@ def run_gpu(s, args, precision, steps, warmup, timed_kernels=True, closed_shell=
     for _ in range(warmup):
         gs.step(wk, seed=args.seed)
     torch.cuda.synchronize()
+    gs.bound_counts(clear=True)
     if timed_kernels:
         gs.kernel_timing(True)
     # per-step HIP events on the stream the steps run on (the current torch stream)
@@ -110,6 +111,31 @@ def run_gpu(s, args, precision, steps, warmup, timed_kernels=True, closed_shell=
     return gs, wk, (t1 - t0), kt, e
 
 
+def estimator_report(gs, wk, e):
+    """The mixed estimate at the end of the timed steps, the population's E_T and cap centre
+    (growth phase), and how often the rare-event bounds bound over the timed steps."""
+    e_t, e_bar = gs.growth(wk)
+    c = gs.bound_counts()
+    live = max(c[3], 1)
+    return {"e_mix": e[0] / e[2], "e_trial": e_t, "cap_centre": e_bar,
+            "cap_half_width": math.sqrt(gs.params.el_cap_C / gs.dtau),
+            "capped_local_energy_fraction": c[0] / live, "capped_weight_fraction": c[1] / live,
+            "capped_force_bias_components": c[2], "walker_steps_counted": c[3],
+            "fp64_guard_fraction": c[4] / live,
+            "alive": e[3], "status": e[4]}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(s, args):
     """The oracle as it stands, on a bounded sample of the same workload."""
     import numpy as np
@@ -131,7 +157,7 @@ def cpu_baseline(s, args):
         A.step(S, P, wk, x, comb_uniform(args.seed, 0, k))
     dt = time.perf_counter() - t0
     out = {"value": nw * nsteps / dt, "unit": "walker-steps/s", "cores": int(cores),
-           "kind": "oracle", "cpu_count": os.cpu_count(),
+           "kind": "oracle", "cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
            "sample": f"{nw} walkers x {nsteps} steps of the same workload (NumPy FP64, "
                      f"{dt:.1f} s)"}
     # the same oracle on one thread, on a smaller sample
@@ -427,7 +453,10 @@ def main():
                 "attainable_method": "afqmc_mfma_peak: register-only MFMA chains on every SIMD"}
     kernels_ms = {k: round(v[0] / max(args.steps, 1), 4) for k, v in kt.items()}
     eprint(f"bench: {ms_step:.3f} ms/step, {value:.1f} walker-steps/s; per-step kernel ms {kernels_ms}")
-    eprint(f"bench: E_mix = {e[0] / e[2]:.8f}, alive {e[3]}, status {e[4]:#x}")
+    est = estimator_report(gs, wk, e)
+    eprint(f"bench: E_mix = {e[0] / e[2]:.8f}, alive {e[3]}, status {e[4]:#x}, E_T "
+           f"{est['e_trial']:.6f}, cap centre {est['cap_centre']:.6f}, capped E_L fraction "
+           f"{est['capped_local_energy_fraction']:.4f}")
 
     out = {"metric": "walker-steps/s at M=128,N=32,Ng=800 (phaseless AFQMC step)",
            "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
@@ -443,7 +472,7 @@ def main():
                        "p90": round(float(np.percentile(step_ms, 90)), 4),
                        "min": round(min(step_ms), 4), "max": round(max(step_ms), 4),
                        "note": "HIP events per step; every 5th step adds the QR and the comb"},
-           "e_mix": e[0] / e[2]}
+           "e_mix": e[0] / e[2], "estimator": est}
 
     if args.precision != "fp64" and not args.no_compare:
         err64, err_or, n_or = el_error(s, args, gs, wk)

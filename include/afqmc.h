@@ -84,7 +84,8 @@ typedef enum {
 
 /* Weight update (afqmc_params.flags; at most one of the two bits):
  *   0                        phaseless, local-energy importance function (eq:if_rle):
- *                            W <- W exp(-dtau (Re E_L^cap(Psi) - E_T)) max(0, cos dtheta)
+ *                            W <- W exp(-dtau (Re E_L^cap(Psi) - E_T)) max(0, cos dtheta),
+ *                            Re E_L capped to Ebar +- sqrt(C/dtau) (eq:cap)
  *   AFQMC_FLAG_HYBRID        phaseless with the hybrid importance function (eq:hybrid-wt):
  *                            W <- W |I(x, xbar; Psi)| max(0, cos dtheta), capped at w_max
  *   AFQMC_FLAG_FREE_PROJECTION  free projection (Sec. II.C, eq:weight_update) with the hybrid
@@ -117,12 +118,40 @@ typedef struct {
   int32_t qr_period;    /* re-orthonormalize after steps k with (k+1) % p == 0; 0 = never */
   int32_t pop_period;   /* comb after steps k with (k+1) % p == 0; 0 = never          */
   int32_t precision;    /* afqmc_precision                                            */
-  double el_cap_C;      /* local-energy cap |Re E_L - E_T| <= sqrt(C/dtau), > 0 (eq:cap) */
+  double el_cap_C;      /* local-energy cap |Re E_L - Ebar| <= sqrt(C/dtau), > 0 (eq:cap) */
   double w_max;         /* weight cap; NaN -> max(100, n_walkers/10) (App. B.1)       */
   double fb_cap;        /* cap on |xbar_g|, > 0 (App. B.1)                            */
   uint32_t flags;       /* AFQMC_FLAG_* bits; weight mode 0 = phaseless local energy  */
-  uint32_t reserved;
+  int32_t n_growth;     /* steps of the growth phase, >= 0 (see "Growth phase" below) */
+  double theta_guard;   /* precision guard of the mixed modes, > 0 or NaN (see below)   */
 } afqmc_params;
+
+/* Precision guard (AFQMC_FP32, AFQMC_BF16X3).  The rounding error of the low-precision
+ * contraction grows with the size of Theta = U (V^T U)^-1, which grows as a walker's overlap
+ * with the trial becomes ill-conditioned far into a run.  With the guard, every live walker
+ * whose largest |Theta_pc| (over both spins and every determinant) exceeds theta_guard has its
+ * force-bias traces and exchange sums computed again on the FP64 MFMA contraction, in the same
+ * step, and those FP64 values are the ones used.  theta_guard NaN -> 4.0 in AFQMC_FP32 and
+ * 0.75 in AFQMC_BF16X3 (measured: at these bounds the local energy stays within 1e-4 Ha of
+ * FP64 on the 128-orbital workload); +inf turns the guard off.  The guard needs the FP64
+ * MFMA contraction's shapes (max(n_up, n_dn) <= 32, M <= 128): elsewhere it is off.  The
+ * FP64 mode ignores theta_guard. */
+
+/* Growth phase (App. B.1, App. B.2).  Every walker population (its workspace) carries the
+ * trial energy E_T of the importance function and the centre Ebar of the local-energy cap
+ * (eq:cap).  afqmc_walkers_init sets both to the system's E_T (afqmc_info.e_trial).  In the
+ * phaseless modes (weight mode 0 or AFQMC_FLAG_HYBRID) the steps k < n_growth form the growth
+ * phase: over each population-control block of pop_period steps the library sums, over the
+ * live walkers, the total weight before (T_k) and after (T_{k+1}) every weight update and
+ * sum_w W Re E_L; at the block's last step, before the comb,
+ *   E_T  <- E_T - (1/dtau) log( sum_k T_{k+1} / sum_k T_k )   (eq:corsam; the factor -1/dtau
+ *                                                               follows from eq:whycorsam)
+ *   Ebar <- sum_k sum_w W Re E_L / sum_k sum_w W               (the local energy averaged over
+ *                                                               the block, App. B.1)
+ * Afterwards both stay fixed.  n_growth = 0 (or pop_period = 0) keeps both at the initial
+ * E_T throughout.  E_T scales every weight of a step alike, so the mixed estimate does not
+ * depend on it; it keeps the total weight from drifting, so that w_max keeps its meaning.
+ * Free projection has no caps and ignores n_growth. */
 
 typedef struct {
   int32_t n_walkers;     /* >= 1 */
@@ -200,8 +229,9 @@ AFQMC_API int afqmc_workspace_bytes(afqmc_sys s, int32_t n_walkers, size_t* byte
 AFQMC_API int afqmc_get_info(afqmc_sys s, afqmc_info* info);
 
 /* Start every walker at {Psi_I = Phi_T, W = 1, theta = 0} (Sec. II.C, Sec. III.E step 1):
- * writes U, weight, walker_id = index, step = 0, and computes the overlap phase, E_L and
- * the cached force-bias traces.  Asynchronous. */
+ * writes U, weight, walker_id = index, step = 0, computes the overlap phase, E_L and
+ * the cached force-bias traces, and starts the population's growth state (E_T = Ebar = the
+ * system's E_T, empty block sums).  Asynchronous. */
 AFQMC_API int afqmc_walkers_init(afqmc_sys s, afqmc_walkers* w);
 
 /* Recompute, from the current U, everything cached per walker: arg_ovlp, log_ovlp, e_loc
@@ -277,7 +307,8 @@ AFQMC_API int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc
 
 /* Mixed-estimator sums over the walkers (eq:localenergy), reduced on the device in a fixed
  * order, copied to the host, synchronizing the stream.  With c_w = W_w e^{i theta_w}
- * (theta = 0 in the phaseless modes) and E_w = E_L(Psi_w), capped (eq:cap) in the phaseless
+ * (theta = 0 in the phaseless modes) and E_w = E_L(Psi_w), its real part capped to
+ * Ebar +- sqrt(C/dtau) (eq:cap; Ebar of the population, see "Growth phase") in the phaseless
  * modes and uncapped in free projection:
  *   out[0] = Re sum_w c_w E_w      out[1] = Im sum_w c_w E_w
  *   out[2] = Re sum_w c_w          out[5] = Im sum_w c_w
@@ -316,6 +347,20 @@ AFQMC_API int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_
 #define AFQMC_MFMA_PEAK_BYTES 16384
 AFQMC_API int afqmc_mfma_peak(int32_t precision, void* out_dev, size_t out_bytes,
                               void* hip_stream, double* tflops);
+
+/* The current E_T (out[0]) and cap centre Ebar (out[1]) of a walker population (see
+ * "Growth phase"); synchronizes the stream. */
+AFQMC_API int afqmc_get_growth(afqmc_sys s, const afqmc_walkers* w, double out[2]);
+
+/* Counters of the rare-event bounds (App. B.1) accumulated by afqmc_step since setup or the
+ * last clear (synchronizes the stream; clear != 0 zeroes them afterwards):
+ *   out[0] walker-steps whose local energy was capped in the weight (eq:cap)
+ *   out[1] walker-steps whose weight was capped at w_max
+ *   out[2] force-bias components xbar_g whose modulus was capped at fb_cap
+ *   out[3] walker-steps whose weight was updated (live walkers)
+ *   out[4] walker-steps whose contraction the precision guard redid in FP64
+ * out[0] / out[3] is the fraction of capped walker-steps. */
+AFQMC_API int afqmc_get_bound_counts(afqmc_sys s, uint64_t out[5], int clear);
 
 /* Read and clear the sticky status word (synchronizes the stream). */
 AFQMC_API int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear);

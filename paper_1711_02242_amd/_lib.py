@@ -25,7 +25,7 @@ EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walk
            "afqmc_mcd_workspace_bytes", "afqmc_modified_cholesky", "afqmc_setup_multidet",
            "afqmc_batch_create", "afqmc_batch_step", "afqmc_batch_destroy", "afqmc_autotune",
            "afqmc_set_tile", "afqmc_get_tile", "afqmc_energy_enqueue", "afqmc_footprint_bytes",
-           "afqmc_mfma_peak"]
+           "afqmc_mfma_peak", "afqmc_get_growth", "afqmc_get_bound_counts"]
 
 TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5}
 MFMA_PEAK_BYTES = 16384   # AFQMC_MFMA_PEAK_BYTES
@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("dtau", C.c_double), ("e_trial", C.c_double), ("n_taylor", C.c_int32),
                 ("qr_period", C.c_int32), ("pop_period", C.c_int32), ("precision", C.c_int32),
                 ("el_cap_C", C.c_double), ("w_max", C.c_double), ("fb_cap", C.c_double),
-                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+                ("flags", C.c_uint32), ("n_growth", C.c_int32), ("theta_guard", C.c_double)]
 
 
 class WalkersC(C.Structure):
@@ -94,6 +94,8 @@ def load(path: str | None = None) -> C.CDLL:
         "afqmc_fields_draw": ([C.c_void_p, P(WalkersC), P(FieldsC), C.c_void_p], C.c_int),
         "afqmc_energy": ([C.c_void_p, P(WalkersC), P(C.c_double)], C.c_int),
         "afqmc_get_status": ([C.c_void_p, P(C.c_uint32), C.c_int], C.c_int),
+        "afqmc_get_growth": ([C.c_void_p, P(WalkersC), P(C.c_double)], C.c_int),
+        "afqmc_get_bound_counts": ([C.c_void_p, P(C.c_uint64), C.c_int], C.c_int),
         "afqmc_kernel_timing": ([C.c_void_p, C.c_int], C.c_int),
         "afqmc_kernel_time": ([C.c_void_p, C.c_int, P(C.c_double), P(C.c_int64)], C.c_int),
         "afqmc_destroy": ([C.c_void_p], C.c_int),

@@ -38,7 +38,8 @@ class System:
                  n_taylor: int = 6, qr_period: int = 5, pop_period: int = 5, el_cap_C: float = 2.0,
                  w_max: float | None = None, fb_cap: float = 1.0, e_trial: float | None = None,
                  weight_mode: str = "phaseless", mean_field: bool = False,
-                 closed_shell: bool = False, coeffs=None, stream=None):
+                 closed_shell: bool = False, coeffs=None, n_growth: int = 200,
+                 theta_guard: float | None = None, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise L.AfqmcError("no GPU visible: the AFQMC library runs on the GPU only")
@@ -70,7 +71,8 @@ class System:
                      w_max=math.nan if w_max is None else float(w_max), fb_cap=fb_cap,
                      flags=L.WEIGHT_MODES[weight_mode]
                      | (L.FLAG_MEAN_FIELD if mean_field else 0)
-                     | (L.FLAG_CLOSED_SHELL if closed_shell else 0), reserved=0)
+                     | (L.FLAG_CLOSED_SHELL if closed_shell else 0), n_growth=int(n_growth),
+                     theta_guard=math.nan if theta_guard is None else float(theta_guard))
         self.weight_mode = weight_mode
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -176,6 +178,21 @@ class System:
     def mixed_energy(self, wk: "Walkers") -> float:
         a, _, c, _, _ = self.energy(wk)
         return a / c
+
+    def growth(self, wk: "Walkers"):
+        """(E_T, cap centre) of the population (``afqmc_get_growth``; synchronizes)."""
+        out = (C.c_double * 2)()
+        L.check(self.lib.afqmc_get_growth(self.handle, wk.c_ref(), out), "afqmc_get_growth")
+        return out[0], out[1]
+
+    def bound_counts(self, clear: bool = False):
+        """(capped local energies, capped weights, capped force-bias components, live
+        walker-steps, walker-steps redone in FP64 by the precision guard) since setup or the
+        last clear (``afqmc_get_bound_counts``)."""
+        out = (C.c_uint64 * 5)()
+        L.check(self.lib.afqmc_get_bound_counts(self.handle, out, int(clear)),
+                "afqmc_get_bound_counts")
+        return tuple(int(v) for v in out)
 
     def status(self, clear: bool = False) -> int:
         st = C.c_uint32()

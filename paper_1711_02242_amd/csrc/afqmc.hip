@@ -53,7 +53,8 @@ struct TimedLaunch {
 
 struct WsLayout {
   size_t thetaT, tcur, tpart, exch, e1, logdet, wflag, enew, y, A, X0, X1, Y, parent, csum,
-      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, mfterm, logR, psnap, ldc, wflc, dstep, total;
+      wnew, asnap, lsnap, esum, thetaP, y32, fbterm, mfterm, logR, psnap, ldc, wflc, dstep, growth,
+      thmax, thetaP64, glist, gcount, total;
 };
 
 }  // namespace
@@ -70,7 +71,11 @@ struct afqmc_sys_s {
   double* Lh = nullptr;    // [G][ntot][M]
   double* ht = nullptr;    // [ntot][M]
   unsigned* status = nullptr;
+  unsigned long long* capcount = nullptr;   // [CAP_COUNT] counters of the rare-event bounds
   MfmaTables mt;           // packed low-precision copies for the MFMA contraction
+  MfmaTables mt64;         // FP64 packed copy for the precision guard of the mixed modes
+  bool guard_on = false;   // mixed mode with the guard: walkers with max|Theta| > guard redone
+  double guard = INFINITY; //   in FP64 (afqmc_params.theta_guard)
   float* Lt32 = nullptr;   // [M(M+1)/2][Gp] FP32 transposed Cholesky tensor, lower triangle
   int* abpairs = nullptr;  // [M(M+1)/2][2] (q M + p, p M + q) of each packed column
   double* Lt64 = nullptr;  // [M(M+1)/2][Gp64] FP64 packed L^T (FP64 A-build)
@@ -137,6 +142,11 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.ldc = take(S->multi ? nw * 2 * 16 : 0);
   L.wflc = take(S->multi ? nw * 2 * 4 : 0);
   L.dstep = take(8);
+  L.growth = take(GR_COUNT * 8);
+  L.thmax = take(S->guard_on ? nw * nd * 2 * 8 : 0);
+  L.thetaP64 = take(S->guard_on ? mfma_theta_bytes(S->mt64, nw) : 0);
+  L.glist = take(S->guard_on ? nw * 4 : 0);
+  L.gcount = take(S->guard_on ? 8 : 0);
   L.total = o;
   return L;
 }
@@ -308,6 +318,7 @@ void free_sys(afqmc_sys_s* S) {
   hipFree(S->Lh);
   hipFree(S->ht);
   hipFree(S->status);
+  hipFree(S->capcount);
   hipFree(S->Lt32);
   hipFree(S->abpairs);
   hipFree(S->Lt64);
@@ -315,6 +326,7 @@ void free_sys(afqmc_sys_s* S) {
   hipFree(S->Eh32);
   hipFree(S->coef);
   mfma_free_tables(S->mt);
+  mfma_free_tables(S->mt64);
   delete S;
 }
 
@@ -347,7 +359,9 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
                        S->ndn, S->V, S->ht, (const cd*)w->U, w->weight, check_weight,          \
                        S->mt.enabled ? nullptr : at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet),   \
                        at<cd>(ws, L.e1),                                                       \
-                       at<unsigned>(ws, L.wflag), packed, kind, S->mt.NP, S->mt.KP);          \
+                       at<unsigned>(ws, L.wflag), packed, kind, S->mt.NP, S->mt.KP,           \
+                       S->guard_on ? at<double>(ws, L.thmax) : nullptr,                        \
+                       S->guard_on ? at<double>(ws, L.thetaP64) : nullptr);                    \
   } while (0)
   if (nmax <= 16)
     OVL(16);
@@ -362,7 +376,9 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
   return AFQMC_OK;
 }
 
-int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
+// The local-energy contraction and the energy assembly.  `in_step` counts the walkers the
+// precision guard redoes in FP64 (the counters of afqmc_get_bound_counts cover steps only).
+int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, bool in_step) {
   void* ws = w->workspace;
   if (!S->mt.enabled) {
     Timer tm(S, KG_CONTRACT);
@@ -387,6 +403,19 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
     Timer tm(S, KG_CONTRACT);
     HIPCHK(mfma_contract(S->mt, S->stream, w->n_walkers, S->n_det, S->G, at<void>(ws, L.thetaP),
                          w->weight, at<cd>(ws, L.tpart), at<cd>(ws, L.exch), S->tile));
+    if (S->guard_on) {
+      // walkers far from the trial (large Theta) again in FP64, over the partial sums of the
+      // low-precision pass
+      hipLaunchKernelGGL(k_guard_list, dim3(1), dim3(1024), 0, S->stream, w->n_walkers, S->n_det,
+                         S->guard, w->weight, (const double*)at<double>(ws, L.thmax),
+                         at<int>(ws, L.glist), at<int>(ws, L.gcount),
+                         in_step ? S->capcount : nullptr);
+      HIPCHK(hipGetLastError());
+      HIPCHK(mfma_contract(S->mt64, S->stream, w->n_walkers, S->n_det, S->G,
+                           at<void>(ws, L.thetaP64), w->weight, at<cd>(ws, L.tpart),
+                           at<cd>(ws, L.exch), TILE_DEFAULT, at<int>(ws, L.glist),
+                           at<int>(ws, L.gcount)));
+    }
   }
   if (S->multi) {
     Timer tm(S, KG_ASSEMBLE);
@@ -413,7 +442,7 @@ int do_measure(afqmc_sys_s* S, afqmc_walkers* w) {
   hipLaunchKernelGGL(k_step_set, dim3(1), dim3(1), 0, S->stream, at<int64_t>(ws, L.dstep), w->step);
   int rc = launch_overlap(S, w, L, 1);
   if (rc) return rc;
-  rc = launch_contract(S, w, L);
+  rc = launch_contract(S, w, L, false);
   if (rc) return rc;
   hipLaunchKernelGGL(k_measure_finish, dim3((w->n_walkers + 255) / 256), dim3(256), 0, S->stream,
                      w->n_walkers, (double)S->sf, at<cd>(ws, S->multi ? L.ldc : L.logdet),
@@ -438,7 +467,8 @@ int launch_fields(afqmc_sys_s* S, const afqmc_walkers* w, const afqmc_fields* f,
                      ((S->p.flags & (AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION)) && !xout)
                          ? at<cd>(ws, L.fbterm) : nullptr,
                      S->lbar,
-                     ((S->p.flags & AFQMC_FLAG_MEAN_FIELD) && !xout) ? at<cd>(ws, L.mfterm) : nullptr);
+                     ((S->p.flags & AFQMC_FLAG_MEAN_FIELD) && !xout) ? at<cd>(ws, L.mfterm) : nullptr,
+                     xout ? nullptr : S->capcount);
   HIPCHK(hipGetLastError());
   return AFQMC_OK;
 }
@@ -465,6 +495,12 @@ const char* afqmc_error_string(int code) {
 
 namespace {
 
+// Threshold of the precision guard: afqmc_params.theta_guard, NaN -> the precision's default.
+double guard_threshold(const afqmc_params* p) {
+  if (!std::isnan(p->theta_guard)) return p->theta_guard;
+  return p->precision == AFQMC_BF16X3 ? 0.75 : 4.0;
+}
+
 // Setup of a trial with n_det determinants; coeffs == nullptr is the single-determinant trial
 // of afqmc_setup.  phi_up / phi_dn hold n_det blocks [M][n_up] / [M][n_dn], the leading first.
 int setup_impl(const afqmc_params* p, double h0, const double* h1, const double* L_chol, int n_det,
@@ -481,7 +517,8 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
   if (M < 1 || nup < 0 || ndn < 0 || nup > M || ndn > M || nup + ndn < 1 || G < 0)
     return AFQMC_E_ARG;
   if (!(p->dtau > 0.0) || p->n_taylor < 1 || p->n_taylor > 20 || p->qr_period < 0 ||
-      p->pop_period < 0 || !(p->el_cap_C > 0.0) || !(p->fb_cap > 0.0))
+      p->pop_period < 0 || !(p->el_cap_C > 0.0) || !(p->fb_cap > 0.0) || p->n_growth < 0 ||
+      !(std::isnan(p->theta_guard) || p->theta_guard > 0.0))
     return AFQMC_E_ARG;
   const uint32_t known = AFQMC_FLAG_HYBRID | AFQMC_FLAG_FREE_PROJECTION | AFQMC_FLAG_MEAN_FIELD |
                          AFQMC_FLAG_CLOSED_SHELL;
@@ -710,11 +747,13 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
       (rc = dev_upload(S, &S->lbar, lb.data(), lb.size())) ||
       (rc = dev_upload(S, &S->Lh, Lh.data(), Lh.size())) ||
       (rc = dev_upload(S, &S->ht, ht.data(), ht.size())) ||
-      (rc = dev_upload<unsigned>(S, &S->status, nullptr, 1))) {
+      (rc = dev_upload<unsigned>(S, &S->status, nullptr, 1)) ||
+      (rc = dev_upload<unsigned long long>(S, &S->capcount, nullptr, CAP_COUNT))) {
     free_sys(S);
     return rc;
   }
-  if (hipMemset(S->status, 0, sizeof(unsigned)) != hipSuccess) {
+  if (hipMemset(S->status, 0, sizeof(unsigned)) != hipSuccess ||
+      hipMemset(S->capcount, 0, CAP_COUNT * sizeof(unsigned long long)) != hipSuccess) {
     free_sys(S);
     return AFQMC_E_HIP;
   }
@@ -765,6 +804,19 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
       return rc;
     }
     if (S->mt.enabled) S->device_bytes += S->mt.bytes;
+    // precision guard of the mixed modes: an FP64 copy of the tables for the walkers redone
+    // in FP64 (the FP64 MFMA contraction covers N <= 32, M <= 128)
+    const double guard = guard_threshold(p);
+    if (p->precision != AFQMC_FP64 && std::isfinite(guard) && S->mt.enabled && !S->mt.wide) {
+      rc = mfma_build_tables(S->mt64, AFQMC_FP64, M, nup_i, ndn_i, G, Lh.data(), n_det);
+      if (rc != AFQMC_OK || S->mt64.NP != S->mt.NP || S->mt64.KP != S->mt.KP) {
+        free_sys(S);
+        return rc != AFQMC_OK ? rc : AFQMC_E_UNSUPPORTED;
+      }
+      S->device_bytes += S->mt64.bytes;
+      S->guard_on = true;
+      S->guard = guard;
+    }
   }
   // FP32 A-build and propagation in the mixed-precision modes: k_propagate_f32 where it
   // covers the shape (M <= 128, N_up + N_dn <= 64), else k_propagate_f32_wide (M <= 224,
@@ -830,6 +882,9 @@ int afqmc_walkers_init(afqmc_sys s, afqmc_walkers* w) {
   if (rc) return rc;
   hipLaunchKernelGGL(k_init_walkers, dim3(w->n_walkers), dim3(256), 0, s->stream, w->n_walkers,
                      s->ntot * s->M, s->V, (cd*)w->U, w->weight, w->walker_id, w->phase);
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  hipLaunchKernelGGL(k_growth_init, dim3(1), dim3(64), 0, s->stream,
+                     at<double>(w->workspace, L.growth), s->e_trial);
   HIPCHK(hipGetLastError());
   w->step = 0;
   return do_measure(s, w);   // also sets the device step counter
@@ -853,6 +908,11 @@ int afqmc_fields_draw(afqmc_sys s, const afqmc_walkers* w, const afqmc_fields* f
 }  // extern "C"
 
 namespace {
+
+// Steps k < n_growth of a phaseless mode form the growth phase (App. B.1, B.2).
+bool in_growth_phase(const afqmc_sys_s* s, int64_t k) {
+  return !(s->p.flags & AFQMC_FLAG_FREE_PROJECTION) && s->p.n_growth > 0 && k < s->p.n_growth;
+}
 
 // One step of the random walk (Sec. III.E) enqueued on s->stream.  With `graph` the step
 // number is read on the device from the workspace counter (so that a captured graph can be
@@ -999,15 +1059,21 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
   }
   // 5-6. overlap, Theta, local energy of the new determinants
   if ((rc = launch_overlap(s, w, L, 1))) return rc;
-  if ((rc = launch_contract(s, w, L))) return rc;
-  // 7. phaseless weights
+  if ((rc = launch_contract(s, w, L, true))) return rc;
+  // 7. phaseless weights, with the growth-phase sums around them (App. B.1, B.2)
+  const bool pop_due = s->p.pop_period > 0 && (k + 1) % s->p.pop_period == 0;
+  const bool growing = in_growth_phase(s, k);
+  double* growth = at<double>(ws, L.growth);
   {
     Timer tm(s, KG_WEIGHT);
     const double wmax = std::isnan(s->p.w_max) ? std::max(100.0, nw / 10.0) : s->p.w_max;
     const int mode = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 2
                      : (s->p.flags & AFQMC_FLAG_HYBRID) ? 1 : 0;
+    if (growing)
+      hipLaunchKernelGGL(k_growth_sum, dim3(1), dim3(256), 0, s->stream, nw, 0, 0, s->p.dtau,
+                         w->weight, (const cd*)w->e_loc, growth);
     hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, s->stream, nw, mode,
-                       (double)s->sf, s->p.dtau, s->h0p, s->e_trial,
+                       (double)s->sf, s->p.dtau, s->h0p, (const double*)growth,
                        sqrt(s->p.el_cap_C / s->p.dtau), wmax,
                        at<cd>(ws, s->multi ? L.ldc : L.logdet),
                        at<unsigned>(ws, s->multi ? L.wflc : L.wflag), at<cd>(ws, L.enew),
@@ -1015,11 +1081,14 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
                        (s->p.flags & AFQMC_FLAG_MEAN_FIELD) ? at<cd>(ws, L.mfterm) : nullptr,
                        (s->G + 3) / 4,
                        qr_due ? at<double>(ws, L.logR) : nullptr, w->weight, w->arg_ovlp,
-                       w->log_ovlp, (cd*)w->e_loc, w->phase, s->status);
+                       w->log_ovlp, (cd*)w->e_loc, w->phase, s->status, s->capcount);
+    if (growing)
+      hipLaunchKernelGGL(k_growth_sum, dim3(1), dim3(256), 0, s->stream, nw, 1, pop_due ? 1 : 0,
+                         s->p.dtau, w->weight, (const cd*)w->e_loc, growth);
     HIPCHK(hipGetLastError());
   }
   // 8. population control
-  if (s->p.pop_period > 0 && (k + 1) % s->p.pop_period == 0) {
+  if (pop_due) {
     Timer tm(s, KG_COMB);
     const double u = f->u_comb;
     const size_t cshm = nw <= 8192 ? (size_t)nw * 8 : 0;
@@ -1219,7 +1288,8 @@ int afqmc_batch_step(afqmc_batch b, const afqmc_fields* fields) {
     const afqmc_params& p = b->sys[i]->p;
     const int64_t k = b->w[i]->step;
     key[i] = (uint8_t)((p.qr_period > 0 && (k + 1) % p.qr_period == 0 ? 1 : 0) |
-                       (p.pop_period > 0 && (k + 1) % p.pop_period == 0 ? 2 : 0));
+                       (p.pop_period > 0 && (k + 1) % p.pop_period == 0 ? 2 : 0) |
+                       (in_growth_phase(b->sys[i], k) ? 4 : 0));
   }
   hipGraphExec_t exec = nullptr;
   for (auto& g : b->graphs)
@@ -1267,8 +1337,9 @@ int afqmc_energy(afqmc_sys s, const afqmc_walkers* w, double out[6]) {
   double* d = at<double>(w->workspace, L.esum);
   const double half = sqrt(s->p.el_cap_C / s->p.dtau);
   const int fp = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 1 : 0;
-  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, fp, s->e_trial,
-                     half, w->weight, w->phase, (const cd*)w->e_loc, nullptr, d);
+  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, fp,
+                     (const double*)at<double>(w->workspace, L.growth), half, w->weight, w->phase,
+                     (const cd*)w->e_loc, nullptr, d);
   HIPCHK(hipGetLastError());
   double h[6];
   unsigned st = 0;
@@ -1290,8 +1361,10 @@ int afqmc_energy_enqueue(afqmc_sys s, const afqmc_walkers* w, double* out_dev) {
   if (rc) return rc;
   const double half = sqrt(s->p.el_cap_C / s->p.dtau);
   const int fp = (s->p.flags & AFQMC_FLAG_FREE_PROJECTION) ? 1 : 0;
-  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, fp, s->e_trial,
-                     half, w->weight, w->phase, (const cd*)w->e_loc, s->status, out_dev);
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(256), 0, s->stream, w->n_walkers, fp,
+                     (const double*)at<double>(w->workspace, L.growth), half, w->weight, w->phase,
+                     (const cd*)w->e_loc, s->status, out_dev);
   HIPCHK(hipGetLastError());
   return AFQMC_OK;
 }
@@ -1316,13 +1389,19 @@ int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walker
   else if (!(p->precision == AFQMC_FP64 && n_det == 1)) return rc;
   S.f32_prop = p->precision != AFQMC_FP64 && M <= WIDE_KMAX &&
                std::max(S.nup, S.ndn) <= 64;
+  if (p->precision != AFQMC_FP64 && std::isfinite(guard_threshold(p)) && S.mt.enabled &&
+      !S.mt.wide && mfma_plan(S.mt64, AFQMC_FP64, M, S.nup, S.ndn, G, n_det) == AFQMC_OK) {
+    S.mt64.enabled = true;
+    S.guard_on = true;
+  }
   S.Gp = S.f32_prop ? ((G + 31) / 32) * 32 : 0;
   const size_t nt = S.ntot, MM = (size_t)M * M, g1 = G > 0 ? G : 1;
   size_t sb = MM * 8 + n_det * nt * M * 8 + g1 * 8;          // E_h, V, lbar
   sb += (n_det * (size_t)G * nt * M > 0 ? n_det * (size_t)G * nt * M : 1) * 8;  // Lh
-  sb += n_det * nt * M * 8 + 4;                              // ht, status
+  sb += n_det * nt * M * 8 + 4 + CAP_COUNT * 8;              // ht, status, bound counters
   if (S.multi) sb += (size_t)2 * n_det * 8;                  // coefficients
   if (S.mt.enabled) sb += S.mt.bytes;
+  if (S.guard_on) sb += S.mt64.bytes;
   const size_t MMh = (size_t)M * (M + 1) / 2;
   if (S.f32_prop || p->precision == AFQMC_FP64) sb += 2 * MMh * 4;   // pair table
   if (S.f32_prop) sb += MMh * (S.Gp > 0 ? S.Gp : 1) * 4 + MM * 4;    // packed L^T, E_h (FP32)
@@ -1334,6 +1413,35 @@ int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walker
   const size_t nw = (size_t)n_walkers;
   *walker_bytes = layout(&S, nw).total + 256 + nw * nt * M * 16 + nw * (8 * 4 + 16 + 8);
   S.mt.enabled = false;   // the descriptor owns no device memory
+  S.mt64.enabled = false;
+  return AFQMC_OK;
+}
+
+int afqmc_get_growth(afqmc_sys s, const afqmc_walkers* w, double out[2]) {
+  if (!s || !out) return AFQMC_E_ARG;
+  int rc = check_walkers(s, w);
+  if (rc) return rc;
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, at<double>(w->workspace, L.growth), sizeof(h), hipMemcpyDeviceToHost,
+                        s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  out[0] = h[GR_ET];
+  out[1] = h[GR_EBAR];
+  return AFQMC_OK;
+}
+
+int afqmc_get_bound_counts(afqmc_sys s, uint64_t out[5], int clear) {
+  if (!s || !out) return AFQMC_E_ARG;
+  unsigned long long h[CAP_COUNT];
+  HIPCHK(hipMemcpyAsync(h, s->capcount, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (int i = 0; i < CAP_COUNT; ++i) out[i] = (uint64_t)h[i];
+  if (clear) {
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, s->stream, s->capcount, CAP_COUNT);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
   return AFQMC_OK;
 }
 

@@ -192,6 +192,36 @@ __device__ inline void wave_argmax(double& best, int& idx) {
   idx = hi_wins ? i63 : i31;
 }
 
+// Growth-phase state of a walker population (k_growth_sum), doubles in the workspace.
+enum { GR_ET = 0, GR_EBAR, GR_NUM, GR_DEN, GR_SWE, GR_SW, GR_COUNT = 8 };
+// Counters of the rare-event bounds (App. B.1), 64-bit, library-owned per system:
+// walker-steps with the local energy capped in the weight, with the weight capped,
+// force-bias components capped, and walker-steps whose weight was updated.
+// The fifth counts walker-steps whose contraction the precision guard redid in FP64.
+enum { CAP_E = 0, CAP_W, CAP_FB, CAP_LIVE, CAP_GUARD, CAP_COUNT = 5 };
+
+// Adds the number of active lanes of the wavefront with `pred` true to *c: one atomic per
+// wavefront, from its lowest active lane (integer sums: the total is order independent).
+__device__ inline void wave_count(unsigned long long* c, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  const unsigned long long act = __ballot(true);
+  if (m && __lane_id() == __builtin_ctzll(act)) atomicAdd(c, (unsigned long long)__popcll(m));
+}
+
+// Largest value over the block of one double per thread; every thread gets the result.
+// `red` must hold blockDim.x / 64 doubles.  Contains __syncthreads().
+__device__ inline double block_max(double v, double* red) {
+  const int lane = threadIdx.x % AFQMC_WAVE, wid = threadIdx.x / AFQMC_WAVE;
+  const int nw = (blockDim.x + AFQMC_WAVE - 1) / AFQMC_WAVE;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, AFQMC_WAVE));
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int i = 1; i < nw; ++i) t = fmax(t, red[i]);
+  return t;
+}
+
 // Sum over the block of one double per thread; every thread gets the result.
 // `red` must hold blockDim.x / 64 doubles.  Contains __syncthreads().
 __device__ inline double block_sum(double v, double* red) {

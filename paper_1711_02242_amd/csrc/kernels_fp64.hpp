@@ -216,7 +216,8 @@ __global__ void __launch_bounds__(256) k_fields(
     uint64_t job, int64_t step_arg, const int64_t* __restrict__ dstep,
     const double* __restrict__ xin, cd* __restrict__ y,
     double* __restrict__ xout, unsigned* __restrict__ status, cd* __restrict__ fbterm,
-    const double* __restrict__ lbar, cd* __restrict__ mfterm) {
+    const double* __restrict__ lbar, cd* __restrict__ mfterm,
+    unsigned long long* __restrict__ counts) {
   // the step number comes from the device counter when one is given (graph replays)
   const int64_t step = dstep ? *dstep : step_arg;
   const int nblk = (G + 3) / 4;
@@ -245,6 +246,7 @@ __global__ void __launch_bounds__(256) k_fields(
   }
   const bool alive = weight[w] > 0.0;
   bool capped = false;
+  unsigned ncap = 0;
   double fr = 0.0, fi = 0.0;  // sum over the block of x xbar - xbar^2 / 2 (eq:hybrid-wt)
   double mr = 0.0, mi = 0.0;  // sum over the block of y_g lbar_g (mean-field c-number)
   for (int j = 0; j < 4; ++j) {
@@ -261,6 +263,7 @@ __global__ void __launch_bounds__(256) k_fields(
         br *= fb_cap / mod;
         bi *= fb_cap / mod;
         capped = true;
+        ++ncap;
       }
       yv = mkc(x[j] - br, -bi);
       fr += x[j] * br - 0.5 * (br * br - bi * bi);
@@ -274,6 +277,8 @@ __global__ void __launch_bounds__(256) k_fields(
   // log of exp(-i s sum y lbar) = (s Im(sum y lbar), -s Re(sum y lbar))
   if (mfterm) mfterm[(size_t)w * nblk + b] = mkc(s * mi, -s * mr);
   if (capped) atomicOr(status, 0x10u);
+  if (counts)
+    for (unsigned j = 1; j <= 4; ++j) wave_count(&counts[CAP_FB], ncap >= j);
 }
 
 
@@ -429,24 +434,30 @@ __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __rest
 // ---------------------------------------------------------------------------
 // Weight update, one thread per walker.
 //   mode 0 phaseless local energy (eq:if_rle, eq:cap):
-//          W <- min(w_max, W exp(-dtau (Re E_L^cap(old) - E_T)) max(0, cos dtheta))
+//          W <- min(w_max, W exp(-dtau (Re E_L^cap(old) - E_T)) max(0, cos dtheta)),
+//          Re E_L capped to the centre +- ecap_half; E_T and the centre come from the
+//          population's growth state (k_growth_sum)
 //   mode 1 phaseless hybrid (eq:hybrid-wt): W <- min(w_max, W |I| max(0, cos dtheta))
 //   mode 2 free projection (Sec. II.C): W e^{i theta} <- W e^{i theta} I
 // with log I = log(<Phi_T|Psi'>/<Phi_T|Psi>) - dtau (h0 - E_T) + sum_g (x xbar - xbar^2/2),
 // where <Phi_T|Psi'> is taken before this step's QR (log det R added back).
 // ---------------------------------------------------------------------------
-__global__ void k_weights(int nw, int mode, double sf, double dtau, double h0, double e_trial,
-                          double ecap_half, double w_max, const cd* __restrict__ logdet,
+__global__ void k_weights(int nw, int mode, double sf, double dtau, double h0,
+                          const double* __restrict__ growth, double ecap_half, double w_max,
+                          const cd* __restrict__ logdet,
                           const unsigned* __restrict__ wflag, const cd* __restrict__ enew,
                           const cd* __restrict__ fbterm, const cd* __restrict__ mfterm, int nblk,
                           const double* __restrict__ logR,
                           double* __restrict__ weight, double* __restrict__ arg_ovlp,
                           double* __restrict__ log_ovlp, cd* __restrict__ e_loc,
-                          double* __restrict__ phase, unsigned* __restrict__ status) {
+                          double* __restrict__ phase, unsigned* __restrict__ status,
+                          unsigned long long* __restrict__ counts) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
   const double W = weight[w];
   if (!(W > 0.0)) return;
+  const double e_trial = growth[GR_ET];
+  const double e_bar = growth[GR_EBAR];
   unsigned st = 0u;
   const cd l0 = logdet[2 * w], l1 = logdet[2 * w + 1];
   double a = sf * l0.im + l1.im;
@@ -473,11 +484,11 @@ __global__ void k_weights(int nw, int mode, double sf, double dtau, double h0, d
   } else if (mode == 0) {
     const cd eo = e_loc[w];
     double ec = eo.re;
-    if (ec < e_trial - ecap_half) {
-      ec = e_trial - ecap_half;
+    if (ec < e_bar - ecap_half) {
+      ec = e_bar - ecap_half;
       st |= 0x4u;
-    } else if (ec > e_trial + ecap_half) {
-      ec = e_trial + ecap_half;
+    } else if (ec > e_bar + ecap_half) {
+      ec = e_bar + ecap_half;
       st |= 0x4u;
     }
     const double proj = fmax(0.0, cos(a - arg_ovlp[w] + mim));
@@ -522,6 +533,102 @@ __global__ void k_weights(int nw, int mode, double sf, double dtau, double h0, d
   log_ovlp[w] = la;
   e_loc[w] = en;
   if (st) atomicOr(status, st);
+  if (counts) {
+    wave_count(&counts[CAP_E], (st & 0x4u) != 0u);
+    wave_count(&counts[CAP_W], (st & 0x8u) != 0u);
+    wave_count(&counts[CAP_LIVE], true);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Growth phase (App. B.1, B.2): the trial energy E_T of the importance function and the
+// centre of the local-energy cap (eq:cap) of one walker population, in the workspace:
+//   g[GR_ET] E_T, g[GR_EBAR] cap centre, and the sums over the current population-control
+//   block: g[GR_NUM] of the total weight after each step, g[GR_DEN] of the total weight
+//   before it, g[GR_SWE] of sum_w W Re E_L (uncapped), g[GR_SW] of sum_w W (live walkers).
+// At the block's last step (the comb step) of the growth phase
+//   E_T <- E_T - log(num / den) / dtau       (eq:corsam, with the -1/dtau of eq:whycorsam)
+//   centre <- swe / sw                       (the local energy averaged over the block)
+// and the sums restart.  Both values stay fixed outside the growth phase.
+// ---------------------------------------------------------------------------
+// Precision guard of the mixed modes: the live walkers whose largest |Theta_pc| over spins
+// and determinants exceeds `limit`, listed in walker order in wlist, and their number in
+// *wcount (added to counts[CAP_GUARD] when counts != NULL).  One workgroup of 1024 threads,
+// each taking a contiguous range of walkers; the list offsets come from one sequential scan.
+__global__ void __launch_bounds__(1024) k_guard_list(int nw, int nd, double limit,
+                                                     const double* __restrict__ weight,
+                                                     const double* __restrict__ thmax,
+                                                     int* __restrict__ wlist,
+                                                     int* __restrict__ wcount,
+                                                     unsigned long long* __restrict__ counts) {
+  __shared__ int part[1024];
+  const int T = blockDim.x, t = threadIdx.x;
+  const int per = (nw + T - 1) / T;
+  const int lo = min(nw, t * per), hi = min(nw, lo + per);
+  auto flagged = [&](int w) {
+    if (!(weight[w] > 0.0)) return false;
+    double m = 0.0;
+    for (int i = 0; i < 2 * nd; ++i) m = fmax(m, thmax[(size_t)w * 2 * nd + i]);
+    return m > limit;
+  };
+  int c = 0;
+  for (int w = lo; w < hi; ++w) c += flagged(w) ? 1 : 0;
+  part[t] = c;
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int i = 0; i < T; ++i) {
+      const int v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+    *wcount = acc;
+    if (counts && acc > 0) atomicAdd(&counts[CAP_GUARD], (unsigned long long)acc);
+  }
+  __syncthreads();
+  int o = part[t];
+  for (int w = lo; w < hi; ++w)
+    if (flagged(w)) wlist[o++] = w;
+}
+
+__global__ void k_clear_u64(unsigned long long* __restrict__ c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
+
+__global__ void k_growth_init(double* __restrict__ g, double e_trial) {
+  if (threadIdx.x < GR_COUNT) g[threadIdx.x] = threadIdx.x <= GR_EBAR ? e_trial : 0.0;
+}
+
+// after == 0: before the weight update, den += sum W.  after == 1: num += sum W,
+// swe += sum W Re E_L, sw += sum W, then the update at a block end.  One block of 256.
+__global__ void __launch_bounds__(256) k_growth_sum(int nw, int after, int block_end, double dtau,
+                                                    const double* __restrict__ weight,
+                                                    const cd* __restrict__ e_loc,
+                                                    double* __restrict__ g) {
+  __shared__ double red[4];
+  double a = 0.0, b = 0.0;
+  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+    const double W = weight[w];
+    if (W > 0.0) {
+      a += W;
+      if (after) b += W * e_loc[w].re;
+    }
+  }
+  a = block_sum(a, red);
+  if (after) b = block_sum(b, red);
+  if (threadIdx.x != 0) return;
+  if (!after) {
+    g[GR_DEN] += a;
+    return;
+  }
+  g[GR_NUM] += a;
+  g[GR_SWE] += b;
+  g[GR_SW] += a;
+  if (block_end) {
+    if (g[GR_NUM] > 0.0 && g[GR_DEN] > 0.0) g[GR_ET] = g[GR_ET] - log(g[GR_NUM] / g[GR_DEN]) / dtau;
+    if (g[GR_SW] > 0.0) g[GR_EBAR] = g[GR_SWE] / g[GR_SW];
+    g[GR_NUM] = g[GR_DEN] = g[GR_SWE] = g[GR_SW] = 0.0;
+  }
 }
 
 // Initialization / measurement: phase and log of the overlap, E_L, from logdet and enew.
@@ -549,7 +656,8 @@ __global__ void k_measure_finish(int nw, double sf, const cd* __restrict__ logde
 // ---------------------------------------------------------------------------
 // Comb population control (Sec. III.D.4): sequential cumulative weights in walker
 // order, positions (u + j) * (sum W / n), parent = walker whose half-open interval
-// holds the position.  One thread does the scan so the arithmetic order is fixed.
+// holds the position; every copy gets weight 1.  One thread does the scan so the
+// arithmetic order is fixed.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_comb_select(int nw, const double* __restrict__ weight,
                                                       double u_given, uint64_t seed, uint64_t job,
@@ -612,7 +720,9 @@ __global__ void __launch_bounds__(1024) k_comb_select(int nw, const double* __re
     }
     parent[j] = lo < last_alive ? lo : last_alive;
   }
-  if (threadIdx.x == 0) *wnew = step_w;
+  // every copy restarts at weight 1: a factor common to all weights leaves the mixed estimate
+  // unchanged, and the weight cap stays relative to the mean weight (App. B.1, B.2)
+  if (threadIdx.x == 0) *wnew = 1.0;
 }
 
 // Gather walker state from a snapshot by parent index.  One block per walker.
@@ -669,7 +779,8 @@ __global__ void __launch_bounds__(256) k_comb_gather(
 // ---------------------------------------------------------------------------
 // Mixed-estimator sums (eq:localenergy, theta = 0) in a fixed reduction order.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_energy_sum(int nw, int free_proj, double e_trial,
+__global__ void __launch_bounds__(256) k_energy_sum(int nw, int free_proj,
+                                                    const double* __restrict__ growth,
                                                     double ecap_half,
                                                     const double* __restrict__ weight,
                                                     const double* __restrict__ phase,
@@ -677,8 +788,10 @@ __global__ void __launch_bounds__(256) k_energy_sum(int nw, int free_proj, doubl
                                                     const unsigned* __restrict__ status,
                                                     double* __restrict__ out) {
   // c = W e^{i theta}: sums of c E (Re, Im), of c (Re, Im) and the live count.  The local
-  // energy is capped (eq:cap) in the phaseless modes and taken as is in free projection.
+  // energy is capped (eq:cap) around the population's cap centre in the phaseless modes and
+  // taken as is in free projection.
   __shared__ double red[8];
+  const double e_bar = growth[GR_EBAR];
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0, f = 0.0;
   for (int w = threadIdx.x; w < nw; w += blockDim.x) {
     const double W = weight[w];
@@ -690,7 +803,7 @@ __global__ void __launch_bounds__(256) k_energy_sum(int nw, int free_proj, doubl
         cr = W * cos(phase[w]);
         ci = W * sin(phase[w]);
       } else {
-        er = fmin(fmax(e.re, e_trial - ecap_half), e_trial + ecap_half);
+        er = fmin(fmax(e.re, e_bar - ecap_half), e_bar + ecap_half);
       }
       a += cr * er - ci * e.im;
       b += cr * e.im + ci * er;

@@ -218,7 +218,7 @@ template <int NP, int NK>
 __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
     int nw, int G, int nup, int ndn, int KP_arg, const double* __restrict__ Lp,
     const double* __restrict__ thp, const double* __restrict__ weight, cd* __restrict__ tpart,
-    cd* __restrict__ exch) {
+    cd* __restrict__ exch, const int* __restrict__ wlist, const int* __restrict__ wcount) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   constexpr int NB = NP / 16;
   constexpr int NCH = NK;                     // K chunks of 8 held per lane as 4 x f64x2
@@ -230,17 +230,24 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int pair = wave >> 1, part = wave & 1;  // part 0: Re Theta, 1: Im Theta
-  const int w = blockIdx.x * 2 + pair;
+  int w = blockIdx.x * 2 + pair;
+  if (wlist) {
+    // only the listed walkers (the precision guard): slot -> walker, workgroups past the
+    // count exit at once (the count is the same for every thread of the workgroup)
+    const int cnt = *wcount;
+    if ((int)blockIdx.x * 2 >= cnt) return;
+    w = w < cnt ? wlist[w] : -1;
+  }
   const int wd = w * n_det + d;                 // (walker, determinant) slot of the outputs
   Lp += (size_t)d * 2 * G * NP * KP;
   if (N == 0) {
-    if (w < nw && part == 0) {
+    if (w >= 0 && w < nw && part == 0) {
       for (int g = lane; g < G; g += 64) tpart[((size_t)wd * 2 + s) * G + g] = mkc(0.0, 0.0);
       if (lane == 0) exch[2 * wd + s] = mkc(0.0, 0.0);
     }
     return;
   }
-  const bool active = (w < nw) && (weight[w] > 0.0);
+  const bool active = (w >= 0) && (w < nw) && (weight[w] > 0.0);
   constexpr int lda = KP + 2;
   double* At = reinterpret_cast<double*>(smem);                       // [NP][KP + 2]
   double* ep = At + (size_t)NP * lda + (size_t)pair * 2 * NP * LDE;   // this pair's planes
@@ -369,7 +376,8 @@ inline size_t mfma_f64_contract_lds_bytes(const MfmaTables& t) {
 
 inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int n_det, int G,
                                 const void* thetaP, const double* weight, cd* tpart, cd* exch,
-                                int tile = TILE_DEFAULT) {
+                                int tile = TILE_DEFAULT, const int* wlist = nullptr,
+                                const int* wcount = nullptr) {
   if (t.precision == AFQMC_FP64) {
     const size_t shm = mfma_f64_contract_lds_bytes(t);
     dim3 grid((nw + 1) / 2, 2 * n_det);
@@ -381,7 +389,7 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
     hipLaunchKernelGGL((k_contract_f64mfma<NPV, NKV>), grid, dim3(256), shm, st, nw, G, t.nup, \
                        t.ndn, t.KP, (const double*)t.Lp, (const double*)thetaP, weight, tpart, \
-                       exch);                                                                  \
+                       exch, wlist, wcount);                                                   \
   } while (0)
 #define LAUNCH_F64_NP(NPV)                                                                     \
   do {                                                                                         \
@@ -544,13 +552,16 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
 //   Theta^T = (T^-1)^T U^T  (16x16 blocks, K = N, complex product as four real ones)
 // Outputs: e1 = tr(ht Theta), log det T (complex), singular flags, and the packed MFMA
 // operand of the contraction or (thetaT != NULL, for the FP64 VALU contraction) Theta^T in FP64.
+// For the precision guard of the mixed modes (thmax != NULL): max |Theta_pc| of the block's
+// walker-spin in thmax and the FP64 packed operand (the layout of packed_kind 3) in packed64.
 // ---------------------------------------------------------------------------
 template <int NPAD>
 __global__ void __launch_bounds__(256) k_overlap_mfma(
     int M, int nup, int ndn, const double* __restrict__ V, const double* __restrict__ ht,
     const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
     cd* __restrict__ thetaT, cd* __restrict__ logdet, cd* __restrict__ e1,
-    unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP) {
+    unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP,
+    double* __restrict__ thmax, double* __restrict__ packed64) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   constexpr int NB = NPAD / 16;
   // determinant d of the trial (blockIdx.z); per-determinant outputs are indexed by
@@ -570,6 +581,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       logdet[2 * wd_ + s] = mkc(0.0, 0.0);
       e1[2 * wd_ + s] = mkc(0.0, 0.0);
       wflag[2 * wd_ + s] = 0u;
+      if (thmax) thmax[2 * wd_ + s] = 0.0;
     }
     return;
   }
@@ -698,6 +710,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
   cd* Tw = thetaT ? thetaT + ((size_t)wd_ * ntot + off) * M : nullptr;
   const double* hts = ht + (size_t)off * M;
   double e1re = 0.0, e1im = 0.0;
+  double th2max = 0.0;   // largest |Theta_pc|^2 this thread stored
   for (int t = wave; t < NB * CB; t += 4) {
     const int a = t / CB, b = t % CB;
     f64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
@@ -740,6 +753,12 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       if (c >= N || p >= M) continue;
       const cd th = mkc(cr[v], ci[v]);
       if (thetaT) Tw[(size_t)c * M + p] = th;   // FP64 copy only for the VALU contraction
+      if (thmax) {
+        th2max = fmax(th2max, th.re * th.re + th.im * th.im);
+        double* o = packed64 + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
+        o[0] = th.re;
+        o[per] = th.im;
+      }
       const double hv = HPRE ? hvv[v] : hts[(size_t)c * M + p];
       e1re = fma(hv, th.re, e1re);
       e1im = fma(hv, th.im, e1im);
@@ -773,6 +792,15 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
       else if (packed_kind == 1) reinterpret_cast<float*>(packed)[o] = 0.f;
       else reinterpret_cast<uint16_t*>(packed)[o] = 0;
     }
+  }
+  if (thmax) {
+    for (size_t e = tid; e < (size_t)2 * per; e += blockDim.x) {
+      const int c = (int)((e % per) / KP), p = (int)(e % KP);
+      if (c < N && p < M) continue;
+      packed64[((size_t)wd_ * 2 + s) * 2 * per + e] = 0.0;
+    }
+    const double m2 = block_max(th2max, red);
+    if (tid == 0) thmax[2 * wd_ + s] = sqrt(m2);
   }
   e1re = block_sum(e1re, red);
   e1im = block_sum(e1im, red);

@@ -116,7 +116,7 @@ def footprint(spec: JobSpec) -> int:
     p = L.Params(M=spec.M, n_up=spec.n_up, n_dn=spec.n_dn, n_chol=spec.n_chol, dtau=spec.dtau,
                  e_trial=math.nan, n_taylor=6, qr_period=5, pop_period=5,
                  precision=L.PRECISIONS[spec.precision], el_cap_C=2.0, w_max=math.nan, fb_cap=1.0,
-                 flags=0, reserved=0)
+                 flags=0, n_growth=0, theta_guard=math.nan)
     sb, wb = C.c_size_t(), C.c_size_t()
     L.check(lib.afqmc_footprint_bytes(C.byref(p), 1, int(spec.n_walkers), C.byref(sb),
                                       C.byref(wb)), "afqmc_footprint_bytes")

@@ -66,7 +66,8 @@ def test_multidet_argument_checks_precede_device_work():
     M, n = 4, 1
     p = pkg._lib.Params(M=M, n_up=n, n_dn=n, n_chol=0, dtau=0.01, e_trial=float("nan"),
                         n_taylor=6, qr_period=5, pop_period=5, precision=0, el_cap_C=2.0,
-                        w_max=float("nan"), fb_cap=1.0, flags=0, reserved=0)
+                        w_max=float("nan"), fb_cap=1.0, flags=0, n_growth=0,
+                        theta_guard=float("nan"))
     h1 = np.eye(M)
     phi = np.zeros((2, M, n))
     phi[:, 0, 0] = 1.0

@@ -87,7 +87,8 @@ def test_flat_dynamic_drift(case, precision, tile):
         steps, dt = (12, 0.01) if s.M <= 40 else (5, 0.005)
     log(f"{tile} dynamic {precision} {case}")
     worst, gs, wk, S, wo = run_lockstep(s, nw, steps, dtau=dt, precision=precision, rtol=1e-4,
-                                        label=f"{tile}-{case}-{precision}", tile=tile)
+                                        label=f"{tile}-{case}-{precision}", tile=tile,
+                                        el_abs=EL_TOL)
     st = gpu_state(wk)
     alive = wo.W > 0
     assert np.abs(st["e"][alive] - wo.e_loc[alive]).max() < EL_TOL

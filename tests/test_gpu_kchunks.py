@@ -60,5 +60,5 @@ def test_propagation_every_shape_lockstep(shape):
     s, nw = _system(shape)
     log(f"propagation lockstep fp32 {shape}")
     worst, *_ = run_lockstep(s, nw, 3, dtau=0.005, precision="fp32", rtol=1e-4,
-                             label=f"kchunks-{shape}")
+                             label=f"kchunks-{shape}", el_abs=1e-4)
     log(f"  worst {worst}")

@@ -86,7 +86,7 @@ def test_dynamic_drift_tiny(precision):
     s = config_system("tiny")
     log(f"dynamic {precision}")
     worst, *_ = run_lockstep(s, 16, 40, dtau=0.01, precision=precision, rtol=5e-5,
-                             label=f"tiny-{precision}")
+                             label=f"tiny-{precision}", el_abs=EL_TOL)
     log(f"  worst {worst}")
 
 
@@ -106,7 +106,8 @@ def test_dynamic_drift_shapes(precision, case):
         s, nw, steps, dt = gen_system(9, 2, 0, seed=8), 5, 10, 0.05
     log(f"dynamic {precision} {case}")
     worst, gs, wk, S, wo = run_lockstep(s, nw, steps, dtau=dt, precision=precision, rtol=1e-4,
-                                        label=f"{case}-{precision}", check_every=1)
+                                        label=f"{case}-{precision}", check_every=1,
+                                        el_abs=EL_TOL)
     st = gpu_state(wk)
     alive = wo.W > 0
     assert np.abs(st["e"][alive] - wo.e_loc[alive]).max() < EL_TOL
@@ -155,7 +156,7 @@ def test_dynamic_drift_wide(precision, case):
     s = gen_system(M, nu, G, seed=32, n_dn=nd)
     log(f"dynamic wide {precision} {case}")
     worst, gs, wk, S, wo = run_lockstep(s, nw, 5, dtau=0.005, precision=precision, rtol=1e-4,
-                                        label=f"wide-{case}-{precision}")
+                                        label=f"wide-{case}-{precision}", el_abs=EL_TOL)
     st = gpu_state(wk)
     alive = wo.W > 0
     assert np.abs(st["e"][alive] - wo.e_loc[alive]).max() < EL_TOL

@@ -55,16 +55,18 @@ def test_admission_respects_the_budget():
 
 
 def test_jobs_retire_at_their_target():
-    """A larger time step decorrelates the energy series within a few hundred steps, so the
-    blocked error reaches its plateau and the job retires before its cap."""
+    """A larger time step shortens the energy series' correlation in steps, so within the cap
+    the blocked error reaches its plateau (growth below 10 % on doubling the block, App. C)
+    below the target and the job retires before its cap."""
     from paper_1711_02242_amd.serve import blocked_error
-    kw = dict(max_steps=3000, discard=300, target_stderr=0.05, dtau=0.05)
-    srv, (r,) = _serve([_spec(3, 16, 256, 301, **kw)], check_every=40)
+    kw = dict(max_steps=20000, discard=300, target_stderr=0.05, dtau=0.05)
+    srv, (r,) = _serve([_spec(3, 16, 256, 301, **kw)], check_every=200)
     log(f"retired after {r.steps} steps: {r.energy:.5f} +- {r.stderr:.5f}")
     x, w = r.energies[300:], r.weights[300:]
     log("  blocking: " + ", ".join(f"L={b}: {blocked_error(x, w, b)[2]:.5f}"
-                                   for b in (1, 2, 4, 8, 16, 32, 64) if len(x) // b >= 16))
-    assert r.plateau and r.stderr < 0.05 and r.steps < 3000 and math.isfinite(r.energy)
+                                   for b in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)
+                                   if len(x) // b >= 16))
+    assert r.plateau and r.stderr < 0.05 and r.steps < 20000 and math.isfinite(r.energy)
 
 
 @pytest.mark.parametrize("M,nw,precision", [(24, 100, "fp32"), (64, 300, "bf16x3"),

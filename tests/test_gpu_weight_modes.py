@@ -32,7 +32,7 @@ def test_weight_modes_lockstep_fp32(mode):
     s = config_system("tiny")
     log(f"weight mode {mode} fp32")
     worst, *_ = run_lockstep(s, 16, 30, dtau=0.01, precision="fp32", rtol=1e-4,
-                             label=f"{mode}-fp32", weight_mode=mode)
+                             label=f"{mode}-fp32", weight_mode=mode, el_abs=1e-4)
     log(f"  worst {worst}")
 
 
