@@ -253,9 +253,12 @@ def batch_leg(args):
 def serving_leg(args):
     """Serving: the first jobs of a Poisson(4/s) trace (M uniform on 32..200, N=M/4, N_g=6M,
     256-2048 walkers) replayed in real time through the continuous-batching server, FP32 bulk,
-    each job run to its target standard error or its step cap.  The serial plain-FP64 figure
-    runs every job alone in FP64 for a few steps, scales its step time to the steps the job
-    took, and queues the jobs first-come-first-served on the same arrival times."""
+    each job run to its target standard error (1 mHa) or its step cap.  Time-to-energy
+    percentiles are taken over the jobs that reached the target only; every job's reblocked
+    error and the steps it would need at its measured rate of error decrease are reported.
+    The serial plain-FP64 figure times every job alone in FP64 over 25 steps (five QR and comb
+    cycles), multiplies that step time by the steps the job took, and queues the jobs
+    first-come-first-served on the same arrival times."""
     import numpy as np
     import torch
 
@@ -272,7 +275,8 @@ def serving_leg(args):
             specs.append(JobSpec(t["job_id"], make, t["M"], t["N"], t["N"], t["n_chol"],
                                  t["n_walkers"], t["seed"], precision="fp32", dtau=0.005,
                                  target_stderr=args.serve_target, max_steps=args.serve_steps,
-                                 discard=args.serve_steps // 3, arrival=t["arrival"] * scale))
+                                 discard=min(200, args.serve_steps // 2),
+                                 arrival=t["arrival"] * scale))
         return specs
 
     def serve(specs):
@@ -283,14 +287,28 @@ def serving_leg(args):
         tte = np.array([r.time_to_energy for r in res])
         ws = sum(r.steps * sp.n_walkers for r, sp in zip(res, specs))
         eprint(f"bench: served {len(res)} jobs in {makespan:.1f} s, max resident "
-               f"{srv.max_resident}, TTE p50 {np.percentile(tte, 50):.1f} s p99 "
-               f"{np.percentile(tte, 99):.1f} s")
+               f"{srv.max_resident}, time to retirement p50 {np.percentile(tte, 50):.1f} s p99 "
+               f"{np.percentile(tte, 99):.1f} s, {sum(reached(r) for r in res)} at the target")
         return res, tte, ws, makespan, srv.max_resident
+
+    def reached(r):
+        return bool(r.plateau and r.stderr < args.serve_target)
+
+    def tte_stats(res, tte):
+        ok = np.array([reached(r) for r in res])
+        out = {"reached_target": int(ok.sum()), "jobs": len(res),
+               "p50_time_to_energy_s": None, "p99_time_to_energy_s": None,
+               "p50_time_to_retirement_s": round(float(np.percentile(tte, 50)), 2),
+               "p99_time_to_retirement_s": round(float(np.percentile(tte, 99)), 2)}
+        if ok.any():
+            out["p50_time_to_energy_s"] = round(float(np.percentile(tte[ok], 50)), 2)
+            out["p99_time_to_energy_s"] = round(float(np.percentile(tte[ok], 99)), 2)
+        return out
 
     specs = job_specs(1.0)
     res, tte, ws, makespan, max_res = serve(specs)
     # serial plain FP64: per-job step time alone, FIFO over the same arrivals
-    t_end, serial_tte = 0.0, []
+    t_end, serial_tte, fp64_ms = 0.0, [], []
     for r, sp in zip(res, specs):
         s = sp.make_system()
         gs = afq.System.from_synthetic(s, dtau=sp.dtau, precision="fp64")
@@ -303,26 +321,35 @@ def serving_leg(args):
             gs.step(wk, seed=sp.seed, job_id=sp.job_id)
         torch.cuda.synchronize()
         per = (time.perf_counter() - a) / args.serve_fp64_steps
+        fp64_ms.append(1e3 * per)
         gs.close()
         del s
         start = max(sp.arrival, t_end)
         t_end = start + per * r.steps
         serial_tte.append(t_end - sp.arrival)
     serial_tte = np.array(serial_tte)
+    jobs = []
+    for r, sp in zip(res, specs):
+        n_est = max(r.steps - sp.discard, 1)
+        need = (sp.discard + n_est * (r.stderr / args.serve_target) ** 2
+                if np.isfinite(r.stderr) else None)
+        jobs.append({"job": r.job_id, "M": sp.M, "walkers": sp.n_walkers, "steps": r.steps,
+                     "energy": round(r.energy, 5), "stderr_ha": round(r.stderr, 5),
+                     "plateau": bool(r.plateau),
+                     "steps_to_target_at_this_rate": None if need is None else int(need)})
     out = {"workload": f"first {len(specs)} jobs of a Poisson(4/s) trace: M uniform on 32..200, "
                        "N=M/4, N_g=6M, 256-2048 walkers, fp32 bulk, dtau=0.005",
-           "jobs": len(res), "hbm_budget_gib": args.serve_budget_gib,
+           "hbm_budget_gib": args.serve_budget_gib,
            "target_stderr_ha": args.serve_target, "step_cap": args.serve_steps,
-           "reached_target": int(sum(r.plateau and r.stderr < args.serve_target for r in res)),
-           "p50_time_to_energy_s": round(float(np.percentile(tte, 50)), 2),
-           "p99_time_to_energy_s": round(float(np.percentile(tte, 99)), 2),
+           **tte_stats(res, tte),
            "walker_steps_per_s": round(ws / makespan, 1), "makespan_s": round(makespan, 2),
-           "max_resident": max_res,
-            "serial_fp64": {"p50_time_to_energy_s": round(float(np.percentile(serial_tte, 50)), 2),
-                            "p99_time_to_energy_s": round(float(np.percentile(serial_tte, 99)), 2),
-                            "walker_steps_per_s": round(ws / float(t_end), 1),
-                            "method": f"each job alone in FP64, {args.serve_fp64_steps} timed "
-                                      "steps scaled to its step count, FIFO on the arrivals"}}
+           "max_resident": max_res, "per_job": jobs,
+           "serial_fp64": {**tte_stats(res, serial_tte),
+                           "walker_steps_per_s": round(ws / float(t_end), 1),
+                           "step_ms_per_job": [round(v, 2) for v in fp64_ms],
+                           "method": f"each job alone in FP64, its step time measured over "
+                                     f"{args.serve_fp64_steps} steps and multiplied by the "
+                                     "steps it took in the served run, FIFO on the arrivals"}}
     if args.serve_load > 0:
         # the same jobs arriving at a fraction of the measured capacity: the trace's arrivals
         # (4/s) keep the server saturated, so its jobs per second of makespan is the capacity
@@ -330,9 +357,7 @@ def serving_leg(args):
         rate = args.serve_load * cap
         res2, tte2, ws2, mk2, mr2 = serve(job_specs(4.0 / rate))
         out["at_load"] = {"load": args.serve_load, "capacity_jobs_per_s": round(cap, 4),
-                          "arrival_rate_jobs_per_s": round(rate, 4),
-                          "p50_time_to_energy_s": round(float(np.percentile(tte2, 50)), 2),
-                          "p99_time_to_energy_s": round(float(np.percentile(tte2, 99)), 2),
+                          "arrival_rate_jobs_per_s": round(rate, 4), **tte_stats(res2, tte2),
                           "walker_steps_per_s": round(ws2 / mk2, 1), "makespan_s": round(mk2, 2),
                           "max_resident": mr2}
     return out
@@ -397,9 +422,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop trace")
     ap.add_argument("--serve-jobs", type=int, default=8)
     ap.add_argument("--serve-steps", type=int, default=300, help="step cap per job")
-    ap.add_argument("--serve-target", type=float, default=0.005, help="target stderr (Ha)")
+    ap.add_argument("--serve-target", type=float, default=0.001, help="target stderr (Ha)")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
-    ap.add_argument("--serve-fp64-steps", type=int, default=2)
+    ap.add_argument("--serve-fp64-steps", type=int, default=25)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="rerun the jobs arriving at this fraction of the measured capacity "
                          "(0: skip)")
