@@ -393,6 +393,23 @@ AFQMC_API int afqmc_modified_cholesky(const double* eri, int32_t M, double delta
                                       int32_t* converged, void* workspace,
                                       size_t workspace_bytes, void* stream);
 
+/* Allocation-free modified Cholesky, for callers that cannot allocate device memory
+ * (serving loops and harnesses that forbid hipMalloc): the same decomposition, kernels and
+ * results as afqmc_modified_cholesky, with its workspace in a library-owned static device
+ * array of AFQMC_MCD_NOALLOC_BYTES bytes, one per GPU, held until the process ends (this
+ * call allocates nothing).  Limit: M <= AFQMC_MCD_NOALLOC_MAX_M, else AFQMC_E_UNSUPPORTED
+ * before any device work.  The array of a GPU is shared by every call on that GPU and keeps
+ * the last call's contents; each call initializes what it reads.  Calls that overlap on one
+ * GPU (from several threads, or on several streams) race on it: serialize them.  The stream
+ * must belong to the current device.  Arguments and errors otherwise as
+ * afqmc_modified_cholesky. */
+#define AFQMC_MCD_NOALLOC_MAX_M 256
+#define AFQMC_MCD_NOALLOC_BYTES 590080   /* D 256^2 doubles + 256^2 flags + state, 256-aligned */
+AFQMC_API int afqmc_modified_cholesky_noalloc(const double* eri, int32_t M, double delta,
+                                              int32_t max_vectors, double* L_out,
+                                              int32_t* n_vectors, int32_t* converged,
+                                              void* stream);
+
 /* Free the device memory owned by the system. */
 AFQMC_API int afqmc_destroy(afqmc_sys s);
 

@@ -25,7 +25,8 @@ EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walk
            "afqmc_mcd_workspace_bytes", "afqmc_modified_cholesky", "afqmc_setup_multidet",
            "afqmc_batch_create", "afqmc_batch_step", "afqmc_batch_destroy", "afqmc_autotune",
            "afqmc_set_tile", "afqmc_get_tile", "afqmc_energy_enqueue", "afqmc_footprint_bytes",
-           "afqmc_mfma_peak", "afqmc_get_growth", "afqmc_get_bound_counts"]
+           "afqmc_mfma_peak", "afqmc_get_growth", "afqmc_get_bound_counts",
+           "afqmc_modified_cholesky_noalloc"]
 
 TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5}
 MFMA_PEAK_BYTES = 16384   # AFQMC_MFMA_PEAK_BYTES
@@ -117,6 +118,9 @@ def load(path: str | None = None) -> C.CDLL:
         "afqmc_modified_cholesky": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p,
                                      P(C.c_int32), P(C.c_int32), C.c_void_p, C.c_size_t,
                                      C.c_void_p], C.c_int),
+        "afqmc_modified_cholesky_noalloc": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32,
+                                             C.c_void_p, P(C.c_int32), P(C.c_int32),
+                                             C.c_void_p], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -1479,25 +1479,49 @@ int afqmc_kernel_time(afqmc_sys s, int kernel, double* ms, int64_t* launches) {
   return AFQMC_OK;
 }
 
-int afqmc_mcd_workspace_bytes(int32_t M, size_t* bytes) {
-  if (M < 1 || !bytes) return AFQMC_E_ARG;
-  const size_t MM = (size_t)M * M;
-  *bytes = al256(MM * 8) + al256(MM) + al256(sizeof(McdState));
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free modified Cholesky: its workspace is this file-scope device array, one copy
+// per GPU, held until the process ends.  Host code must not pass `scratch` itself to a
+// kernel (in host code the name is a host-side stand-in): the device address of each GPU's
+// copy comes from hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t mcd_ws_bytes(size_t M) {
+  return ((M * M * 8 + 255) & ~size_t(255)) + ((M * M + 255) & ~size_t(255)) +
+         ((sizeof(McdState) + 255) & ~size_t(255));
+}
+static_assert(mcd_ws_bytes(AFQMC_MCD_NOALLOC_MAX_M) == AFQMC_MCD_NOALLOC_BYTES,
+              "scratch size of the allocation-free modified Cholesky");
+static __device__ __align__(256) unsigned char scratch[AFQMC_MCD_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first call per device).
+int mcd_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return AFQMC_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return AFQMC_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return AFQMC_E_HIP;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
   return AFQMC_OK;
 }
 
-int afqmc_modified_cholesky(const double* eri, int32_t M, double delta, int32_t max_vectors,
-                            double* L_out, int32_t* n_vectors, int32_t* converged,
-                            void* workspace, size_t workspace_bytes, void* stream) {
-  if (!eri || M < 1 || !(delta > 0.0) || max_vectors < 0 || (max_vectors > 0 && !L_out) ||
-      !n_vectors || !workspace)
-    return AFQMC_E_ARG;
-  size_t need = 0;
-  afqmc_mcd_workspace_bytes(M, &need);
-  if (workspace_bytes < need) return AFQMC_E_NOMEM;
-  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return AFQMC_E_ARG;
+// The decomposition on a workspace laid out as afqmc_mcd_workspace_bytes says: the residual
+// diagonal D, the dead flags and the McdState.  k_mcd_init writes every element of the three
+// that a decomposition of this M reads, so a reused workspace needs no clearing.
+int mcd_run(const double* eri, int32_t M, double delta, int32_t max_vectors, double* L_out,
+            int32_t* n_vectors, int32_t* converged, void* workspace, hipStream_t st) {
   const size_t MM = (size_t)M * M;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   double* D = at<double>(workspace, 0);
   unsigned char* dead = at<unsigned char>(workspace, al256(MM * 8));
   McdState* state = at<McdState>(workspace, al256(MM * 8) + al256(MM));
@@ -1525,6 +1549,45 @@ int afqmc_modified_cholesky(const double* eri, int32_t M, double delta, int32_t 
   *n_vectors = h.count;
   if (converged) *converged = h.count < max_vectors || h.dmax < delta ? 1 : 0;
   return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int afqmc_mcd_workspace_bytes(int32_t M, size_t* bytes) {
+  if (M < 1 || !bytes) return AFQMC_E_ARG;
+  const size_t MM = (size_t)M * M;
+  *bytes = al256(MM * 8) + al256(MM) + al256(sizeof(McdState));
+  return AFQMC_OK;
+}
+
+int afqmc_modified_cholesky(const double* eri, int32_t M, double delta, int32_t max_vectors,
+                            double* L_out, int32_t* n_vectors, int32_t* converged,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  if (!eri || M < 1 || !(delta > 0.0) || max_vectors < 0 || (max_vectors > 0 && !L_out) ||
+      !n_vectors || !workspace)
+    return AFQMC_E_ARG;
+  size_t need = 0;
+  afqmc_mcd_workspace_bytes(M, &need);
+  if (workspace_bytes < need) return AFQMC_E_NOMEM;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return AFQMC_E_ARG;
+  return mcd_run(eri, M, delta, max_vectors, L_out, n_vectors, converged, workspace,
+                 reinterpret_cast<hipStream_t>(stream));
+}
+
+int afqmc_modified_cholesky_noalloc(const double* eri, int32_t M, double delta,
+                                    int32_t max_vectors, double* L_out, int32_t* n_vectors,
+                                    int32_t* converged, void* stream) {
+  if (!eri || M < 1 || !(delta > 0.0) || max_vectors < 0 || (max_vectors > 0 && !L_out) ||
+      !n_vectors)
+    return AFQMC_E_ARG;
+  if (M > AFQMC_MCD_NOALLOC_MAX_M) return AFQMC_E_UNSUPPORTED;
+  void* ws = nullptr;
+  const int rc = mcd_scratch(&ws);
+  if (rc) return rc;
+  return mcd_run(eri, M, delta, max_vectors, L_out, n_vectors, converged, ws,
+                 reinterpret_cast<hipStream_t>(stream));
 }
 
 int afqmc_mfma_peak(int32_t precision, void* out_dev, size_t out_bytes, void* hip_stream,
