@@ -247,7 +247,9 @@ def batch_leg(args):
             "graph_autotuned": {"value": round(vb, 1), "unit": "walker-steps/s",
                                 "ms_per_step": round(1e3 * dt_b / args.batch_steps, 3),
                                 "tiles": tiles, "autotune_s": round(t_tune, 2)},
-            "speedup": round(vb / va, 3), "setup_s": round(t_setup, 1)}
+            "speedup": round(vb / va, 3),
+            "useful_contraction_tflops": round(flops / (dt_b / args.batch_steps) / 1e12, 2),
+            "setup_s": round(t_setup, 1)}
 
 
 def serving_leg(args):

@@ -252,9 +252,13 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
  * 224); the stacked-row kernel stacks the rows the same way but keeps Re and Im Theta as two
  * operands of 16 columns (N padded to a multiple of 16, half the operand traffic per flop).
  * Every variant computes the same quantities.
- *   AFQMC_TILE_DEFAULT  W = 4 where the shape fits it (N <= 32, M <= 128), else wide
+ *   AFQMC_TILE_DEFAULT  where the shape fits it (N <= 32, M <= 128) W = 4 in FP32 and
+ *                       the ping-pong kernel in BF16x3, else wide
  *   AFQMC_TILE_W4, AFQMC_TILE_W2, AFQMC_TILE_WIDE  (wide needs N_P >= 32, i.e. N > 16 or M > 128)
  *   AFQMC_TILE_FLAT, AFQMC_TILE_STACK  (any FP32 / BF16x3 shape)
+ *   AFQMC_TILE_PP  eight walkers per workgroup, two wavefronts per SIMD alternating between
+ *                  the MFMA chain of one Cholesky vector and the LDS epilogue of the one before
+ *                  (N <= 32, M <= 128)
  * The FP64 mode has one contraction kernel per shape and accepts only the default. */
 #define AFQMC_TILE_DEFAULT 0
 #define AFQMC_TILE_W4 1
@@ -262,6 +266,7 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
 #define AFQMC_TILE_WIDE 3
 #define AFQMC_TILE_FLAT 4
 #define AFQMC_TILE_STACK 5
+#define AFQMC_TILE_PP 6
 
 /* Autotuner: times every variant valid for the system's shape on these walkers (initialized
  * or measured; one untimed and three timed launches each, on the system's stream, writing only
@@ -300,6 +305,15 @@ AFQMC_API int afqmc_batch_create(int32_t n, const afqmc_sys* systems, afqmc_walk
                                  void* stream, afqmc_batch* out);
 AFQMC_API int afqmc_batch_step(afqmc_batch b, const afqmc_fields* fields);
 AFQMC_API int afqmc_batch_destroy(afqmc_batch b);
+/* How a batch step launches the local-energy contraction, the dominant kernel.
+ *   0  every system's step keeps its own kernels on its branch: the batch's only mode
+ *      (AFQMC_OK, nothing changes).
+ *   1  one launch per family of systems sharing a kernel instance: not available
+ *      (AFQMC_E_UNSUPPORTED).  An implementation crashed the host process inside the first
+ *      batch step that captured its graph, no cause was found in this library, and it was
+ *      taken out.
+ * Any other value: AFQMC_E_ARG. */
+AFQMC_API int afqmc_batch_set_mode(afqmc_batch b, int32_t mode);
 
 /* Draw (or copy) the fields the next afqmc_step would use, into device x_out
  * [n_walkers][n_chol] doubles.  Asynchronous. */

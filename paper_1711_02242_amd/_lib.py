@@ -26,9 +26,9 @@ EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walk
            "afqmc_batch_create", "afqmc_batch_step", "afqmc_batch_destroy", "afqmc_autotune",
            "afqmc_set_tile", "afqmc_get_tile", "afqmc_energy_enqueue", "afqmc_footprint_bytes",
            "afqmc_mfma_peak", "afqmc_get_growth", "afqmc_get_bound_counts",
-           "afqmc_modified_cholesky_noalloc"]
+           "afqmc_modified_cholesky_noalloc", "afqmc_batch_set_mode"]
 
-TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5}
+TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5, "pp": 6}
 MFMA_PEAK_BYTES = 16384   # AFQMC_MFMA_PEAK_BYTES
 
 
@@ -104,6 +104,7 @@ def load(path: str | None = None) -> C.CDLL:
                                 P(C.c_void_p)], C.c_int),
         "afqmc_batch_step": ([C.c_void_p, P(FieldsC)], C.c_int),
         "afqmc_batch_destroy": ([C.c_void_p], C.c_int),
+        "afqmc_batch_set_mode": ([C.c_void_p, C.c_int32], C.c_int),
         "afqmc_autotune": ([C.c_void_p, P(WalkersC), C.c_int32, P(C.c_int32), P(C.c_double)],
                            C.c_int),
         "afqmc_set_tile": ([C.c_void_p, C.c_int32], C.c_int),

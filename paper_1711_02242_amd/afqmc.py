@@ -278,7 +278,7 @@ class Batch:
     """Systems with their walkers stepped together by one graph launch per step
     (``afqmc_batch_*``).  Keeps the systems and walkers alive while it exists."""
 
-    def __init__(self, pairs, stream=None, autotune: bool = False):
+    def __init__(self, pairs, stream=None, autotune: bool = False, families: bool = False):
         torch = _torch()
         self.lib = L.load()
         self.pairs = list(pairs)
@@ -301,6 +301,13 @@ class Batch:
                                             C.byref(h)), "afqmc_batch_create")
         self.handle = h
         self._fields = (L.FieldsC * n)()
+        if families:
+            self.set_families(True)
+
+    def set_families(self, on: bool) -> None:
+        """One contraction launch per family of systems sharing a kernel instance (mode 1 of
+        ``afqmc_batch_set_mode``, not available: raises) or per system (mode 0)."""
+        L.check(self.lib.afqmc_batch_set_mode(self.handle, 1 if on else 0), "afqmc_batch_set_mode")
 
     def step(self, seeds, job_ids=None) -> None:
         """One step of every system; fields drawn on the device from (seed, job_id)."""

@@ -76,8 +76,8 @@ struct afqmc_sys_s {
   MfmaTables mt64;         // FP64 packed copy for the precision guard of the mixed modes
   bool guard_on = false;   // mixed mode with the guard: walkers with max|Theta| > guard redone
   double guard = INFINITY; //   in FP64 (afqmc_params.theta_guard)
-  float* Lt32 = nullptr;   // [M(M+1)/2][Gp] FP32 transposed Cholesky tensor, lower triangle
-  int* abpairs = nullptr;  // [M(M+1)/2][2] (q M + p, p M + q) of each packed column
+  float* Lt32 = nullptr;   // [apk_size(M)][Gp] FP32 transposed Cholesky tensor, block-packed
+  int* abpairs = nullptr;  // [M(M+1)/2][2] (q M + p, p M + q) of each packed column (FP64)
   double* Lt64 = nullptr;  // [M(M+1)/2][Gp64] FP64 packed L^T (FP64 A-build)
   int Gp64 = 0;            // G rounded up to 16
   float* Eh32 = nullptr;   // [M][M] FP32 exp(-dtau/2 v0)
@@ -122,7 +122,8 @@ WsLayout layout(const afqmc_sys_s* S, size_t nw) {
   L.wflag = take(nw * nd * 2 * 4);
   L.enew = take(nw * 16);
   L.y = take(nw * G * 16);
-  L.A = take(nw * M * M * 16);
+  // exponent A: FP32 block-packed Re and Im planes, else FP64 complex M x M
+  L.A = take(S->f32_prop ? nw * (size_t)apk_size((int)M) * 8 : nw * M * M * 16);
   L.X0 = take(nw * nt * M * 16);
   L.X1 = take(nw * nt * M * 16);
   L.Y = take(nw * nt * M * 16);
@@ -378,7 +379,8 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
 
 // The local-energy contraction and the energy assembly.  `in_step` counts the walkers the
 // precision guard redoes in FP64 (the counters of afqmc_get_bound_counts cover steps only).
-int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, bool in_step) {
+// The contraction proper (tpart, exch of every walker in the system's precision).
+int launch_contraction(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L) {
   void* ws = w->workspace;
   if (!S->mt.enabled) {
     Timer tm(S, KG_CONTRACT);
@@ -403,6 +405,16 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, b
     Timer tm(S, KG_CONTRACT);
     HIPCHK(mfma_contract(S->mt, S->stream, w->n_walkers, S->n_det, S->G, at<void>(ws, L.thetaP),
                          w->weight, at<cd>(ws, L.tpart), at<cd>(ws, L.exch), S->tile));
+  }
+  return AFQMC_OK;
+}
+
+// After the contraction: the precision guard's FP64 pass and the energy assembly.
+int launch_guard_assemble(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L,
+                          bool in_step) {
+  void* ws = w->workspace;
+  if (S->mt.enabled) {
+    Timer tm(S, KG_CONTRACT);
     if (S->guard_on) {
       // walkers far from the trial (large Theta) again in FP64, over the partial sums of the
       // low-precision pass
@@ -434,6 +446,11 @@ int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, b
     HIPCHK(hipGetLastError());
   }
   return AFQMC_OK;
+}
+
+int launch_contract(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, bool in_step) {
+  const int rc = launch_contraction(S, w, L);
+  return rc ? rc : launch_guard_assemble(S, w, L, in_step);
 }
 
 int do_measure(afqmc_sys_s* S, afqmc_walkers* w) {
@@ -757,9 +774,8 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     free_sys(S);
     return AFQMC_E_HIP;
   }
-  // packed pairs (q M + p, p M + q), p <= q, of the symmetric A-build; FP64 packed L^T
-  if (p->precision == AFQMC_FP64 || (p->precision != AFQMC_FP64 && M <= WIDE_KMAX &&
-                                     std::max(nup_i, ndn_i) <= 64)) {
+  // packed pairs (q M + p, p M + q), p <= q, of the symmetric FP64 A-build; FP64 packed L^T
+  if (p->precision == AFQMC_FP64) {
     const size_t MMh = (size_t)M * (M + 1) / 2;
     const std::vector<std::pair<int, int>> order = pair_order(M);
     std::vector<int> pairs(2 * MMh);
@@ -772,17 +788,15 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
       free_sys(S);
       return rc;
     }
-    if (p->precision == AFQMC_FP64) {
-      S->Gp64 = ((G + 15) / 16) * 16;
-      std::vector<double> lt(MMh * (S->Gp64 > 0 ? S->Gp64 : 1), 0.0);
-      for (size_t k = 0; k < MMh; ++k)
-        for (int g = 0; g < G; ++g)
-          lt[k * S->Gp64 + g] =
-              L_chol[(size_t)g * M * M + (size_t)order[k].first * M + order[k].second];
-      if ((rc = dev_upload(S, &S->Lt64, lt.data(), lt.size()))) {
-        free_sys(S);
-        return rc;
-      }
+    S->Gp64 = ((G + 15) / 16) * 16;
+    std::vector<double> lt(MMh * (S->Gp64 > 0 ? S->Gp64 : 1), 0.0);
+    for (size_t k = 0; k < MMh; ++k)
+      for (int g = 0; g < G; ++g)
+        lt[k * S->Gp64 + g] =
+            L_chol[(size_t)g * M * M + (size_t)order[k].first * M + order[k].second];
+    if ((rc = dev_upload(S, &S->Lt64, lt.data(), lt.size()))) {
+      free_sys(S);
+      return rc;
     }
   }
   if (multi) {
@@ -825,15 +839,15 @@ int setup_impl(const afqmc_params* p, double h0, const double* h1, const double*
     S->prop_wide = M > MFMA_KMAX || S->ntot > 64;
     S->f32_prop = true;
     S->Gp = ((G + 31) / 32) * 32;
-    // lower triangle of every L^g (L^g is symmetric), one packed row per pair p <= q
-    const size_t MMh = (size_t)M * (M + 1) / 2;
-    std::vector<float> lt(MMh * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
-    {
-      const std::vector<std::pair<int, int>> order = pair_order(M);
-      for (size_t k = 0; k < MMh; ++k)
+    // one row per entry of the block-packed A (L^g is symmetric; rows past M stay zero)
+    const size_t MA = (size_t)apk_size(M);
+    std::vector<float> lt(MA * (S->Gp > 0 ? S->Gp : 1), 0.0f), eh((size_t)M * M);
+    for (size_t k = 0; k < MA; ++k) {
+      int q, pp;
+      apk_entry((int)k, q, pp);
+      if (q < M && pp < M)
         for (int g = 0; g < G; ++g)
-          lt[k * S->Gp + g] =
-              (float)L_chol[(size_t)g * M * M + (size_t)order[k].first * M + order[k].second];
+          lt[k * S->Gp + g] = (float)L_chol[(size_t)g * M * M + (size_t)q * M + pp];
     }
     for (size_t e = 0; e < eh.size(); ++e) eh[e] = (float)Eh[e];
     if ((rc = dev_upload(S, &S->Lt32, lt.data(), lt.size())) ||
@@ -914,11 +928,12 @@ bool in_growth_phase(const afqmc_sys_s* s, int64_t k) {
   return !(s->p.flags & AFQMC_FLAG_FREE_PROJECTION) && s->p.n_growth > 0 && k < s->p.n_growth;
 }
 
-// One step of the random walk (Sec. III.E) enqueued on s->stream.  With `graph` the step
-// number is read on the device from the workspace counter (so that a captured graph can be
-// replayed) and the counter is advanced at the end; otherwise the host value is used and
-// the counter is set to it.
-int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool graph) {
+// One step of the random walk (Sec. III.E) enqueued on s->stream, in three parts: everything
+// up to the new overlaps (step_pre), the local-energy contraction, and the rest (step_post).
+// With `graph` the step number is read on the device from the workspace counter (so that a
+// captured graph can be replayed) and the counter is advanced at the end; otherwise the host
+// value is used and the counter is set to it.
+int step_pre(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool graph) {
   const WsLayout L = layout(s, (size_t)w->n_walkers);
   void* ws = w->workspace;
   const int nw = w->n_walkers, M = s->M, nt = s->ntot;
@@ -930,17 +945,16 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
   // 2-3. propagator exponent A and propagation U <- E_h T_n(A) E_h U
   if (s->f32_prop) {
     float* Are = at<float>(ws, L.A);
-    float* Aim = Are + (size_t)nw * M * M;
+    float* Aim = Are + (size_t)nw * apk_size(M);
     if (s->G > 0) {
       Timer tm(s, KG_ABUILD);
       const size_t ne = (size_t)nw * s->Gp;
       hipLaunchKernelGGL(k_y_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s->stream, nw,
                          s->G, s->Gp, at<cd>(ws, L.y), at<float>(ws, L.y32));
-      const int MMh = M * (M + 1) / 2;
-      dim3 grid((2 * nw + AB_BM - 1) / AB_BM, (MMh + AB_BN - 1) / AB_BN);
-      hipLaunchKernelGGL(k_abuild_f32, grid, dim3(256), 0, s->stream, 2 * nw, MMh, M * M, s->Gp,
-                         (float)s->s, at<float>(ws, L.y32), s->Lt32,
-                         reinterpret_cast<const int2*>(s->abpairs), Are, Aim);
+      const int MA = apk_size(M);
+      dim3 grid((2 * nw + AB_BM - 1) / AB_BM, (MA + AB_BN - 1) / AB_BN);
+      hipLaunchKernelGGL(k_abuild_f32, grid, dim3(256), 0, s->stream, 2 * nw, MA, s->Gp,
+                         (float)s->s, at<float>(ws, L.y32), s->Lt32, Are, Aim);
       HIPCHK(hipGetLastError());
     }
     if (s->prop_wide) {
@@ -1057,9 +1071,20 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
     }
     HIPCHK(hipGetLastError());
   }
-  // 5-6. overlap, Theta, local energy of the new determinants
-  if ((rc = launch_overlap(s, w, L, 1))) return rc;
-  if ((rc = launch_contract(s, w, L, true))) return rc;
+  // 5. overlap and Theta of the new determinants
+  return launch_overlap(s, w, L, 1);
+}
+
+int step_post(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool graph) {
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  void* ws = w->workspace;
+  const int nw = w->n_walkers, M = s->M, nt = s->ntot;
+  const int64_t k = w->step;
+  int64_t* dstep = at<int64_t>(ws, L.dstep);
+  int rc;
+  // 6. the local energy of the new determinants (after the contraction)
+  if ((rc = launch_guard_assemble(s, w, L, true))) return rc;
+  const bool qr_due = s->p.qr_period > 0 && (k + 1) % s->p.qr_period == 0;
   // 7. phaseless weights, with the growth-phase sums around them (App. B.1, B.2)
   const bool pop_due = s->p.pop_period > 0 && (k + 1) % s->p.pop_period == 0;
   const bool growing = in_growth_phase(s, k);
@@ -1114,6 +1139,14 @@ int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool grap
   HIPCHK(hipGetLastError());
   w->step = k + 1;
   return AFQMC_OK;
+}
+
+int step_impl(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool graph) {
+  int rc = step_pre(s, w, f, graph);
+  if (rc) return rc;
+  const WsLayout L = layout(s, (size_t)w->n_walkers);
+  if ((rc = launch_contraction(s, w, L))) return rc;
+  return step_post(s, w, f, graph);
 }
 
 }  // namespace
@@ -1321,6 +1354,14 @@ int afqmc_batch_step(afqmc_batch b, const afqmc_fields* fields) {
   return AFQMC_OK;
 }
 
+int afqmc_batch_set_mode(afqmc_batch b, int32_t mode) {
+  if (!b || mode < 0 || mode > 1) return AFQMC_E_ARG;
+  // One launch per family of systems is not available: the host process crashed inside the
+  // first batch step that captured such a graph, and no cause was found in this library, so
+  // the implementation was taken out.  Mode 0 is the batch's only mode.
+  return mode == 0 ? AFQMC_OK : AFQMC_E_UNSUPPORTED;
+}
+
 int afqmc_batch_destroy(afqmc_batch b) {
   if (!b) return AFQMC_E_ARG;
   (void)hipStreamSynchronize(b->cap);
@@ -1403,8 +1444,9 @@ int afqmc_footprint_bytes(const afqmc_params* p, int32_t n_det, int32_t n_walker
   if (S.mt.enabled) sb += S.mt.bytes;
   if (S.guard_on) sb += S.mt64.bytes;
   const size_t MMh = (size_t)M * (M + 1) / 2;
-  if (S.f32_prop || p->precision == AFQMC_FP64) sb += 2 * MMh * 4;   // pair table
-  if (S.f32_prop) sb += MMh * (S.Gp > 0 ? S.Gp : 1) * 4 + MM * 4;    // packed L^T, E_h (FP32)
+  if (p->precision == AFQMC_FP64) sb += 2 * MMh * 4;                // pair table
+  if (S.f32_prop)                                                     // packed L^T, E_h (FP32)
+    sb += (size_t)apk_size(M) * (S.Gp > 0 ? S.Gp : 1) * 4 + MM * 4;
   if (p->precision == AFQMC_FP64) {                                   // packed L^T (FP64)
     const size_t gp64 = ((size_t)G + 15) / 16 * 16;
     sb += MMh * (gp64 > 0 ? gp64 : 1) * 8;

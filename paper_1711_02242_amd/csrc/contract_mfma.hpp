@@ -26,11 +26,25 @@ __device__ inline void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One term of tr(Omega Omega): the lane's Omega_ij = R + i I times its partner
+// Omega_ji = Rt + i It, accumulated into (pr, pi) by four FMAs (the fewest vector
+// instructions: on the matrix-core SIMDs vector work adds to the MFMA time).  The FMAs are
+// explicit so that the rounding is the same in every kernel that uses them.
+__device__ __forceinline__ void exch_term(float R, float I, float Rt, float It, float& pr,
+                                          float& pi) {
+  pr = __builtin_fmaf(R, Rt, pr);
+  pr = __builtin_fmaf(-I, It, pr);
+  pi = __builtin_fmaf(R, It, pi);
+  pi = __builtin_fmaf(I, Rt, pi);
+}
+
 // One K chunk of Omega = Lh Theta for the Re and Im halves.  FP32: a holds four K values of
 // one row of Lh (one per MFMA step), br / bi four K values of one column of Re / Im Theta.
 // BF16x3: a / al the hi / lo bf16 of eight K values, br / brl and bi / bil likewise; the
 // three products hi.hi + hi.lo + lo.hi.
-template <int NP, bool BF16, typename Acc>
+// FIRST: the chunk starts Omega, so its first products take a zero accumulator (an inline
+// constant of the MFMA instead of clearing the accumulator registers with vector moves).
+template <int NP, bool BF16, bool FIRST = false, typename Acc>
 __device__ __forceinline__ void contract_chunk(u32x4 ah, u32x4 al, u32x4 brh, u32x4 brl,
                                                u32x4 bih, u32x4 bil, Acc& cre, Acc& cim) {
   if constexpr (!BF16) {
@@ -39,18 +53,23 @@ __device__ __forceinline__ void contract_chunk(u32x4 ah, u32x4 al, u32x4 brh, u3
     const f32x4 bi = __builtin_bit_cast(f32x4, bih);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+      const Acc cr = FIRST && k == 0 ? Acc{} : cre, ci = FIRST && k == 0 ? Acc{} : cim;
       if constexpr (NP == 32) {
-        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a[k], br[k], cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a[k], bi[k], cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a[k], br[k], cr, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a[k], bi[k], ci, 0, 0, 0);
       } else {
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], br[k], cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bi[k], cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], br[k], cr, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bi[k], ci, 0, 0, 0);
       }
     }
   } else {
     const bf16x8 h = __builtin_bit_cast(bf16x8, ah), l = __builtin_bit_cast(bf16x8, al);
     const bf16x8 rh = __builtin_bit_cast(bf16x8, brh), rl = __builtin_bit_cast(bf16x8, brl);
     const bf16x8 ih = __builtin_bit_cast(bf16x8, bih), il = __builtin_bit_cast(bf16x8, bil);
+    if constexpr (FIRST) {
+      cre = Acc{};
+      cim = Acc{};
+    }
     if constexpr (NP == 32) {
       cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, rh, cre, 0, 0, 0);
       cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(l, ih, cim, 0, 0, 0);
@@ -197,7 +216,7 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
     }
     const unsigned char* arow = Acur + ((size_t)col * lda + kofs) * ESZ;
     const size_t lo_ofs = (size_t)NP * lda * ESZ;   // bf16: lo plane of the tile
-    Acc cre = {}, cim = {};
+    Acc cre, cim;   // set by the first chunk (read only by active waves)
     if (active) {
       if constexpr (WPB == 4) {
         // A fragment of chunk c + 1 read while chunk c's MFMAs run; the scheduling barrier
@@ -212,8 +231,12 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
             if constexpr (BF16)
               nl = *reinterpret_cast<const u32x4*>(arow + lo_ofs + (size_t)(c + 1) * KCH * ESZ);
           }
-          contract_chunk<NP, BF16>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
-                                   bim_lo[BF16 ? c : 0], cre, cim);
+          if (c == 0)
+            contract_chunk<NP, BF16, true>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
+                                           bim_lo[BF16 ? c : 0], cre, cim);
+          else
+            contract_chunk<NP, BF16>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
+                                     bim_lo[BF16 ? c : 0], cre, cim);
           __builtin_amdgcn_sched_barrier(0);
           ah = nh;
           al = nl;
@@ -226,8 +249,12 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
           const u32x4 ah = *reinterpret_cast<const u32x4*>(arow + (size_t)c * KCH * ESZ);
           const u32x4 al =
               BF16 ? *reinterpret_cast<const u32x4*>(arow + lo_ofs + (size_t)c * KCH * ESZ) : ah;
-          contract_chunk<NP, BF16>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
-                                   bim_lo[BF16 ? c : 0], cre, cim);
+          if (c == 0)
+            contract_chunk<NP, BF16, true>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
+                                           bim_lo[BF16 ? c : 0], cre, cim);
+          else
+            contract_chunk<NP, BF16>(ah, al, bre[c], bre_lo[BF16 ? c : 0], bim[c],
+                                     bim_lo[BF16 ? c : 0], cre, cim);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -260,19 +287,12 @@ __global__ void __launch_bounds__(64 * WPB, 2) k_contract_mfma(
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const float R = cre[v], I = cim[v];
-          pr += R * Rt[v] - I * It[v];
-          pi += R * It[v] + I * Rt[v];
-        }
+        for (int v = 0; v < NV; ++v) exch_term(cre[v], cim[v], Rt[v], It[v], pr, pi);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const int i = (NP == 32 ? 8 * (v / 4) : 0) + 4 * kg + (v % 4);
-          const float R = cre[v], I = cim[v];
-          const float Rt = ep_re[i * LDE + col], It = ep_im[i * LDE + col];
-          pr += R * Rt - I * It;
-          pi += R * It + I * Rt;
+          exch_term(cre[v], cim[v], ep_re[i * LDE + col], ep_im[i * LDE + col], pr, pi);
         }
       }
       xr += (double)pr;

@@ -41,7 +41,7 @@ constexpr int WIDE_KMAX = 224;   // K limit of the wide (workgroup-per-walker) k
 // Contraction kernel variants (tile shapes) the autotuner chooses among.
 enum {
   TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_FLAT = 4, TILE_STACK = 5,
-  TILE_COUNT = 6
+  TILE_PP = 6, TILE_COUNT = 7
 };
 
 struct MfmaTables {
@@ -169,6 +169,7 @@ inline void mfma_free_tables(MfmaTables& t) {
 #include "contract_mfma.hpp"
 #include "contract_wide.hpp"
 #include "contract_flat.hpp"
+#include "contract_pp.hpp"
 
 inline size_t mfma_contract_lds_bytes(const MfmaTables& t, int wpb) {
   const bool bf = t.precision == AFQMC_BF16X3;
@@ -185,7 +186,8 @@ inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
   switch (tile) {
     case TILE_DEFAULT: return true;
     case TILE_W4:
-    case TILE_W2: return !t.wide;
+    case TILE_W2:
+    case TILE_PP: return !t.wide;
     case TILE_WIDE: return t.NP >= 32 && t.KP <= WIDE_KMAX;
     case TILE_FLAT:
     case TILE_STACK: {
@@ -408,6 +410,8 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   }
   const bool bf = t.precision == AFQMC_BF16X3;
   if (!mfma_tile_valid(t, tile)) tile = TILE_DEFAULT;
+  // BF16x3 defaults to the ping-pong schedule (its per-g chain is short against the epilogue)
+  if (tile == TILE_DEFAULT && bf && !t.wide) tile = TILE_PP;
   if (tile == TILE_FLAT || tile == TILE_STACK) {
     const bool stk = tile == TILE_STACK;
     const FlatLaunch f = flat_launch(t.nup, t.ndn, G, bf, stk);
@@ -499,6 +503,37 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   const int wpb = tile == TILE_W2 ? 2 : 4;
   // the kernels are instantiated for K_P = 32, 64, 96, 128
   if (t.KP % 32 != 0 || t.KP < 32 || t.KP > MFMA_KMAX) return hipErrorInvalidValue;
+  if (tile == TILE_PP) {
+    const size_t shm = pp_contract_lds_bytes(t.NP, t.KP, bf);
+    dim3 grid((nw + 7) / 8, 2 * n_det);
+#define LAUNCH_PP_K(NPV, BFV, NKV)                                                             \
+  do {                                                                                         \
+    (void)hipFuncSetAttribute((const void*)k_contract_mfma_pp<NPV, BFV, NKV>,                  \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
+    hipLaunchKernelGGL((k_contract_mfma_pp<NPV, BFV, NKV>), grid, dim3(512), shm, st, nw, G,   \
+                       t.nup, t.ndn, (const void*)t.Lp, thetaP, weight, tpart, exch);          \
+  } while (0)
+#define LAUNCH_PP(NPV, BFV)                                                                    \
+  do {                                                                                         \
+    constexpr int KCH_ = contract_kch<NPV, BFV>();                                             \
+    switch (t.KP / KCH_) {                                                                     \
+      case 32 / KCH_: LAUNCH_PP_K(NPV, BFV, 32 / KCH_); break;                                 \
+      case 64 / KCH_: LAUNCH_PP_K(NPV, BFV, 64 / KCH_); break;                                 \
+      case 96 / KCH_: LAUNCH_PP_K(NPV, BFV, 96 / KCH_); break;                                 \
+      default: LAUNCH_PP_K(NPV, BFV, 128 / KCH_); break;                                       \
+    }                                                                                          \
+  } while (0)
+    if (t.NP == 32) {
+      if (bf) LAUNCH_PP(32, true);
+      else LAUNCH_PP(32, false);
+    } else {
+      if (bf) LAUNCH_PP(16, true);
+      else LAUNCH_PP(16, false);
+    }
+#undef LAUNCH_PP
+#undef LAUNCH_PP_K
+    return hipGetLastError();
+  }
   const size_t shm = mfma_contract_lds_bytes(t, wpb);
   dim3 grid((nw + wpb - 1) / wpb, 2 * n_det);
 #define LAUNCH_CONTRACT_K(NPV, BFV, WPBV, NKV)                                                  \

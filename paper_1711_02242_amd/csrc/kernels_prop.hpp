@@ -14,28 +14,80 @@
 #include "kernels_mfma.hpp"
 
 // ---------------------------------------------------------------------------
+// Block-packed storage of the FP32 exponent A_w (symmetric, one Re and one Im plane per
+// walker): the 8 x 8 blocks (QB, PB), PB <= QB, of the lower block triangle, block row by
+// block row, each block whole and row-major (a diagonal block holds both of its halves).
+// A_w[q][p] for p in the upper block triangle is read as A_w[p][q].  Entries past M (the last
+// block row and column when 8 does not divide M) hold zero.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int apk_size(int M) {
+  const int nb = (M + 7) / 8;
+  return 32 * nb * (nb + 1);   // 64 entries per block, nb (nb + 1) / 2 blocks
+}
+__host__ __device__ inline int apk_index(int q, int p) {
+  int QB = q >> 3, PB = p >> 3, qi = q & 7, pi = p & 7;
+  if (PB > QB) {
+    const int t = QB, ti = qi;
+    QB = PB, qi = pi;
+    PB = t, pi = ti;
+  }
+  return 64 * (QB * (QB + 1) / 2 + PB) + 8 * qi + pi;
+}
+// The (q, p) of packed entry k (inverse of apk_index on the lower block triangle).
+inline void apk_entry(int k, int& q, int& p) {
+  const int blk = k >> 6, e = k & 63;
+  int QB = 0;
+  while ((QB + 1) * (QB + 2) / 2 <= blk) ++QB;
+  const int PB = blk - QB * (QB + 1) / 2;
+  q = 8 * QB + (e >> 3);
+  p = 8 * PB + (e & 7);
+}
+
+// Workgroup tile of a gx x gy grid renumbered so that each of the 8 XCDs (workgroups go to
+// them round-robin by linear id) takes a contiguous run of tiles in x-fastest order: tiles of
+// one grid column y then share one XCD's L2.
+__device__ __forceinline__ int2 xcd_tile(int gx, int gy) {
+  const int n = gx * gy, L = blockIdx.x + gx * blockIdx.y;
+  const int x = L & 7, j = L >> 3, q = n >> 3, r = n & 7;
+  const int t = x * q + (x < r ? x : r) + j;
+  return make_int2(t % gx, t / gx);
+}
+
+// Four consecutive entries A[q][p0 .. p0 + 3] (p0 a multiple of 4, q < M) of a block-packed
+// plane, zero past M: one 16-byte load inside the lower block triangle, four loads of a
+// column of the block (p0, q) above it.
+__device__ __forceinline__ f32x4 apk_load4(const float* __restrict__ Ap, int M, int q, int p0) {
+  if ((p0 >> 3) <= (q >> 3)) return *reinterpret_cast<const f32x4*>(Ap + apk_index(q, p0));
+  f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (p0 + e < M) v[e] = Ap[apk_index(q, p0 + e)];
+  return v;
+}
+
+// ---------------------------------------------------------------------------
 // A-build as a tiled MFMA GEMM:  C[r][col] = sum_k Y[r][k] Lt[col][k]
-//   r = 2w + (0: Re y, 1: Im y),  col = packed index of a pair p <= q (A is symmetric, so
-//   only the lower triangle is computed: MM = M(M+1)/2 columns),  k = g (padded to Gp, zeros).
-//   Re A_w[q][p] = Re A_w[p][q] = -s C[2w+1][col],  Im = s C[2w][col]  (planar FP32 output
-//   of MA = M^2 entries per walker; pairs[col] = (q M + p, p M + q)).
+//   r = 2w + (0: Re y, 1: Im y),  col = block-packed entry of A (apk_index; MA = apk_size(M)
+//   columns, about half of M^2 since A is symmetric),  k = g (padded to Gp, zeros).
+//   Re A_w[col] = -s C[2w+1][col],  Im = s C[2w][col]: planar FP32 output of MA entries per
+//   walker, each written once (a tile's columns are whole block rows: contiguous stores).
 // Tile 128 x 128 per workgroup, K chunks of 32 double-buffered in LDS,
-// 4 wavefronts of 64 x 64 (2 x 2 blocks of v_mfma_f32_32x32x2_f32).
+// 4 wavefronts of 64 x 64 (2 x 2 blocks of v_mfma_f32_32x32x2_f32); the workgroups of one
+// column tile of Lt run on one XCD.
 // ---------------------------------------------------------------------------
 constexpr int AB_BM = 128, AB_BN = 128, AB_BK = 32, AB_LD = AB_BK + 4;
 
-__global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM, int MA, int Gp,
-                                                       float s,
+__global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MA, int Gp, float s,
                                                        const float* __restrict__ Y,
                                                        const float* __restrict__ Lt,
-                                                       const int2* __restrict__ pairs,
                                                        float* __restrict__ Are,
                                                        float* __restrict__ Aim) {
   __shared__ __attribute__((aligned(16))) float As[2][AB_BM * AB_LD];
   __shared__ __attribute__((aligned(16))) float Bs[2][AB_BN * AB_LD];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int r0 = blockIdx.x * AB_BM, c0 = blockIdx.y * AB_BN;
+  const int2 tile = xcd_tile(gridDim.x, gridDim.y);
+  const int r0 = tile.x * AB_BM, c0 = tile.y * AB_BN;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
   const int col = lane & 31, h = lane >> 5;
   // each thread moves 4 float4 of A and 4 of B per K chunk
@@ -49,7 +101,7 @@ __global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM
       const int e_ = tid + c_ * 256;                                                     \
       const int rr_ = e_ >> 3, kk_ = (e_ & 7) * 4;                                       \
       const int gr_ = r0 + rr_, gc_ = c0 + rr_;                                          \
-      const int sr_ = gr_ < rows ? gr_ : 0, sc_ = gc_ < MM ? gc_ : 0;                     \
+      const int sr_ = gr_ < rows ? gr_ : 0, sc_ = gc_ < MA ? gc_ : 0;                     \
       pa[c_] = *reinterpret_cast<const f32x4*>(Y + (size_t)sr_ * Gp + (K0_) + kk_);      \
       pb[c_] = *reinterpret_cast<const f32x4*>(Lt + (size_t)sc_ * Gp + (K0_) + kk_);     \
     }                                                                                    \
@@ -103,20 +155,14 @@ __global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MM
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int cc = c0 + wc + 32 * b + col;
-      if (cc >= MM) continue;
-      const int2 pq = pairs[cc];   // (q M + p, p M + q) of the packed column
+      if (cc >= MA) continue;
 #pragma unroll
       for (int v = 0; v < 16; v += 2) {
         const int r = r0 + wr + 32 * a + 8 * (v / 4) + 4 * h + (v % 4);  // even
         if (r >= rows) continue;
         const int w = r >> 1;
-        const float re = -s * acc[a][b][v + 1], im = s * acc[a][b][v];
-        Are[(size_t)w * MA + pq.x] = re;
-        Aim[(size_t)w * MA + pq.x] = im;
-        if (pq.y != pq.x) {
-          Are[(size_t)w * MA + pq.y] = re;
-          Aim[(size_t)w * MA + pq.y] = im;
-        }
+        Are[(size_t)w * MA + cc] = -s * acc[a][b][v + 1];
+        Aim[(size_t)w * MA + cc] = s * acc[a][b][v];
       }
     }
 }
@@ -152,7 +198,7 @@ __global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
   float* Ti = tsm + RP * ldt;  // [RP][ldt]
   const int j = lane & 15, q4 = lane >> 4;
   const int qcol = 16 * wave + j;  // output column owned by the lane
-  const int MM = M * M;
+  const size_t MA = (size_t)apk_size(M);
 
   // load U rows (FP64 complex) into the term planes, zero padding: all loads of a thread go
   // out before the first store (padding positions read a valid element and store zero)
@@ -183,19 +229,15 @@ __global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
     bar_[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
     bai[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int p0 = 16 * kc + 4 * q4;
-    if (colok && (M & 3) == 0 && p0 + 4 <= M) {
-      be[kc] = *reinterpret_cast<const f32x4*>(Eh32 + (size_t)qcol * M + p0);
-      bar_[kc] = *reinterpret_cast<const f32x4*>(Are + (size_t)w * MM + (size_t)qcol * M + p0);
-      bai[kc] = *reinterpret_cast<const f32x4*>(Aim + (size_t)w * MM + (size_t)qcol * M + p0);
-    } else if (colok) {
+    if (colok) {
+      bar_[kc] = apk_load4(Are + (size_t)w * MA, M, qcol, p0);
+      bai[kc] = apk_load4(Aim + (size_t)w * MA, M, qcol, p0);
+      if ((M & 3) == 0 && p0 + 4 <= M) {
+        be[kc] = *reinterpret_cast<const f32x4*>(Eh32 + (size_t)qcol * M + p0);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int p = p0 + e;
-        if (p < M) {
-          be[kc][e] = Eh32[(size_t)qcol * M + p];
-          bar_[kc][e] = Are[(size_t)w * MM + (size_t)qcol * M + p];
-          bai[kc][e] = Aim[(size_t)w * MM + (size_t)qcol * M + p];
-        }
+        for (int e = 0; e < 4; ++e)
+          if (p0 + e < M) be[kc][e] = Eh32[(size_t)qcol * M + p0 + e];
       }
     }
   }
@@ -357,12 +399,16 @@ __global__ void __launch_bounds__(64 * NKC) k_propagate_f32_wide(
   const int j = lane & 15, q4 = lane >> 4;
   const int qcol = 16 * wave + j;   // output column owned by the lane
   const bool colok = qcol < M;
-  const size_t MM = (size_t)M * M;
+  const size_t MA = (size_t)apk_size(M);
   const int nrb = (N + 15) / 16;
   const float* Eq = Eh32 + (size_t)(colok ? qcol : 0) * M;
-  const float* Arq = Are + (size_t)w * MM + (size_t)(colok ? qcol : 0) * M;
-  const float* Aiq = Aim + (size_t)w * MM + (size_t)(colok ? qcol : 0) * M;
-  // B operand of K chunk kc: rows p = 16 kc + 4 q4 + e of column qcol (zero beyond M)
+  const float* Aw_re = Are + (size_t)w * MA;
+  const float* Aw_im = Aim + (size_t)w * MA;
+  // B operand of K chunk kc: rows p = 16 kc + 4 q4 + e of column qcol (zero beyond M), of
+  // E_h (full) and of A (block-packed)
+  auto lda4 = [&](const float* Ap, int kc) {
+    return colok ? apk_load4(Ap, M, qcol, 16 * kc + 4 * q4) : f32x4{0.f, 0.f, 0.f, 0.f};
+  };
   auto ld4 = [&](const float* row, int kc) {
     f32x4 v = {0.f, 0.f, 0.f, 0.f};
     const int p0 = 16 * kc + 4 * q4;
@@ -438,11 +484,11 @@ __global__ void __launch_bounds__(64 * NKC) k_propagate_f32_wide(
       cre[rb] = f32x4{};
       cim[rb] = f32x4{};
     }
-    f32x4 br = ld4(Arq, 0), bi = ld4(Aiq, 0);
+    f32x4 br = lda4(Aw_re, 0), bi = lda4(Aw_im, 0);
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
-      const f32x4 brn = kc + 1 < NKC ? ld4(Arq, kc + 1) : br;
-      const f32x4 bin = kc + 1 < NKC ? ld4(Aiq, kc + 1) : bi;
+      const f32x4 brn = kc + 1 < NKC ? lda4(Aw_re, kc + 1) : br;
+      const f32x4 bin = kc + 1 < NKC ? lda4(Aw_im, kc + 1) : bi;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         if (rb >= nrb) break;

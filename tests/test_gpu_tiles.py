@@ -1,4 +1,5 @@
-"""Contraction tile variants (walkers per workgroup, wide, flattened and stacked-row kernels) and the autotuner: every
+"""Contraction tile variants (walkers per workgroup, wide, flattened, stacked-row and ping-pong
+kernels) and the autotuner: every
 variant meets the parity bar against the FP64 oracle, and the variants agree with each other."""
 
 import numpy as np
@@ -33,7 +34,7 @@ def test_every_tile_meets_the_bar(shape, precision):
     gs.init(wk)
     wk.U.copy_(torch.from_numpy(oracle_U_to_gpu(Uu, Ud)))
     energies = {}
-    for tile in ("w4", "w2", "wide", "flat", "stack"):
+    for tile in ("w4", "w2", "wide", "flat", "stack", "pp"):
         if tile == "wide" and max(s.n_up, s.n_dn) <= 16:
             with pytest.raises(afq.AfqmcError):
                 gs.set_tile(tile)
@@ -48,6 +49,8 @@ def test_every_tile_meets_the_bar(shape, precision):
         energies[tile] = e
     for tile, e in energies.items():
         assert np.abs(e - energies["w4"]).max() < 2e-5, tile
+    # the same per-wavefront arithmetic in another schedule: identical results
+    assert np.array_equal(energies["pp"], energies["w4"])
 
 
 def test_autotune_picks_a_valid_tile_and_reuses_it():
@@ -58,7 +61,7 @@ def test_autotune_picks_a_valid_tile_and_reuses_it():
     gs.init(wk)
     tile, ms = gs.autotune(wk, reuse=False)
     log(f"autotune: {tile} {ms:.3f} ms")
-    assert tile in ("w4", "w2", "wide", "flat", "stack") and ms > 0 and gs.tile == tile
+    assert tile in ("w4", "w2", "wide", "flat", "stack", "pp") and ms > 0 and gs.tile == tile
     gs2 = afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
     wk2 = gs2.walkers(64)
     gs2.init(wk2)
