@@ -252,13 +252,15 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
  * 224); the stacked-row kernel stacks the rows the same way but keeps Re and Im Theta as two
  * operands of 16 columns (N padded to a multiple of 16, half the operand traffic per flop).
  * Every variant computes the same quantities.
- *   AFQMC_TILE_DEFAULT  where the shape fits it (N <= 32, M <= 128) W = 4 in FP32 and
- *                       the ping-pong kernel in BF16x3, else wide
+ *   AFQMC_TILE_DEFAULT  where the shape fits it (N <= 32, M <= 128) the block-exchange
+ *                       kernel for 16 < N <= 32 and W = 4 for N <= 16, else wide
  *   AFQMC_TILE_W4, AFQMC_TILE_W2, AFQMC_TILE_WIDE  (wide needs N_P >= 32, i.e. N > 16 or M > 128)
  *   AFQMC_TILE_FLAT, AFQMC_TILE_STACK  (any FP32 / BF16x3 shape)
  *   AFQMC_TILE_PP  eight walkers per workgroup, two wavefronts per SIMD alternating between
  *                  the MFMA chain of one Cholesky vector and the LDS epilogue of the one before
  *                  (N <= 32, M <= 128)
+ *   AFQMC_TILE_BX  W = 4 with Omega as four 16 x 16 blocks, the off-diagonal exchange
+ *                  lane-local (16 < N <= 32, M <= 128)
  * The FP64 mode has one contraction kernel per shape and accepts only the default. */
 #define AFQMC_TILE_DEFAULT 0
 #define AFQMC_TILE_W4 1
@@ -267,6 +269,7 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
 #define AFQMC_TILE_FLAT 4
 #define AFQMC_TILE_STACK 5
 #define AFQMC_TILE_PP 6
+#define AFQMC_TILE_BX 7
 
 /* Autotuner: times every variant valid for the system's shape on these walkers (initialized
  * or measured; one untimed and three timed launches each, on the system's stream, writing only
@@ -384,7 +387,7 @@ AFQMC_API int afqmc_get_status(afqmc_sys s, uint32_t* status, int clear);
  * milliseconds and the number of launches of one kernel group, synchronizing the stream:
  *   0 = local-energy contraction, 1 = overlap / inverse, 2 = fields and force bias,
  *   3 = propagator build, 4 = Taylor propagation, 5 = QR, 6 = weights, 7 = comb,
- *   8 = energy assembly. */
+ *   8 = energy assembly, 9 = the precision guard (walker list and FP64 redo). */
 AFQMC_API int afqmc_kernel_timing(afqmc_sys s, int enable);
 AFQMC_API int afqmc_kernel_time(afqmc_sys s, int kernel, double* ms, int64_t* launches);
 

@@ -17,7 +17,7 @@ STATUS_BITS = {0x1: "nonfinite", 0x2: "singular", 0x4: "ecap", 0x8: "wcap", 0x10
                0x20: "phase"}
 
 KERNEL_GROUPS = ["contract", "overlap", "fields", "abuild", "propagate", "qr", "weights", "comb",
-                 "assemble"]
+                 "assemble", "guard"]
 
 EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walkers_init",
            "afqmc_measure", "afqmc_step", "afqmc_fields_draw", "afqmc_energy", "afqmc_get_status",
@@ -28,7 +28,7 @@ EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walk
            "afqmc_mfma_peak", "afqmc_get_growth", "afqmc_get_bound_counts",
            "afqmc_modified_cholesky_noalloc", "afqmc_batch_set_mode"]
 
-TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5, "pp": 6}
+TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5, "pp": 6, "bx": 7}
 MFMA_PEAK_BYTES = 16384   # AFQMC_MFMA_PEAK_BYTES
 
 

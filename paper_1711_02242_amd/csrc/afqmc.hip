@@ -44,7 +44,7 @@ inline std::vector<std::pair<int, int>> pair_order(int M) {
 
 
 enum { KG_CONTRACT = 0, KG_OVERLAP, KG_FIELDS, KG_ABUILD, KG_PROP, KG_QR, KG_WEIGHT, KG_COMB,
-       KG_ASSEMBLE, KG_COUNT };
+       KG_ASSEMBLE, KG_GUARD, KG_COUNT };
 
 struct TimedLaunch {
   int group;
@@ -413,21 +413,19 @@ int launch_contraction(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L
 int launch_guard_assemble(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L,
                           bool in_step) {
   void* ws = w->workspace;
-  if (S->mt.enabled) {
-    Timer tm(S, KG_CONTRACT);
-    if (S->guard_on) {
-      // walkers far from the trial (large Theta) again in FP64, over the partial sums of the
-      // low-precision pass
-      hipLaunchKernelGGL(k_guard_list, dim3(1), dim3(1024), 0, S->stream, w->n_walkers, S->n_det,
-                         S->guard, w->weight, (const double*)at<double>(ws, L.thmax),
-                         at<int>(ws, L.glist), at<int>(ws, L.gcount),
-                         in_step ? S->capcount : nullptr);
-      HIPCHK(hipGetLastError());
-      HIPCHK(mfma_contract(S->mt64, S->stream, w->n_walkers, S->n_det, S->G,
-                           at<void>(ws, L.thetaP64), w->weight, at<cd>(ws, L.tpart),
-                           at<cd>(ws, L.exch), TILE_DEFAULT, at<int>(ws, L.glist),
-                           at<int>(ws, L.gcount)));
-    }
+  if (S->mt.enabled && S->guard_on) {
+    // walkers far from the trial (large Theta) again in FP64, over the partial sums of the
+    // low-precision pass
+    Timer tm(S, KG_GUARD);
+    hipLaunchKernelGGL(k_guard_list, dim3(1), dim3(1024), 0, S->stream, w->n_walkers, S->n_det,
+                       S->guard, w->weight, (const double*)at<double>(ws, L.thmax),
+                       at<int>(ws, L.glist), at<int>(ws, L.gcount),
+                       in_step ? S->capcount : nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(mfma_contract(S->mt64, S->stream, w->n_walkers, S->n_det, S->G,
+                         at<void>(ws, L.thetaP64), w->weight, at<cd>(ws, L.tpart),
+                         at<cd>(ws, L.exch), TILE_DEFAULT, at<int>(ws, L.glist),
+                         at<int>(ws, L.gcount)));
   }
   if (S->multi) {
     Timer tm(S, KG_ASSEMBLE);

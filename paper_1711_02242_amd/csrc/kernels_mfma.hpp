@@ -41,7 +41,7 @@ constexpr int WIDE_KMAX = 224;   // K limit of the wide (workgroup-per-walker) k
 // Contraction kernel variants (tile shapes) the autotuner chooses among.
 enum {
   TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_FLAT = 4, TILE_STACK = 5,
-  TILE_PP = 6, TILE_COUNT = 7
+  TILE_PP = 6, TILE_BX = 7, TILE_COUNT = 8
 };
 
 struct MfmaTables {
@@ -170,6 +170,7 @@ inline void mfma_free_tables(MfmaTables& t) {
 #include "contract_wide.hpp"
 #include "contract_flat.hpp"
 #include "contract_pp.hpp"
+#include "contract_bx.hpp"
 
 inline size_t mfma_contract_lds_bytes(const MfmaTables& t, int wpb) {
   const bool bf = t.precision == AFQMC_BF16X3;
@@ -188,6 +189,7 @@ inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
     case TILE_W4:
     case TILE_W2:
     case TILE_PP: return !t.wide;
+    case TILE_BX: return !t.wide && t.NP == 32;
     case TILE_WIDE: return t.NP >= 32 && t.KP <= WIDE_KMAX;
     case TILE_FLAT:
     case TILE_STACK: {
@@ -410,8 +412,8 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   }
   const bool bf = t.precision == AFQMC_BF16X3;
   if (!mfma_tile_valid(t, tile)) tile = TILE_DEFAULT;
-  // BF16x3 defaults to the ping-pong schedule (its per-g chain is short against the epilogue)
-  if (tile == TILE_DEFAULT && bf && !t.wide) tile = TILE_PP;
+  // default at N_P = 32: the block-exchange kernel (fewest LDS and vector instructions per g)
+  if (tile == TILE_DEFAULT && !t.wide && t.NP == 32) tile = TILE_BX;
   if (tile == TILE_FLAT || tile == TILE_STACK) {
     const bool stk = tile == TILE_STACK;
     const FlatLaunch f = flat_launch(t.nup, t.ndn, G, bf, stk);
@@ -503,6 +505,27 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   const int wpb = tile == TILE_W2 ? 2 : 4;
   // the kernels are instantiated for K_P = 32, 64, 96, 128
   if (t.KP % 32 != 0 || t.KP < 32 || t.KP > MFMA_KMAX) return hipErrorInvalidValue;
+  if (tile == TILE_BX) {
+    const size_t shm = bx_contract_lds_bytes(t.KP, bf);
+    dim3 grid((nw + 3) / 4, 2 * n_det);
+#define LAUNCH_BX(BFV, NKV)                                                                    \
+  case NKV:                                                                                    \
+    (void)hipFuncSetAttribute((const void*)k_contract_mfma_bx<BFV, NKV>,                       \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
+    hipLaunchKernelGGL((k_contract_mfma_bx<BFV, NKV>), grid, dim3(256), shm, st, nw, G, t.nup, \
+                       t.ndn, (const void*)t.Lp, thetaP, weight, tpart, exch);                 \
+    break;
+    // one instantiation per K chunk count (K_P = 32 .. 128 in steps of 32)
+    if (bf) {
+      switch (t.KP / 32) { LAUNCH_BX(true, 1) LAUNCH_BX(true, 2) LAUNCH_BX(true, 3)
+                           default: LAUNCH_BX(true, 4) }
+    } else {
+      switch (t.KP / 16) { LAUNCH_BX(false, 2) LAUNCH_BX(false, 4) LAUNCH_BX(false, 6)
+                           default: LAUNCH_BX(false, 8) }
+    }
+#undef LAUNCH_BX
+    return hipGetLastError();
+  }
   if (tile == TILE_PP) {
     const size_t shm = pp_contract_lds_bytes(t.NP, t.KP, bf);
     dim3 grid((nw + 7) / 8, 2 * n_det);

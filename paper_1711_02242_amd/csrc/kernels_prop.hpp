@@ -43,12 +43,20 @@ inline void apk_entry(int k, int& q, int& p) {
   p = 8 * PB + (e & 7);
 }
 
-// Workgroup tile of a gx x gy grid renumbered so that each of the 8 XCDs (workgroups go to
-// them round-robin by linear id) takes a contiguous run of tiles in x-fastest order: tiles of
-// one grid column y then share one XCD's L2.
+// Workgroup tile of a gx x gy grid renumbered for the 8 XCDs (workgroups go to them
+// round-robin by linear id, each XCD with an L2 of its own).  Where gx is even and 4 divides
+// gy, XCD x takes the block of half the rows (x & 1) and a quarter of the columns (x >> 1),
+// rows fastest: its share of the row operand stays small enough for its L2 while the column
+// operand streams through once.  Otherwise each XCD takes a contiguous run of tiles in
+// x-fastest order.
 __device__ __forceinline__ int2 xcd_tile(int gx, int gy) {
   const int n = gx * gy, L = blockIdx.x + gx * blockIdx.y;
-  const int x = L & 7, j = L >> 3, q = n >> 3, r = n & 7;
+  const int x = L & 7, j = L >> 3;
+  if ((gx & 1) == 0 && (gy & 3) == 0) {
+    const int hx = gx >> 1, qy = gy >> 2;   // block of hx x qy tiles = n / 8
+    return make_int2((x & 1) * hx + j % hx, (x >> 1) * qy + j / hx);
+  }
+  const int q = n >> 3, r = n & 7;
   const int t = x * q + (x < r ? x : r) + j;
   return make_int2(t % gx, t / gx);
 }

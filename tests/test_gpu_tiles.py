@@ -1,5 +1,5 @@
-"""Contraction tile variants (walkers per workgroup, wide, flattened, stacked-row and ping-pong
-kernels) and the autotuner: every
+"""Contraction tile variants (walkers per workgroup, wide, flattened, stacked-row, ping-pong and
+block-exchange kernels) and the autotuner: every
 variant meets the parity bar against the FP64 oracle, and the variants agree with each other."""
 
 import numpy as np
@@ -34,8 +34,8 @@ def test_every_tile_meets_the_bar(shape, precision):
     gs.init(wk)
     wk.U.copy_(torch.from_numpy(oracle_U_to_gpu(Uu, Ud)))
     energies = {}
-    for tile in ("w4", "w2", "wide", "flat", "stack", "pp"):
-        if tile == "wide" and max(s.n_up, s.n_dn) <= 16:
+    for tile in ("w4", "w2", "wide", "flat", "stack", "pp", "bx"):
+        if tile in ("wide", "bx") and max(s.n_up, s.n_dn) <= 16:
             with pytest.raises(afq.AfqmcError):
                 gs.set_tile(tile)
             continue
@@ -61,7 +61,7 @@ def test_autotune_picks_a_valid_tile_and_reuses_it():
     gs.init(wk)
     tile, ms = gs.autotune(wk, reuse=False)
     log(f"autotune: {tile} {ms:.3f} ms")
-    assert tile in ("w4", "w2", "wide", "flat", "stack", "pp") and ms > 0 and gs.tile == tile
+    assert tile in ("w4", "w2", "wide", "flat", "stack", "pp", "bx") and ms > 0 and gs.tile == tile
     gs2 = afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
     wk2 = gs2.walkers(64)
     gs2.init(wk2)
