@@ -253,14 +253,16 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
  * operands of 16 columns (N padded to a multiple of 16, half the operand traffic per flop).
  * Every variant computes the same quantities.
  *   AFQMC_TILE_DEFAULT  where the shape fits it (N <= 32, M <= 128) the block-exchange
- *                       kernel for 16 < N <= 32 and W = 4 for N <= 16, else wide
+ *                       kernel for 16 < N <= 32 (W = 8 when the workgroups with work still
+ *                       number at least the device's compute units, else W = 4) and W = 4
+ *                       for N <= 16, else wide
  *   AFQMC_TILE_W4, AFQMC_TILE_W2, AFQMC_TILE_WIDE  (wide needs N_P >= 32, i.e. N > 16 or M > 128)
  *   AFQMC_TILE_FLAT, AFQMC_TILE_STACK  (any FP32 / BF16x3 shape)
  *   AFQMC_TILE_PP  eight walkers per workgroup, two wavefronts per SIMD alternating between
  *                  the MFMA chain of one Cholesky vector and the LDS epilogue of the one before
  *                  (N <= 32, M <= 128)
  *   AFQMC_TILE_BX  W = 4 with Omega as four 16 x 16 blocks, the off-diagonal exchange
- *                  lane-local (16 < N <= 32, M <= 128)
+ *                  lane-local (16 < N <= 32, M <= 128); AFQMC_TILE_BX8 the same with W = 8
  * The FP64 mode has one contraction kernel per shape and accepts only the default. */
 #define AFQMC_TILE_DEFAULT 0
 #define AFQMC_TILE_W4 1
@@ -270,6 +272,7 @@ AFQMC_API int afqmc_step(afqmc_sys s, afqmc_walkers* w, const afqmc_fields* f);
 #define AFQMC_TILE_STACK 5
 #define AFQMC_TILE_PP 6
 #define AFQMC_TILE_BX 7
+#define AFQMC_TILE_BX8 8
 
 /* Autotuner: times every variant valid for the system's shape on these walkers (initialized
  * or measured; one untimed and three timed launches each, on the system's stream, writing only

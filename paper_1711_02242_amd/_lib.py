@@ -28,7 +28,7 @@ EXPORTS = ["afqmc_setup", "afqmc_workspace_bytes", "afqmc_get_info", "afqmc_walk
            "afqmc_mfma_peak", "afqmc_get_growth", "afqmc_get_bound_counts",
            "afqmc_modified_cholesky_noalloc", "afqmc_batch_set_mode"]
 
-TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5, "pp": 6, "bx": 7}
+TILES = {"default": 0, "w4": 1, "w2": 2, "wide": 3, "flat": 4, "stack": 5, "pp": 6, "bx": 7, "bx8": 8}
 MFMA_PEAK_BYTES = 16384   # AFQMC_MFMA_PEAK_BYTES
 
 

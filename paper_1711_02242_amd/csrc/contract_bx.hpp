@@ -17,12 +17,14 @@
 // form, and on the matrix-core SIMDs both add to the MFMA time.
 #pragma once
 
-template <bool BF16, int NK>
-__global__ void __launch_bounds__(256, 2) k_contract_mfma_bx(
+// WPB walkers per workgroup (4 or 8; two wavefronts per SIMD either way): eight share each
+// tile copy and barrier among twice the walkers.
+template <bool BF16, int NK, int WPB>
+__global__ void __launch_bounds__(64 * WPB, 8 / WPB) k_contract_mfma_bx(
     int nw, int G, int nup, int ndn, const void* __restrict__ Lp_, const void* __restrict__ thp_,
     const double* __restrict__ weight, cd* __restrict__ tpart, cd* __restrict__ exch) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  constexpr int NP = 32, WPB = 4, NT = 256;
+  constexpr int NP = 32, NT = 64 * WPB;
   constexpr int ESZ = BF16 ? 2 : 4, PLANES = BF16 ? 2 : 1;
   constexpr int KCH = BF16 ? 32 : 16;     // K per chunk: FP32 4 MFMA steps of 4, BF16 one of 32
   constexpr int KP = NK * KCH;
@@ -228,8 +230,8 @@ __global__ void __launch_bounds__(256, 2) k_contract_mfma_bx(
   }
 }
 
-// Dynamic LDS of the block-exchange kernel: two tile buffers and four wavefronts' planes.
-inline size_t bx_contract_lds_bytes(int KP, bool bf) {
+// Dynamic LDS of the block-exchange kernel: two tile buffers and the wavefronts' planes.
+inline size_t bx_contract_lds_bytes(int KP, bool bf, int wpb) {
   const size_t tile = bf ? (size_t)32 * (KP + 8) * 2 * 2 : (size_t)32 * (KP + 4) * 4;
-  return 2 * tile + (size_t)4 * 16 * 17 * 4 * 4;
+  return 2 * tile + (size_t)wpb * 16 * 17 * 4 * 4;
 }

@@ -41,7 +41,7 @@ constexpr int WIDE_KMAX = 224;   // K limit of the wide (workgroup-per-walker) k
 // Contraction kernel variants (tile shapes) the autotuner chooses among.
 enum {
   TILE_DEFAULT = 0, TILE_W4 = 1, TILE_W2 = 2, TILE_WIDE = 3, TILE_FLAT = 4, TILE_STACK = 5,
-  TILE_PP = 6, TILE_BX = 7, TILE_COUNT = 8
+  TILE_PP = 6, TILE_BX = 7, TILE_BX8 = 8, TILE_COUNT = 9
 };
 
 struct MfmaTables {
@@ -180,6 +180,21 @@ inline size_t mfma_contract_lds_bytes(const MfmaTables& t, int wpb) {
   return 2 * tile + (size_t)wpb * 2 * t.NP * (t.NP + 4) * 4;
 }
 
+// Compute units of the current device (queried once per device).
+inline int device_cu_count() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] <= 0) {
+    int n = 0;
+    cus[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                       n > 0
+                   ? n
+                   : 256;
+  }
+  return cus[dev];
+}
+
 // Whether a contraction variant can run on these tables.
 inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
   if (!t.enabled) return false;
@@ -189,7 +204,8 @@ inline bool mfma_tile_valid(const MfmaTables& t, int tile) {
     case TILE_W4:
     case TILE_W2:
     case TILE_PP: return !t.wide;
-    case TILE_BX: return !t.wide && t.NP == 32;
+    case TILE_BX:
+    case TILE_BX8: return !t.wide && t.NP == 32;
     case TILE_WIDE: return t.NP >= 32 && t.KP <= WIDE_KMAX;
     case TILE_FLAT:
     case TILE_STACK: {
@@ -412,8 +428,14 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   }
   const bool bf = t.precision == AFQMC_BF16X3;
   if (!mfma_tile_valid(t, tile)) tile = TILE_DEFAULT;
-  // default at N_P = 32: the block-exchange kernel (fewest LDS and vector instructions per g)
-  if (tile == TILE_DEFAULT && !t.wide && t.NP == 32) tile = TILE_BX;
+  // default at N_P = 32: the block-exchange kernel (fewest LDS and vector instructions per g),
+  // eight walkers per workgroup when the workgroups with work (walkers, active spins,
+  // determinants) still cover every CU
+  if (tile == TILE_DEFAULT && !t.wide && t.NP == 32) {
+    const int spins = (t.nup > 0 ? 1 : 0) + (t.ndn > 0 ? 1 : 0);
+    tile = (size_t)((nw + 7) / 8) * spins * n_det >= (size_t)device_cu_count() ? TILE_BX8
+                                                                                 : TILE_BX;
+  }
   if (tile == TILE_FLAT || tile == TILE_STACK) {
     const bool stk = tile == TILE_STACK;
     const FlatLaunch f = flat_launch(t.nup, t.ndn, G, bf, stk);
@@ -505,24 +527,31 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
   const int wpb = tile == TILE_W2 ? 2 : 4;
   // the kernels are instantiated for K_P = 32, 64, 96, 128
   if (t.KP % 32 != 0 || t.KP < 32 || t.KP > MFMA_KMAX) return hipErrorInvalidValue;
-  if (tile == TILE_BX) {
-    const size_t shm = bx_contract_lds_bytes(t.KP, bf);
-    dim3 grid((nw + 3) / 4, 2 * n_det);
-#define LAUNCH_BX(BFV, NKV)                                                                    \
-  case NKV:                                                                                    \
-    (void)hipFuncSetAttribute((const void*)k_contract_mfma_bx<BFV, NKV>,                       \
+  if (tile == TILE_BX || tile == TILE_BX8) {
+    const int wb = tile == TILE_BX8 ? 8 : 4;
+    const size_t shm = bx_contract_lds_bytes(t.KP, bf, wb);
+    dim3 grid((nw + wb - 1) / wb, 2 * n_det);
+#define LAUNCH_BX(BFV, NKV, WBV)                                                               \
+  do {                                                                                         \
+    (void)hipFuncSetAttribute((const void*)k_contract_mfma_bx<BFV, NKV, WBV>,                  \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
-    hipLaunchKernelGGL((k_contract_mfma_bx<BFV, NKV>), grid, dim3(256), shm, st, nw, G, t.nup, \
-                       t.ndn, (const void*)t.Lp, thetaP, weight, tpart, exch);                 \
+    hipLaunchKernelGGL((k_contract_mfma_bx<BFV, NKV, WBV>), grid, dim3(64 * WBV), shm, st, nw, \
+                       G, t.nup, t.ndn, (const void*)t.Lp, thetaP, weight, tpart, exch);       \
+  } while (0)
+#define LAUNCH_BX_W(BFV, NKV)                                                                  \
+  case NKV:                                                                                    \
+    if (wb == 8) LAUNCH_BX(BFV, NKV, 8);                                                       \
+    else LAUNCH_BX(BFV, NKV, 4);                                                               \
     break;
     // one instantiation per K chunk count (K_P = 32 .. 128 in steps of 32)
     if (bf) {
-      switch (t.KP / 32) { LAUNCH_BX(true, 1) LAUNCH_BX(true, 2) LAUNCH_BX(true, 3)
-                           default: LAUNCH_BX(true, 4) }
+      switch (t.KP / 32) { LAUNCH_BX_W(true, 1) LAUNCH_BX_W(true, 2) LAUNCH_BX_W(true, 3)
+                           default: LAUNCH_BX_W(true, 4) }
     } else {
-      switch (t.KP / 16) { LAUNCH_BX(false, 2) LAUNCH_BX(false, 4) LAUNCH_BX(false, 6)
-                           default: LAUNCH_BX(false, 8) }
+      switch (t.KP / 16) { LAUNCH_BX_W(false, 2) LAUNCH_BX_W(false, 4) LAUNCH_BX_W(false, 6)
+                           default: LAUNCH_BX_W(false, 8) }
     }
+#undef LAUNCH_BX_W
 #undef LAUNCH_BX
     return hipGetLastError();
   }

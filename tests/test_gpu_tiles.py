@@ -34,8 +34,8 @@ def test_every_tile_meets_the_bar(shape, precision):
     gs.init(wk)
     wk.U.copy_(torch.from_numpy(oracle_U_to_gpu(Uu, Ud)))
     energies = {}
-    for tile in ("w4", "w2", "wide", "flat", "stack", "pp", "bx"):
-        if tile in ("wide", "bx") and max(s.n_up, s.n_dn) <= 16:
+    for tile in ("w4", "w2", "wide", "flat", "stack", "pp", "bx", "bx8"):
+        if tile in ("wide", "bx", "bx8") and max(s.n_up, s.n_dn) <= 16:
             with pytest.raises(afq.AfqmcError):
                 gs.set_tile(tile)
             continue
@@ -51,6 +51,8 @@ def test_every_tile_meets_the_bar(shape, precision):
         assert np.abs(e - energies["w4"]).max() < 2e-5, tile
     # the same per-wavefront arithmetic in another schedule: identical results
     assert np.array_equal(energies["pp"], energies["w4"])
+    if "bx" in energies:
+        assert np.array_equal(energies["bx8"], energies["bx"])
 
 
 def test_autotune_picks_a_valid_tile_and_reuses_it():
@@ -61,7 +63,7 @@ def test_autotune_picks_a_valid_tile_and_reuses_it():
     gs.init(wk)
     tile, ms = gs.autotune(wk, reuse=False)
     log(f"autotune: {tile} {ms:.3f} ms")
-    assert tile in ("w4", "w2", "wide", "flat", "stack", "pp", "bx") and ms > 0 and gs.tile == tile
+    assert tile in ("w4", "w2", "wide", "flat", "stack", "pp", "bx", "bx8") and ms > 0 and gs.tile == tile
     gs2 = afq.System.from_synthetic(s, dtau=0.005, precision="fp32")
     wk2 = gs2.walkers(64)
     gs2.init(wk2)
