@@ -61,6 +61,39 @@ def test_closed_shell_large_static_energy():
         assert np.abs(a - b).max() < 1e-10 * max(1.0, np.abs(a).max())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("nw", [1024, 2048])
+def test_closed_shell_large_mixed_precision(precision, nw):
+    """Full-size closed-shell measure in the mixed modes, at populations on both sides of the
+    default contraction's switch to eight walkers per workgroup (one active spin: 2048 walkers
+    take it, 1024 do not; two spins take it at both): E_L equals the two-spin path's in the same
+    precision, and both are within 1e-4 Ha of the two-spin FP64 path."""
+    import torch
+
+    import paper_1711_02242_amd as afq
+    s = config_system("large")
+    Uu, _ = random_walkers(s, 64, seed=4, amplitude=0.3)
+    Ut = torch.from_numpy(np.ascontiguousarray(Uu.transpose(0, 2, 1))).cuda()
+    Ut = Ut.repeat(nw // 64, 1, 1)
+    out = {}
+    for prec, cs in ((precision, False), (precision, True), ("fp64", False)):
+        gs = afq.System.from_synthetic(s, dtau=0.005, precision=prec, closed_shell=cs)
+        wk = gs.walkers(nw)
+        gs.init(wk)
+        wk.U.copy_(torch.cat([Ut, Ut], dim=1) if not cs else Ut)
+        gs.measure(wk)
+        torch.cuda.synchronize()
+        out[(prec, cs)] = wk.e_loc.cpu().numpy()
+        del wk
+        gs.close()
+    two, one, ref = out[(precision, False)], out[(precision, True)], out[("fp64", False)]
+    log(f"closed shell {precision} nw={nw}: max |one - two| {np.abs(one - two).max():.2e}, "
+        f"max |dE_L| vs FP64 {np.abs(one - ref).max():.2e} Ha")
+    assert np.abs(one - two).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(one - ref).max() < 1e-4
+    assert np.abs(two - ref).max() < 1e-4
+
+
 def test_closed_shell_rejects_open_shell_input():
     import paper_1711_02242_amd as afq
     s = gen_system(10, 3, 12, seed=7, n_dn=2)
