@@ -411,8 +411,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain-FP64 GPU run and the local-energy error measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-walkers", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-walkers", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--oracle-sample", type=int, default=4)
     ap.add_argument("--no-closed-shell", action="store_true",
                     help="skip the closed-shell one-spin measurement")
