@@ -344,7 +344,7 @@ int check_walkers(const afqmc_sys_s* S, const afqmc_walkers* w) {
 int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, int check_weight) {
   Timer tm(S, KG_OVERLAP);
   const int nmax = std::max(S->nup, S->ndn);
-  // one workgroup per (walker, spin, determinant); only the Gauss-Jordan matrix sits in LDS
+  // one workgroup per (walker, spin, determinant)
   dim3 grid(w->n_walkers, 2, S->n_det);
   void* ws = w->workspace;
   void* packed = S->mt.enabled ? at<void>(ws, L.thetaP) : nullptr;
@@ -364,15 +364,25 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
                        S->guard_on ? at<double>(ws, L.thmax) : nullptr,                        \
                        S->guard_on ? at<double>(ws, L.thetaP64) : nullptr);                    \
   } while (0)
+#define OVW(NPAD)                                                                              \
+  hipLaunchKernelGGL(k_overlap_wave<NPAD>, grid, dim3(64), 0, S->stream, S->M, S->nup, S->ndn,   \
+                     S->V, S->ht, (const cd*)w->U, w->weight, check_weight,                      \
+                     S->mt.enabled ? nullptr : at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet),       \
+                     at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed, kind, S->mt.NP,        \
+                     S->mt.KP, S->guard_on ? at<double>(ws, L.thmax) : nullptr,                  \
+                     S->guard_on ? at<double>(ws, L.thetaP64) : nullptr)
+  // up to N = 32 one wavefront per matrix (elimination in registers), beyond it the
+  // four-wavefront kernel with [T | I] in LDS
   if (nmax <= 16)
-    OVL(16);
+    OVW(16);
   else if (nmax <= 32)
-    OVL(32);
+    OVW(32);
   else if (nmax <= 48)
     OVL(48);
   else
     OVL(64);
 #undef OVL
+#undef OVW
   HIPCHK(hipGetLastError());
   return AFQMC_OK;
 }
@@ -950,9 +960,18 @@ int step_pre(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool graph
       hipLaunchKernelGGL(k_y_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s->stream, nw,
                          s->G, s->Gp, at<cd>(ws, L.y), at<float>(ws, L.y32));
       const int MA = apk_size(M);
-      dim3 grid((2 * nw + AB_BM - 1) / AB_BM, (MA + AB_BN - 1) / AB_BN);
-      hipLaunchKernelGGL(k_abuild_f32, grid, dim3(256), 0, s->stream, 2 * nw, MA, s->Gp,
-                         (float)s->s, at<float>(ws, L.y32), s->Lt32, Are, Aim);
+      const int cb = abuild_cb(2 * nw, MA);
+      dim3 grid((2 * nw + AB_BM - 1) / AB_BM, (MA + 16 * cb - 1) / (16 * cb));
+#define ABUILD(CBV)                                                                              \
+  case CBV:                                                                                      \
+    hipLaunchKernelGGL(k_abuild_f32<CBV>, grid, dim3(256), 0, s->stream, 2 * nw, MA, s->Gp,      \
+                       (float)s->s, at<float>(ws, L.y32), s->Lt32, Are, Aim);                    \
+    break;
+      switch (cb) {
+        ABUILD(17) ABUILD(16) ABUILD(12) ABUILD(8) ABUILD(4)
+        default: return AFQMC_E_UNSUPPORTED;
+      }
+#undef ABUILD
       HIPCHK(hipGetLastError());
     }
     if (s->prop_wide) {

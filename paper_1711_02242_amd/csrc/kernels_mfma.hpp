@@ -893,3 +893,351 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(
   e1im = block_sum(e1im, red);
   if (tid == 0) e1[2 * wd_ + s] = mkc(e1re, e1im);
 }
+
+// A double of lane l (l wave-uniform) in every lane.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint64_t r = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  return __builtin_bit_cast(double, r);
+}
+
+// Zero the padding of one walker-spin's packed operand planes (rows c >= N of every column,
+// columns p >= M of rows c < N), one wavefront.
+template <typename E>
+__device__ inline void zero_packed_pad(E* base, int planes, size_t per, int N, int M, int NP, int KP,
+                                       int lane) {
+  for (int pl = 0; pl < planes; ++pl) {
+    E* o = base + (size_t)pl * per;
+    for (int c = N; c < NP; ++c)
+      for (int p = lane; p < KP; p += 64) o[(size_t)c * KP + p] = E(0);
+    if (M < KP)
+      for (int c = 0; c < N; ++c)
+        for (int p = M + lane; p < KP; p += 64) o[(size_t)c * KP + p] = E(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The outputs of k_overlap_mfma for N <= 32 (Theorem 1.1-1.2, eq:precomputing) with one
+// wavefront per (walker, spin, determinant) and no workgroup barrier:
+//   T = V^T U on FP64 MFMA (16 x 16 blocks, K = M; each lane loads four consecutive k and
+//     MFMA u takes the u-th of them, the same permutation of k in both operands);
+//   T^-1 by Gauss-Jordan in place in registers: lane i + 32 h holds row i, columns
+//     16 h .. 16 h + 15, with the identity in rows and columns past N.  Pivoting is implicit:
+//     rows stay in their lanes and step k takes as pivot the unused row p_k with the largest
+//     |T_ik|.  The result X satisfies (T^-1)_ij = X[p_i][q_j], q the inverse of p, so
+//     det T = prod_k pivot_k times the sign of the permutation p, and
+//   Theta^T[c][m] = sum_j (T^-1)_jc U_jm = sum_r X[r][q_c] U[q_r][m] on FP64 MFMA (K = r).
+// Step k of the elimination: the two lanes of row p_k put its raw entries in LDS and every
+// lane reads those of its own half of the columns; row i loses f_i times that row, with
+// f_i = T_ik / T_pk and f_p = 1 - 1 / T_pk (which leaves the pivot row divided by the pivot);
+// column k then holds -f_i, and 1 / T_pk in row p_k.
+// ---------------------------------------------------------------------------
+template <int NPAD>
+__global__ void __launch_bounds__(64, 2) k_overlap_wave(
+    int M, int nup, int ndn, const double* __restrict__ V, const double* __restrict__ ht,
+    const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
+    cd* __restrict__ thetaT, cd* __restrict__ logdet, cd* __restrict__ e1,
+    unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP,
+    double* __restrict__ thmax, double* __restrict__ packed64) {
+  static_assert(NPAD == 16 || NPAD == 32, "one wavefront inverts at most 32 x 32");
+  constexpr int NB = NPAD / 16, NKC = NPAD / 16, XL = 33;
+  __shared__ __attribute__((aligned(16))) cd Xs[32 * XL];   // T, then X
+  __shared__ __attribute__((aligned(16))) cd Rb[2][16];     // pivot row, by column half
+  __shared__ cd s_pv[32];
+  __shared__ int s_p[32], s_q[32];
+  const int d = blockIdx.z, n_det = gridDim.z;
+  const int wd_ = blockIdx.x * n_det + d;
+  V += (size_t)d * (nup + ndn) * M;
+  ht += (size_t)d * (nup + ndn) * M;
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s == 0 ? nup : ndn;
+  const int off = s == 0 ? 0 : nup;
+  const int ntot = nup + ndn;
+  const int lane = threadIdx.x;
+  if (N == 0) {
+    if (lane == 0) {
+      logdet[2 * wd_ + s] = mkc(0.0, 0.0);
+      e1[2 * wd_ + s] = mkc(0.0, 0.0);
+      wflag[2 * wd_ + s] = 0u;
+      if (thmax) thmax[2 * wd_ + s] = 0.0;
+    }
+    return;
+  }
+  if (check_weight && !(weight[w] > 0.0)) return;
+  const int l16 = lane & 15, q = lane >> 4;
+  const cd* Uw = U + ((size_t)w * ntot + off) * M;
+  const double* Vs = V + (size_t)off * M;
+
+  // ---- T = V^T U: block (a, b) rows 16 a + l16 of V, columns 16 b + l16 (rows of U); rows
+  // past N read row 0 (never stored), k past M reads column M - 1 with V zeroed there.  The
+  // loads of the next 16 k go out before the MFMAs of these.
+  {
+    f64x4 tr[NB][NB], ti[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) tr[a][b] = ti[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double* vrow[NB];
+    const cd* urow[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int r = 16 * a + l16;
+      vrow[a] = Vs + (size_t)(r < N ? r : 0) * M;
+      urow[a] = Uw + (size_t)(r < N ? r : 0) * M;
+    }
+    double va[NB][4], vn[NB][4];
+    cd ub[NB][4], un[NB][4];
+    auto load = [&](int k0, double (&vv)[NB][4], cd (&uu)[NB][4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * q + u, kk = k < M ? k : M - 1;
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const double x = vrow[a][kk];
+          vv[a][u] = k < M ? x : 0.0;
+          uu[a][u] = urow[a][kk];
+        }
+      }
+    };
+    load(0, va, ub);
+    for (int k0 = 0; k0 < M; k0 += 16) {
+      if (k0 + 16 < M) load(k0 + 16, vn, un);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            tr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[a][u], ub[b][u].re, tr[a][b], 0, 0, 0);
+            ti[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[a][u], ub[b][u].im, ti[a][b], 0, 0, 0);
+          }
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          va[a][u] = vn[a][u];
+          ub[a][u] = un[a][u];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * a + q + 4 * v, c = 16 * b + l16;
+          if (r < N && c < N) Xs[r * XL + c] = mkc(tr[a][b][v], ti[a][b][v]);
+        }
+  }
+  wave_lds_fence();
+
+  // ---- Gauss-Jordan in registers
+  const int gi = lane & 31, gh = lane >> 5;
+  cd x[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int j = 16 * gh + c;
+    x[c] = gi < N && j < N ? Xs[gi * XL + j] : mkc(gi == j ? 1.0 : 0.0, 0.0);
+  }
+  bool used = false;
+  int sing = 0;
+  // a fixed trip count keeps the loop unrolled, so x[ck] is a register; the body is skipped
+  // (uniformly) past N or after a zero pivot
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    if (k >= N || sing) continue;
+    const int hk = k >> 4, ck = k & 15;
+    const cd xk = x[ck];   // column k in the lanes of half hk
+    double best = gh == hk && !used && gi < N ? xk.re * xk.re + xk.im * xk.im : -1.0;
+    int bi = gi;
+    wave_argmax(best, bi);
+    const int p = __builtin_amdgcn_readfirstlane(bi);
+    best = readlane_d(best, 0);
+    if (!(best > 0.0)) {
+      sing = 1;
+      continue;
+    }
+    const int pl = p + 32 * hk;
+    const cd pk = mkc(readlane_d(xk.re, pl), readlane_d(xk.im, pl));
+    const double rb = 1.0 / best;
+    const cd inv = mkc(pk.re * rb, -pk.im * rb);
+    if (gi == p) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) Rb[gh][c] = x[c];
+    }
+    if (lane == 0) {
+      s_p[k] = p;
+      s_pv[k] = pk;
+    }
+    // this lane's T_ik: its own register in half hk, the partner lane's (lane ^ 32) otherwise
+    const cd xo = mkc(__shfl_xor(xk.re, 32), __shfl_xor(xk.im, 32));
+    const cd aik = gh == hk ? xk : xo;
+    cd f = mkc(aik.re * inv.re - aik.im * inv.im, aik.re * inv.im + aik.im * inv.re);
+    if (gi == p) f = mkc(1.0 - inv.re, -inv.im);
+    wave_lds_fence();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) cfms(x[c], f, Rb[gh][c]);
+    if (gh == hk) x[ck] = gi == p ? inv : mkc(-f.re, -f.im);
+    used = used || gi == p;
+    wave_lds_fence();   // the next step's pivot row overwrites Rb
+  }
+  if (sing) {
+    if (lane == 0) {
+      wflag[2 * wd_ + s] = WFLAG_SINGULAR;
+      logdet[2 * wd_ + s] = mkc(-INFINITY, 0.0);
+      e1[2 * wd_ + s] = mkc(0.0, 0.0);
+    }
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) Xs[gi * XL + 16 * gh + c] = x[c];
+  if (lane < N) s_q[s_p[lane]] = lane;
+  wave_lds_fence();
+  {
+    // log det T = sum_k log pivot_k, plus i pi when the permutation p is odd
+    double la = 0.0, ar = 0.0;
+    if (lane < N) {
+      const cd pv = s_pv[lane];
+      la = log(hypot(pv.re, pv.im));
+      ar = atan2(pv.im, pv.re);
+    }
+    la = wave_sum(la);
+    ar = wave_sum(ar);
+    if (lane == 0) {
+      unsigned seen = 0u;
+      int cycles = 0;
+      for (int i0 = 0; i0 < N; ++i0) {
+        if ((seen >> i0) & 1u) continue;
+        ++cycles;
+        for (int j = i0; !((seen >> j) & 1u); j = s_p[j]) seen |= 1u << j;
+      }
+      logdet[2 * wd_ + s] = mkc(la, ar + M_PI * (double)((N - cycles) & 1));
+      wflag[2 * wd_ + s] = 0u;
+    }
+  }
+
+  // ---- Theta^T[c][m] = sum_r X[r][q_c] U[q_r][m]: the X operand read from LDS at
+  // immediate offsets from one address per row block a (rows r past N of X are identity rows,
+  // zero in the columns q_c < N; columns c past N read column 0 and are never stored), U rows
+  // by q, 16 columns m per block, the next block's U loads ahead of this block's MFMAs
+  int xb[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const int c = 16 * a + l16;
+    xb[a] = 4 * q * XL + (c < N ? s_q[c] : 0);
+  }
+  int uro[NKC][4];   // U row q_r, as an element offset
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 16 * kc + 4 * q + u;
+      uro[kc][u] = (r < N ? s_q[r] : 0) * M;
+    }
+  const int CBn = (M + 15) / 16;
+  const size_t per = (size_t)NP * KP;
+  cd* Tw = thetaT ? thetaT + ((size_t)wd_ * ntot + off) * M : nullptr;
+  const double* hts = ht + (size_t)off * M;
+  double e1re = 0.0, e1im = 0.0, th2max = 0.0;
+  cd uv[NKC][4], un2[NKC][4];
+  auto loadu = [&](int b, cd (&dst)[NKC][4]) {
+    const int pp = 16 * b + l16, pc = pp < M ? pp : M - 1;
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) dst[kc][u] = Uw[uro[kc][u] + pc];
+  };
+  loadu(0, uv);
+  for (int b0 = 0; b0 < CBn; ++b0) {
+    // an opaque block index keeps the compiler from turning every store address of the
+    // epilogue into a 64-bit induction variable held across the loop
+    int b = b0;
+    asm volatile("" : "+s"(b));
+    if (b + 1 < CBn) loadu(b + 1, un2);
+    const int pp = 16 * b + l16, pc = pp < M ? pp : M - 1;
+    double hvv[NB][4];   // h~ at this block's outputs, loaded ahead of the MFMAs
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * a + q + 4 * v;
+        hvv[a][v] = hts[(size_t)(c < N ? c : N - 1) * M + pc];
+      }
+    f64x4 cr[NB], ci[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) cr[a] = ci[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // the X reads stay in the loop (hoisted they would hold 64 registers across it)
+    int xo[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      xo[a] = xb[a];
+      asm volatile("" : "+v"(xo[a]));
+    }
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const cd tv = Xs[xo[a] + (16 * kc + u) * XL], uw = uv[kc][u];
+          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uw.re, cr[a], 0, 0, 0);
+          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(-tv.im, uw.im, cr[a], 0, 0, 0);
+          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uw.im, ci[a], 0, 0, 0);
+          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.im, uw.re, ci[a], 0, 0, 0);
+        }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * a + q + 4 * v, p = pp;
+        if (c >= N || p >= M) continue;
+        const cd th = mkc(cr[a][v], ci[a][v]);
+        if (thetaT) Tw[(size_t)c * M + p] = th;
+        if (thmax) {
+          th2max = fmax(th2max, th.re * th.re + th.im * th.im);
+          double* o = packed64 + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
+          o[0] = th.re;
+          o[per] = th.im;
+        }
+        e1re = fma(hvv[a][v], th.re, e1re);
+        e1im = fma(hvv[a][v], th.im, e1im);
+        if (packed_kind == 3) {
+          double* o = reinterpret_cast<double*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
+          o[0] = th.re;
+          o[per] = th.im;
+        } else if (packed_kind == 1) {
+          float* o = reinterpret_cast<float*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
+          o[0] = (float)th.re;
+          o[per] = (float)th.im;
+        } else if (packed_kind == 2) {
+          uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)wd_ * 2 + s) * 4 * per + (size_t)c * KP + p;
+          const float xr = (float)th.re, xi = (float)th.im;
+          const uint16_t hr = f32_to_bf16_bits(xr), hi = f32_to_bf16_bits(xi);
+          o[0] = hr;
+          o[per] = f32_to_bf16_bits(xr - bf16_bits_to_f32(hr));
+          o[2 * per] = hi;
+          o[3 * per] = f32_to_bf16_bits(xi - bf16_bits_to_f32(hi));
+        }
+      }
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) uv[kc][u] = un2[kc][u];
+  }
+  const size_t ws_ = (size_t)wd_ * 2 + s;
+  if (packed_kind == 3)
+    zero_packed_pad(reinterpret_cast<double*>(packed) + ws_ * 2 * per, 2, per, N, M, NP, KP, lane);
+  else if (packed_kind == 1)
+    zero_packed_pad(reinterpret_cast<float*>(packed) + ws_ * 2 * per, 2, per, N, M, NP, KP, lane);
+  else if (packed_kind == 2)
+    zero_packed_pad(reinterpret_cast<uint16_t*>(packed) + ws_ * 4 * per, 4, per, N, M, NP, KP, lane);
+  if (thmax) {
+    zero_packed_pad(packed64 + ws_ * 2 * per, 2, per, N, M, NP, KP, lane);
+    for (int o = 32; o > 0; o >>= 1) th2max = fmax(th2max, __shfl_xor(th2max, o));
+    if (lane == 0) thmax[2 * wd_ + s] = sqrt(th2max);
+  }
+  e1re = wave_sum(e1re);
+  e1im = wave_sum(e1im);
+  if (lane == 0) e1[2 * wd_ + s] = mkc(e1re, e1im);
+}

@@ -79,100 +79,143 @@ __device__ __forceinline__ f32x4 apk_load4(const float* __restrict__ Ap, int M, 
 //   columns, about half of M^2 since A is symmetric),  k = g (padded to Gp, zeros).
 //   Re A_w[col] = -s C[2w+1][col],  Im = s C[2w][col]: planar FP32 output of MA entries per
 //   walker, each written once (a tile's columns are whole block rows: contiguous stores).
-// Tile 128 x 128 per workgroup, K chunks of 32 double-buffered in LDS,
-// 4 wavefronts of 64 x 64 (2 x 2 blocks of v_mfma_f32_32x32x2_f32); the workgroups of one
-// column tile of Lt run on one XCD.
+// Tile 128 rows x 16 CB columns per workgroup, two workgroups per CU; four wavefronts of
+// 32 rows x 16 CB columns (2 x CB blocks of v_mfma_f32_16x16x4_f32); K chunks of 16
+// double-buffered in LDS, Y rows first, then the Lt rows of the tile's columns.  The host
+// picks CB (abuild_cb) so that the workgroups fill whole rounds of the device's slots: at
+// M = 128 the 8704 packed columns make 32 tiles of 272 (CB = 17), and 1024 walkers 16 row
+// tiles, 512 workgroups in all, one round on 256 CUs.  A lane holds four consecutive k of
+// its row in each operand and MFMA e takes the e-th of them: a permutation of the k of the
+// chunk, the same in both operands.
 // ---------------------------------------------------------------------------
-constexpr int AB_BM = 128, AB_BN = 128, AB_BK = 32, AB_LD = AB_BK + 4;
+constexpr int AB_BM = 128, AB_BK = 16, AB_LD = AB_BK + 4;
 
+template <int CB>
 __global__ void __launch_bounds__(256, 2) k_abuild_f32(int rows /*2 nw*/, int MA, int Gp, float s,
                                                        const float* __restrict__ Y,
                                                        const float* __restrict__ Lt,
                                                        float* __restrict__ Are,
                                                        float* __restrict__ Aim) {
-  __shared__ __attribute__((aligned(16))) float As[2][AB_BM * AB_LD];
-  __shared__ __attribute__((aligned(16))) float Bs[2][AB_BN * AB_LD];
+  constexpr int BN = 16 * CB, TR = AB_BM + BN;
+  constexpr int NLD = TR * (AB_BK / 4);           // 16-byte pieces of one K chunk
+  constexpr int PER = (NLD + 255) / 256;
+  static_assert(2 * TR * AB_LD * 4 <= 65536, "tile exceeds the static LDS of a workgroup");
+  __shared__ __attribute__((aligned(16))) float Ls[2][TR * AB_LD];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int2 tile = xcd_tile(gridDim.x, gridDim.y);
-  const int r0 = tile.x * AB_BM, c0 = tile.y * AB_BN;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-  const int col = lane & 31, h = lane >> 5;
-  // each thread moves 4 float4 of A and 4 of B per K chunk
-  f32x4 pa[4], pb[4];
-  // rows past the walkers and columns past the packed triangle re-read row / column 0: they
-  // only feed accumulator rows / columns the epilogue never stores (zeroing them here would
-  // make every chunk wait for its loads before the MFMAs of the previous chunk)
-#define AB_GLOAD(K0_)                                                                    \
-  do {                                                                                   \
-    _Pragma("unroll") for (int c_ = 0; c_ < 4; ++c_) {                                   \
-      const int e_ = tid + c_ * 256;                                                     \
-      const int rr_ = e_ >> 3, kk_ = (e_ & 7) * 4;                                       \
-      const int gr_ = r0 + rr_, gc_ = c0 + rr_;                                          \
-      const int sr_ = gr_ < rows ? gr_ : 0, sc_ = gc_ < MA ? gc_ : 0;                     \
-      pa[c_] = *reinterpret_cast<const f32x4*>(Y + (size_t)sr_ * Gp + (K0_) + kk_);      \
-      pb[c_] = *reinterpret_cast<const f32x4*>(Lt + (size_t)sc_ * Gp + (K0_) + kk_);     \
-    }                                                                                    \
-  } while (0)
-#define AB_LSTORE(BUF_)                                                                  \
-  do {                                                                                   \
-    _Pragma("unroll") for (int c_ = 0; c_ < 4; ++c_) {                                   \
-      const int e_ = tid + c_ * 256;                                                     \
-      const int rr_ = e_ >> 3, kk_ = (e_ & 7) * 4;                                       \
-      *reinterpret_cast<f32x4*>(&As[BUF_][rr_ * AB_LD + kk_]) = pa[c_];                  \
-      *reinterpret_cast<f32x4*>(&Bs[BUF_][rr_ * AB_LD + kk_]) = pb[c_];                  \
-    }                                                                                    \
-  } while (0)
-  f32x16 acc[2][2];
+  const int r0 = tile.x * AB_BM, c0 = tile.y * BN;
+  const int wr = wave * 32;
+  const int col = lane & 15, kg = lane >> 4;
+  // piece e of a chunk: tile row e / 4 (rows below AB_BM are Y rows, the rest Lt rows), k
+  // offset 4 (e % 4); with 256 threads, pass c covers rows 64 c .. 64 c + 63, so the Y / Lt
+  // choice is uniform per pass.  Rows past the walkers and columns past the packed triangle
+  // re-read row / column 0: they only feed accumulator rows / columns that are never stored.
+  f32x4 stg[PER];
+  auto gload = [&](int k0) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
-  const int nk = Gp / AB_BK;
-  AB_GLOAD(0);
-  AB_LSTORE(0);
-  __syncthreads();
-  for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nk) AB_GLOAD((kc + 1) * AB_BK);
-#pragma unroll
-    for (int s8 = 0; s8 < AB_BK / 8; ++s8) {
-      f32x4 fa[2], fb[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-        fa[a] = *reinterpret_cast<const f32x4*>(&As[buf][(wr + 32 * a + col) * AB_LD + 8 * s8 + 4 * h]);
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        fb[b] = *reinterpret_cast<const f32x4*>(&Bs[buf][(wc + 32 * b + col) * AB_LD + 8 * s8 + 4 * h]);
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[a][e], fb[b][e], acc[a][b], 0, 0, 0);
-    }
-    if (kc + 1 < nk) AB_LSTORE(buf ^ 1);
-    __syncthreads();
-  }
-#undef AB_GLOAD
-#undef AB_LSTORE
-  // epilogue: rows 8*(v/4) + 4h + v%4; v%4 in {0,1} -> walker rows (Re, Im), {2,3} next walker
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int cc = c0 + wc + 32 * b + col;
-      if (cc >= MA) continue;
-#pragma unroll
-      for (int v = 0; v < 16; v += 2) {
-        const int r = r0 + wr + 32 * a + 8 * (v / 4) + 4 * h + (v % 4);  // even
-        if (r >= rows) continue;
-        const int w = r >> 1;
-        Are[(size_t)w * MA + cc] = -s * acc[a][b][v + 1];
-        Aim[(size_t)w * MA + cc] = s * acc[a][b][v];
+    for (int c = 0; c < PER; ++c) {
+      const int e = tid + c * 256;
+      if ((c + 1) * 256 <= NLD || e < NLD) {
+        const int rr = e >> 2, kk = (e & 3) * 4;
+        const float* src;
+        if (c * 64 + 63 < AB_BM) {
+          const int gr = r0 + rr;
+          src = Y + (size_t)(gr < rows ? gr : 0) * Gp;
+        } else {
+          const int gc = c0 + rr - AB_BM;
+          src = Lt + (size_t)(gc < MA ? gc : 0) * Gp;
+        }
+        stg[c] = *reinterpret_cast<const f32x4*>(src + k0 + kk);
       }
     }
+  };
+  auto lstore = [&](float* dst) {
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int e = tid + c * 256;
+      if ((c + 1) * 256 <= NLD || e < NLD)
+        *reinterpret_cast<f32x4*>(dst + (e >> 2) * AB_LD + (e & 3) * 4) = stg[c];
+    }
+  };
+  f32x4 acc[2][CB];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = Gp / AB_BK;
+  gload(0);
+  lstore(Ls[0]);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const float* Lb = Ls[kc & 1];
+    if (kc + 1 < nk) gload((kc + 1) * AB_BK);
+    const f32x4 fa0 = *reinterpret_cast<const f32x4*>(Lb + (wr + col) * AB_LD + 4 * kg);
+    const f32x4 fa1 = *reinterpret_cast<const f32x4*>(Lb + (wr + 16 + col) * AB_LD + 4 * kg);
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const f32x4 fb = *reinterpret_cast<const f32x4*>(Lb + (AB_BM + 16 * b + col) * AB_LD + 4 * kg);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0[e], fb[e], acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1[e], fb[e], acc[1][b], 0, 0, 0);
+      }
+    }
+    if (kc + 1 < nk) lstore(Ls[(kc + 1) & 1]);
+    __syncthreads();
+  }
+  // epilogue: lane holds column 16 b + col, rows 16 a + 4 kg + v of the wave's 32; v = 0, 1
+  // are the Re and Im rows of one walker, v = 2, 3 of the next
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int cc = c0 + 16 * b + col;
+      if (cc >= MA) continue;
+#pragma unroll
+      for (int v = 0; v < 4; v += 2) {
+        const int r = r0 + wr + 16 * a + 4 * kg + v;   // even
+        if (r >= rows) continue;
+        const size_t o = (size_t)(r >> 1) * MA + cc;
+        Are[o] = -s * acc[a][b][v + 1];
+        Aim[o] = s * acc[a][b][v];
+      }
+    }
+}
+
+// Column blocks of 16 per A-build tile, from those compiled: the least MFMA time, counted as
+// (rounds of the device's workgroup slots) x (workgroups per CU) x CB, with the workgroups
+// per CU of each instance from the runtime's occupancy (queried once per device); ties go to
+// the wider tile.
+constexpr int AB_CBS[] = {17, 16, 12, 8, 4};
+constexpr int AB_NCB = sizeof(AB_CBS) / sizeof(AB_CBS[0]);
+template <int I>
+inline const void* abuild_fn() {
+  return reinterpret_cast<const void*>(k_abuild_f32<AB_CBS[I]>);
+}
+inline int abuild_cb(int rows, int MA) {
+  static int per_cu[64][AB_NCB] = {};
+  static const void* const fns[AB_NCB] = {abuild_fn<0>(), abuild_fn<1>(), abuild_fn<2>(),
+                                          abuild_fn<3>(), abuild_fn<4>()};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  const long long cus = device_cu_count(), nrow = (rows + AB_BM - 1) / AB_BM;
+  int best = AB_CBS[0];
+  long long best_cost = -1;
+  for (int i = 0; i < AB_NCB; ++i) {
+    if (per_cu[dev][i] <= 0) {
+      int n = 0;
+      per_cu[dev][i] =
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fns[i], 256, 0) == hipSuccess && n > 0
+              ? n
+              : 1;
+    }
+    const long long cb = AB_CBS[i], n = per_cu[dev][i];
+    const long long wgs = nrow * ((MA + 16 * cb - 1) / (16 * cb));
+    const long long cost = (wgs + n * cus - 1) / (n * cus) * n * cb;
+    if (best_cost < 0 || cost < best_cost) best = (int)cb, best_cost = cost;
+  }
+  return best;
 }
 
 // ---------------------------------------------------------------------------
