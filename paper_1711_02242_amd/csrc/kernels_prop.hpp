@@ -272,25 +272,35 @@ __global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
   }
   // B operands: lane holds rows q = qcol, k = 16*kc + 4*q4 .. +3 (16-byte loads where the
   // four are inside the row and aligned)
-  f32x4 be[NKC], bar_[NKC], bai[NKC];
+  f32x4 be[NKC], bar_[NKC], bai[NKC], bas[NKC];
   const bool colok = qcol < M;
+  auto load_eh = [&]() {
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+      be[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int p0 = 16 * kc + 4 * q4;
+      if (colok) {
+        if ((M & 3) == 0 && p0 + 4 <= M) {
+          be[kc] = *reinterpret_cast<const f32x4*>(Eh32 + (size_t)qcol * M + p0);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (p0 + e < M) be[kc][e] = Eh32[(size_t)qcol * M + p0 + e];
+        }
+      }
+    }
+  };
+  load_eh();
 #pragma unroll
   for (int kc = 0; kc < NKC; ++kc) {
-    be[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
     bar_[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
     bai[kc] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int p0 = 16 * kc + 4 * q4;
     if (colok) {
       bar_[kc] = apk_load4(Are + (size_t)w * MA, M, qcol, p0);
       bai[kc] = apk_load4(Aim + (size_t)w * MA, M, qcol, p0);
-      if ((M & 3) == 0 && p0 + 4 <= M) {
-        be[kc] = *reinterpret_cast<const f32x4*>(Eh32 + (size_t)qcol * M + p0);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (p0 + e < M) be[kc][e] = Eh32[(size_t)qcol * M + p0 + e];
-      }
     }
+    bas[kc] = bar_[kc] + bai[kc];
   }
   __syncthreads();
 
@@ -329,25 +339,23 @@ __global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
     }
   }
   __syncthreads();
-  // Taylor terms: T <- T A / n, Y += T
+  // Taylor terms: T <- T A / n, Y += T.  The complex product takes three real ones,
+  // P1 = Tr Ar, P2 = Ti Ai, P3 = (Tr + Ti)(Ar + Ai): Re = P1 - P2, Im = P3 - P1 - P2.
   for (int n = 1; n <= n_taylor; ++n) {
-#pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) {
-      cre[rb] = f32x4{};
-      cim[rb] = f32x4{};
-    }
+    f32x4 p1[NRB], p2[NRB], p3[NRB];
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
         const f32x4 ar = *reinterpret_cast<const f32x4*>(&Tr[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
         const f32x4 ai = *reinterpret_cast<const f32x4*>(&Ti[(16 * rb + j) * ldt + 16 * kc + 4 * q4]);
+        const f32x4 as = ar + ai;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], bar_[kc][e], cre[rb], 0, 0, 0);
-          cre[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[e], bai[kc][e], cre[rb], 0, 0, 0);
-          cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], bai[kc][e], cim[rb], 0, 0, 0);
-          cim[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], bar_[kc][e], cim[rb], 0, 0, 0);
+          const bool first = kc == 0 && e == 0;
+          p1[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[e], bar_[kc][e], first ? f32x4{} : p1[rb], 0, 0, 0);
+          p2[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[e], bai[kc][e], first ? f32x4{} : p2[rb], 0, 0, 0);
+          p3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[e], bas[kc][e], first ? f32x4{} : p3[rb], 0, 0, 0);
         }
       }
     }
@@ -355,8 +363,8 @@ __global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
     __syncthreads();
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) {
-      cre[rb] *= inv;
-      cim[rb] *= inv;
+      cre[rb] = (p1[rb] - p2[rb]) * inv;
+      cim[rb] = (p3[rb] - p1[rb] - p2[rb]) * inv;
       yre[rb] += cre[rb];
       yim[rb] += cim[rb];
       if (qcol < Kp) {
@@ -369,7 +377,8 @@ __global__ void __launch_bounds__(64 * NKC, 1) k_propagate_f32(
     }
     __syncthreads();
   }
-  // Y into the planes, then U' = Y E_h
+  // Y into the planes, then U' = Y E_h (E_h read again: the Taylor loop does not hold it)
+  load_eh();
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb) {
     if (qcol < Kp) {
