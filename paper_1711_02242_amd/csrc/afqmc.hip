@@ -1076,8 +1076,18 @@ int step_pre(afqmc_sys_s* s, afqmc_walkers* w, const afqmc_fields* f, bool graph
   const bool qr_due = s->p.qr_period > 0 && (k + 1) % s->p.qr_period == 0;
   if (qr_due) {
     Timer tm(s, KG_QR);
-    const size_t shm = (size_t)std::max(s->nup, s->ndn) * M * 16;
-    if (shm <= 128 * 1024) {
+    const int nmax = std::max(s->nup, s->ndn);
+    const size_t shm = (size_t)nmax * M * 16;
+    if (nmax <= 32 && M <= 256) {
+      // rows in registers, one barrier per orthonormalized row
+      const dim3 grid(nw, 2);
+      switch ((M + 63) / 64) {
+        case 1: hipLaunchKernelGGL(k_mgs_reg<1>, grid, dim3(256), 0, s->stream, M, s->nup, s->ndn, (cd*)w->U, w->weight, s->status, at<double>(ws, L.logR)); break;
+        case 2: hipLaunchKernelGGL(k_mgs_reg<2>, grid, dim3(256), 0, s->stream, M, s->nup, s->ndn, (cd*)w->U, w->weight, s->status, at<double>(ws, L.logR)); break;
+        case 3: hipLaunchKernelGGL(k_mgs_reg<3>, grid, dim3(256), 0, s->stream, M, s->nup, s->ndn, (cd*)w->U, w->weight, s->status, at<double>(ws, L.logR)); break;
+        default: hipLaunchKernelGGL(k_mgs_reg<4>, grid, dim3(256), 0, s->stream, M, s->nup, s->ndn, (cd*)w->U, w->weight, s->status, at<double>(ws, L.logR)); break;
+      }
+    } else if (shm <= 128 * 1024) {
       (void)hipFuncSetAttribute((const void*)k_mgs<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shm);
       hipLaunchKernelGGL(k_mgs<true>, dim3(nw, 2), dim3(256), shm, s->stream, M, s->nup, s->ndn,

@@ -432,6 +432,99 @@ __global__ void __launch_bounds__(256) k_mgs(int M, int nup, int ndn, cd* __rest
 }
 
 // ---------------------------------------------------------------------------
+// The same modified Gram-Schmidt (Sec. III.D.5) for N <= 32 and M <= 64 NE with the rows in
+// registers: wavefront t of the four holds rows j = 4 s + t (s < 8), elements p = lane + 64 e
+// (e < NE) of each.  Step k: the wavefront of row k normalizes it and puts it in LDS (two
+// buffers, so one barrier per step suffices); every wavefront then removes its projection
+// from its own rows j > k.  log det R is summed per wavefront, then over the four.
+// ---------------------------------------------------------------------------
+template <int NE>
+__global__ void __launch_bounds__(256) k_mgs_reg(int M, int nup, int ndn, cd* __restrict__ U,
+                                                 const double* __restrict__ weight,
+                                                 unsigned* __restrict__ status,
+                                                 double* __restrict__ logR) {
+  __shared__ __attribute__((aligned(16))) cd qb[2][64 * NE];
+  __shared__ double lrs[4];
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s == 0 ? nup : ndn;
+  const int off = s == 0 ? 0 : nup;
+  const int ntot = nup + ndn;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (N == 0) {
+    if (tid == 0) logR[2 * w + s] = 0.0;
+    return;
+  }
+  if (!(weight[w] > 0.0)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  cd* Ug = U + ((size_t)w * ntot + off) * M;
+  cd r[8][NE];
+#pragma unroll
+  for (int s8 = 0; s8 < 8; ++s8) {
+    const int j = 4 * s8 + wave;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int p = lane + 64 * e;
+      r[s8][e] = j < N && p < M ? Ug[(size_t)j * M + p] : mkc(0.0, 0.0);
+    }
+  }
+  double lr = 0.0;   // sum of log r_kk over this wavefront's rows
+  for (int k = 0; k < N; ++k) {
+    if (wave == (k & 3)) {
+      // row k is slot k / 4: selected by a compile-time slot index, so r stays in registers
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        if (s8 != (k >> 2)) continue;
+        double nn = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) nn += r[s8][e].re * r[s8][e].re + r[s8][e].im * r[s8][e].im;
+        nn = wave_sum(nn);
+        const double nrm = sqrt(nn);
+        if (!(nrm > 0.0) && lane == 0) atomicOr(status, 0x2u);
+        lr += log(nrm);
+        const double inv = 1.0 / nrm;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          r[s8][e] = cscale(r[s8][e], inv);
+          qb[k & 1][lane + 64 * e] = r[s8][e];
+        }
+      }
+    }
+    __syncthreads();
+    cd q[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) q[e] = qb[k & 1][lane + 64 * e];
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) {
+      const int j = 4 * s8 + wave;
+      if (j <= k || j >= N) continue;
+      double dr = 0.0, di = 0.0;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const cd v = cconjmul(q[e], r[s8][e]);
+        dr += v.re;
+        di += v.im;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) cfms(r[s8][e], mkc(dr, di), q[e]);
+    }
+  }
+#pragma unroll
+  for (int s8 = 0; s8 < 8; ++s8) {
+    const int j = 4 * s8 + wave;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int p = lane + 64 * e;
+      if (j < N && p < M) Ug[(size_t)j * M + p] = r[s8][e];
+    }
+  }
+  if (lane == 0) lrs[wave] = lr;
+  __syncthreads();
+  if (tid == 0) logR[2 * w + s] = lrs[0] + lrs[1] + lrs[2] + lrs[3];
+}
+
+// ---------------------------------------------------------------------------
 // Weight update, one thread per walker.
 //   mode 0 phaseless local energy (eq:if_rle, eq:cap):
 //          W <- min(w_max, W exp(-dtau (Re E_L^cap(old) - E_T)) max(0, cos dtheta)),
