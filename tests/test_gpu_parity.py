@@ -168,14 +168,18 @@ def test_gpu_singular_and_nonfinite_walkers_are_killed(torch_cuda, precision):
     assert gpu_state(wk)["W"][1] == 0.0
 
 
-@pytest.mark.parametrize("case", ["n34_m136", "n48_m200"])
+@pytest.mark.parametrize("case", ["n34_m136", "n48_m200", "n20_m232"])
 def test_gpu_fp64_beyond_mfma_tile_limits(torch_cuda, case):
     """FP64 sizes outside the register-resident MFMA tiles (N > 32 or M > 128) run the FP64
-    VALU contraction, with the overlap on k_overlap_mfma<48>."""
+    VALU contraction, with the overlap on k_overlap_mfma<48> beyond N = 32.  n20_m232 keeps
+    N <= 32 at M = 232: the one-wavefront overlap with a ragged K tail (232 = 14.5 x 16) and the
+    register Gram-Schmidt with four elements per lane, whose QR runs at the fifth step."""
     if case == "n34_m136":
         s, nw, steps = gen_system(136, 34, 40, seed=21, n_dn=30), 3, 5
-    else:
+    elif case == "n48_m200":
         s, nw, steps = gen_system(200, 48, 24, seed=22, n_dn=40), 2, 5
+    else:
+        s, nw, steps = gen_system(232, 20, 6, seed=1), 2, 6
     log(f"fp64 large shape {case}")
     worst, *_ = run_lockstep(s, nw, steps, dtau=0.005, label=case)
     log(f"{case} worst {worst}")
