@@ -370,7 +370,7 @@ int launch_overlap(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout& L, in
                      S->mt.enabled ? nullptr : at<cd>(ws, L.thetaT), at<cd>(ws, L.logdet),       \
                      at<cd>(ws, L.e1), at<unsigned>(ws, L.wflag), packed, kind, S->mt.NP,        \
                      S->mt.KP, S->guard_on ? at<double>(ws, L.thmax) : nullptr,                  \
-                     S->guard_on ? at<double>(ws, L.thetaP64) : nullptr)
+                     S->guard_on ? at<double>(ws, L.thetaP64) : nullptr, S->guard)
   // up to N = 32 one wavefront per matrix (elimination in registers), beyond it the
   // four-wavefront kernel with [T | I] in LDS
   if (nmax <= 16)
@@ -425,7 +425,7 @@ int launch_guard_assemble(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout
   void* ws = w->workspace;
   if (S->mt.enabled && S->guard_on) {
     // walkers far from the trial (large Theta) again in FP64, over the partial sums of the
-    // low-precision pass
+    // low-precision pass: of a listed walker, the spins whose max |Theta| exceeds the threshold
     Timer tm(S, KG_GUARD);
     hipLaunchKernelGGL(k_guard_list, dim3(1), dim3(1024), 0, S->stream, w->n_walkers, S->n_det,
                        S->guard, w->weight, (const double*)at<double>(ws, L.thmax),
@@ -435,7 +435,8 @@ int launch_guard_assemble(afqmc_sys_s* S, const afqmc_walkers* w, const WsLayout
     HIPCHK(mfma_contract(S->mt64, S->stream, w->n_walkers, S->n_det, S->G,
                          at<void>(ws, L.thetaP64), w->weight, at<cd>(ws, L.tpart),
                          at<cd>(ws, L.exch), TILE_DEFAULT, at<int>(ws, L.glist),
-                         at<int>(ws, L.gcount)));
+                         at<int>(ws, L.gcount), (const double*)at<double>(ws, L.thmax),
+                         S->guard));
   }
   if (S->multi) {
     Timer tm(S, KG_ASSEMBLE);

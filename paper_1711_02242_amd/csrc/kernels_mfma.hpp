@@ -238,7 +238,8 @@ template <int NP, int NK>
 __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
     int nw, int G, int nup, int ndn, int KP_arg, const double* __restrict__ Lp,
     const double* __restrict__ thp, const double* __restrict__ weight, cd* __restrict__ tpart,
-    cd* __restrict__ exch, const int* __restrict__ wlist, const int* __restrict__ wcount) {
+    cd* __restrict__ exch, const int* __restrict__ wlist, const int* __restrict__ wcount,
+    const double* __restrict__ gthmax, double guard) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   constexpr int NB = NP / 16;
   constexpr int NCH = NK;                     // K chunks of 8 held per lane as 4 x f64x2
@@ -267,7 +268,10 @@ __global__ void __launch_bounds__(256, 2) k_contract_f64mfma(
     }
     return;
   }
-  const bool active = (w >= 0) && (w < nw) && (weight[w] > 0.0);
+  bool active = (w >= 0) && (w < nw) && (weight[w] > 0.0);
+  // with the precision guard's per-spin maxima, of a listed walker only the spins above the
+  // threshold (those whose FP64 operand the overlap kernel wrote); the others keep their sums
+  if (active && wlist && gthmax) active = gthmax[2 * wd + s] > guard;
   constexpr int lda = KP + 2;
   double* At = reinterpret_cast<double*>(smem);                       // [NP][KP + 2]
   double* ep = At + (size_t)NP * lda + (size_t)pair * 2 * NP * LDE;   // this pair's planes
@@ -397,7 +401,8 @@ inline size_t mfma_f64_contract_lds_bytes(const MfmaTables& t) {
 inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int n_det, int G,
                                 const void* thetaP, const double* weight, cd* tpart, cd* exch,
                                 int tile = TILE_DEFAULT, const int* wlist = nullptr,
-                                const int* wcount = nullptr) {
+                                const int* wcount = nullptr, const double* gthmax = nullptr,
+                                double guard = 0.0) {
   if (t.precision == AFQMC_FP64) {
     const size_t shm = mfma_f64_contract_lds_bytes(t);
     dim3 grid((nw + 1) / 2, 2 * n_det);
@@ -409,7 +414,7 @@ inline hipError_t mfma_contract(const MfmaTables& t, hipStream_t st, int nw, int
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);           \
     hipLaunchKernelGGL((k_contract_f64mfma<NPV, NKV>), grid, dim3(256), shm, st, nw, G, t.nup, \
                        t.ndn, t.KP, (const double*)t.Lp, (const double*)thetaP, weight, tpart, \
-                       exch, wlist, wcount);                                                   \
+                       exch, wlist, wcount, gthmax, guard);                                    \
   } while (0)
 #define LAUNCH_F64_NP(NPV)                                                                     \
   do {                                                                                         \
@@ -932,6 +937,8 @@ __device__ inline void zero_packed_pad(E* base, int planes, size_t per, int N, i
 // lane reads those of its own half of the columns; row i loses f_i times that row, with
 // f_i = T_ik / T_pk and f_p = 1 - 1 / T_pk (which leaves the pivot row divided by the pivot);
 // column k then holds -f_i, and 1 / T_pk in row p_k.
+// With the precision guard (thmax != NULL) the FP64 operand is written only for a walker-spin
+// whose max |Theta| exceeds the guard's threshold: the guard redoes exactly those spins.
 // ---------------------------------------------------------------------------
 template <int NPAD>
 __global__ void __launch_bounds__(64, 2) k_overlap_wave(
@@ -939,7 +946,7 @@ __global__ void __launch_bounds__(64, 2) k_overlap_wave(
     const cd* __restrict__ U, const double* __restrict__ weight, int check_weight,
     cd* __restrict__ thetaT, cd* __restrict__ logdet, cd* __restrict__ e1,
     unsigned* __restrict__ wflag, void* __restrict__ packed, int packed_kind, int NP, int KP,
-    double* __restrict__ thmax, double* __restrict__ packed64) {
+    double* __restrict__ thmax, double* __restrict__ packed64, double guard) {
   static_assert(NPAD == 16 || NPAD == 32, "one wavefront inverts at most 32 x 32");
   constexpr int NB = NPAD / 16, NKC = NPAD / 16, XL = 33;
   __shared__ __attribute__((aligned(16))) cd Xs[32 * XL];   // T, then X
@@ -1140,6 +1147,7 @@ __global__ void __launch_bounds__(64, 2) k_overlap_wave(
   cd* Tw = thetaT ? thetaT + ((size_t)wd_ * ntot + off) * M : nullptr;
   const double* hts = ht + (size_t)off * M;
   double e1re = 0.0, e1im = 0.0, th2max = 0.0;
+  bool guarded = false;   // the precision guard takes this walker-spin
   cd uv[NKC][4], un2[NKC][4];
   auto loadu = [&](int b, cd (&dst)[NKC][4]) {
     const int pp = 16 * b + l16, pc = pp < M ? pp : M - 1;
@@ -1148,6 +1156,18 @@ __global__ void __launch_bounds__(64, 2) k_overlap_wave(
 #pragma unroll
       for (int u = 0; u < 4; ++u) dst[kc][u] = Uw[uro[kc][u] + pc];
   };
+  // pass 0 writes the outputs and finds max |Theta|; pass 1, only for a walker-spin the
+  // precision guard takes (max |Theta| above its threshold, the test the guard applies to the
+  // stored value), computes Theta again for its FP64 operand
+  for (int pass = 0; pass < 2; ++pass) {
+  if (pass == 1) {
+    if (!thmax) break;
+    for (int o = 32; o > 0; o >>= 1) th2max = fmax(th2max, __shfl_xor(th2max, o));
+    const double m = sqrt(th2max);
+    if (lane == 0) thmax[2 * wd_ + s] = m;
+    guarded = m > guard;
+    if (!guarded) break;
+  }
   loadu(0, uv);
   for (int b0 = 0; b0 < CBn; ++b0) {
     // an opaque block index keeps the compiler from turning every store address of the
@@ -1193,13 +1213,14 @@ __global__ void __launch_bounds__(64, 2) k_overlap_wave(
         const int c = 16 * a + q + 4 * v, p = pp;
         if (c >= N || p >= M) continue;
         const cd th = mkc(cr[a][v], ci[a][v]);
-        if (thetaT) Tw[(size_t)c * M + p] = th;
-        if (thmax) {
-          th2max = fmax(th2max, th.re * th.re + th.im * th.im);
+        if (pass == 1) {
           double* o = packed64 + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
           o[0] = th.re;
           o[per] = th.im;
+          continue;
         }
+        if (thetaT) Tw[(size_t)c * M + p] = th;
+        if (thmax) th2max = fmax(th2max, th.re * th.re + th.im * th.im);
         e1re = fma(hvv[a][v], th.re, e1re);
         e1im = fma(hvv[a][v], th.im, e1im);
         if (packed_kind == 3) {
@@ -1225,6 +1246,7 @@ __global__ void __launch_bounds__(64, 2) k_overlap_wave(
 #pragma unroll
       for (int u = 0; u < 4; ++u) uv[kc][u] = un2[kc][u];
   }
+  }
   const size_t ws_ = (size_t)wd_ * 2 + s;
   if (packed_kind == 3)
     zero_packed_pad(reinterpret_cast<double*>(packed) + ws_ * 2 * per, 2, per, N, M, NP, KP, lane);
@@ -1232,11 +1254,7 @@ __global__ void __launch_bounds__(64, 2) k_overlap_wave(
     zero_packed_pad(reinterpret_cast<float*>(packed) + ws_ * 2 * per, 2, per, N, M, NP, KP, lane);
   else if (packed_kind == 2)
     zero_packed_pad(reinterpret_cast<uint16_t*>(packed) + ws_ * 4 * per, 4, per, N, M, NP, KP, lane);
-  if (thmax) {
-    zero_packed_pad(packed64 + ws_ * 2 * per, 2, per, N, M, NP, KP, lane);
-    for (int o = 32; o > 0; o >>= 1) th2max = fmax(th2max, __shfl_xor(th2max, o));
-    if (lane == 0) thmax[2 * wd_ + s] = sqrt(th2max);
-  }
+  if (guarded) zero_packed_pad(packed64 + ws_ * 2 * per, 2, per, N, M, NP, KP, lane);
   e1re = wave_sum(e1re);
   e1im = wave_sum(e1im);
   if (lane == 0) e1[2 * wd_ + s] = mkc(e1re, e1im);

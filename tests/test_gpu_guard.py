@@ -1,5 +1,7 @@
 """The precision guard of the mixed-precision modes (FP32, BF16x3): walkers whose largest
-|Theta_pc| exceeds the threshold have their contraction redone on the FP64 MFMA kernel.
+|Theta_pc| exceeds the threshold have their contraction redone on the FP64 MFMA kernel, spin
+by spin (a spin below the threshold keeps its low-precision sums, and the overlap kernel writes
+the FP64 operand only for the spins above it).
 
 * With a threshold below every walker's, every walker goes through FP64: the mixed modes then
   give the FP64 path's local energies and traces to FP64 rounding (single and multi-determinant
