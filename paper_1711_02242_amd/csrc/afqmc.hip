@@ -170,14 +170,14 @@ struct Timer {
   hipEvent_t a{}, b{};
   Timer(afqmc_sys_s* s, int g) : S(s), group(g) {
     if (S->timing) {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
-      hipEventRecord(a, S->stream);
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, S->stream);
     }
   }
   ~Timer() {
     if (S->timing) {
-      hipEventRecord(b, S->stream);
+      (void)hipEventRecord(b, S->stream);
       S->launches.push_back(TimedLaunch{group, a, b});
     }
   }
@@ -188,11 +188,11 @@ void flush_timing(afqmc_sys_s* S) {
   (void)hipStreamSynchronize(S->stream);
   for (auto& t : S->launches) {
     float ms = 0.f;
-    hipEventElapsedTime(&ms, t.a, t.b);
+    (void)hipEventElapsedTime(&ms, t.a, t.b);
     S->acc_ms[t.group] += ms;
     S->acc_n[t.group] += 1;
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
   S->launches.clear();
 }
@@ -311,21 +311,21 @@ int dev_upload(afqmc_sys_s* S, T** dst, const T* src, size_t count) {
 void free_sys(afqmc_sys_s* S) {
   if (!S) return;
   for (auto& t : S->launches) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
-  hipFree(S->Eh);
-  hipFree(S->V);
-  hipFree(S->Lh);
-  hipFree(S->ht);
-  hipFree(S->status);
-  hipFree(S->capcount);
-  hipFree(S->Lt32);
-  hipFree(S->abpairs);
-  hipFree(S->Lt64);
-  hipFree(S->lbar);
-  hipFree(S->Eh32);
-  hipFree(S->coef);
+  (void)hipFree(S->Eh);
+  (void)hipFree(S->V);
+  (void)hipFree(S->Lh);
+  (void)hipFree(S->ht);
+  (void)hipFree(S->status);
+  (void)hipFree(S->capcount);
+  (void)hipFree(S->Lt32);
+  (void)hipFree(S->abpairs);
+  (void)hipFree(S->Lt64);
+  (void)hipFree(S->lbar);
+  (void)hipFree(S->Eh32);
+  (void)hipFree(S->coef);
   mfma_free_tables(S->mt);
   mfma_free_tables(S->mt64);
   delete S;

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(1024) k_mcd_pivot(int MM, double delta, int n,
   __shared__ double bv[16];
   __shared__ int bi[16];
   __shared__ double s_dmax;
-  __shared__ int s_piv, s_stop;
+  __shared__ int s_stop;
   if (threadIdx.x == 0) s_stop = st->done;
   __syncthreads();
   if (s_stop) return;
@@ -75,7 +75,6 @@ __global__ void __launch_bounds__(1024) k_mcd_pivot(int MM, double delta, int n,
         i = bi[k];
       }
     s_dmax = b;
-    s_piv = i;
     if (!(b >= delta) || n >= max_vectors) {
       st->done = 1;
       st->count = n;
