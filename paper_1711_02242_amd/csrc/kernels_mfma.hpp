@@ -1160,92 +1160,92 @@ __global__ void __launch_bounds__(64, 2) k_overlap_wave(
   // precision guard takes (max |Theta| above its threshold, the test the guard applies to the
   // stored value), computes Theta again for its FP64 operand
   for (int pass = 0; pass < 2; ++pass) {
-  if (pass == 1) {
-    if (!thmax) break;
-    for (int o = 32; o > 0; o >>= 1) th2max = fmax(th2max, __shfl_xor(th2max, o));
-    const double m = sqrt(th2max);
-    if (lane == 0) thmax[2 * wd_ + s] = m;
-    guarded = m > guard;
-    if (!guarded) break;
-  }
-  loadu(0, uv);
-  for (int b0 = 0; b0 < CBn; ++b0) {
-    // an opaque block index keeps the compiler from turning every store address of the
-    // epilogue into a 64-bit induction variable held across the loop
-    int b = b0;
-    asm volatile("" : "+s"(b));
-    if (b + 1 < CBn) loadu(b + 1, un2);
-    const int pp = 16 * b + l16, pc = pp < M ? pp : M - 1;
-    double hvv[NB][4];   // h~ at this block's outputs, loaded ahead of the MFMAs
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = 16 * a + q + 4 * v;
-        hvv[a][v] = hts[(size_t)(c < N ? c : N - 1) * M + pc];
-      }
-    f64x4 cr[NB], ci[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) cr[a] = ci[a] = f64x4{0.0, 0.0, 0.0, 0.0};
-    // the X reads stay in the loop (hoisted they would hold 64 registers across it)
-    int xo[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      xo[a] = xb[a];
-      asm volatile("" : "+v"(xo[a]));
+    if (pass == 1) {
+      if (!thmax) break;
+      for (int o = 32; o > 0; o >>= 1) th2max = fmax(th2max, __shfl_xor(th2max, o));
+      const double m = sqrt(th2max);
+      if (lane == 0) thmax[2 * wd_ + s] = m;
+      guarded = m > guard;
+      if (!guarded) break;
     }
+    loadu(0, uv);
+    for (int b0 = 0; b0 < CBn; ++b0) {
+      // an opaque block index keeps the compiler from turning every store address of the
+      // epilogue into a 64-bit induction variable held across the loop
+      int b = b0;
+      asm volatile("" : "+s"(b));
+      if (b + 1 < CBn) loadu(b + 1, un2);
+      const int pp = 16 * b + l16, pc = pp < M ? pp : M - 1;
+      double hvv[NB][4];   // h~ at this block's outputs, loaded ahead of the MFMAs
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc)
+      for (int a = 0; a < NB; ++a)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          const cd tv = Xs[xo[a] + (16 * kc + u) * XL], uw = uv[kc][u];
-          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uw.re, cr[a], 0, 0, 0);
-          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(-tv.im, uw.im, cr[a], 0, 0, 0);
-          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uw.im, ci[a], 0, 0, 0);
-          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.im, uw.re, ci[a], 0, 0, 0);
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * a + q + 4 * v;
+          hvv[a][v] = hts[(size_t)(c < N ? c : N - 1) * M + pc];
         }
+      f64x4 cr[NB], ci[NB];
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+      for (int a = 0; a < NB; ++a) cr[a] = ci[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+      // the X reads stay in the loop (hoisted they would hold 64 registers across it)
+      int xo[NB];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = 16 * a + q + 4 * v, p = pp;
-        if (c >= N || p >= M) continue;
-        const cd th = mkc(cr[a][v], ci[a][v]);
-        if (pass == 1) {
-          double* o = packed64 + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
-          o[0] = th.re;
-          o[per] = th.im;
-          continue;
-        }
-        if (thetaT) Tw[(size_t)c * M + p] = th;
-        if (thmax) th2max = fmax(th2max, th.re * th.re + th.im * th.im);
-        e1re = fma(hvv[a][v], th.re, e1re);
-        e1im = fma(hvv[a][v], th.im, e1im);
-        if (packed_kind == 3) {
-          double* o = reinterpret_cast<double*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
-          o[0] = th.re;
-          o[per] = th.im;
-        } else if (packed_kind == 1) {
-          float* o = reinterpret_cast<float*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
-          o[0] = (float)th.re;
-          o[per] = (float)th.im;
-        } else if (packed_kind == 2) {
-          uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)wd_ * 2 + s) * 4 * per + (size_t)c * KP + p;
-          const float xr = (float)th.re, xi = (float)th.im;
-          const uint16_t hr = f32_to_bf16_bits(xr), hi = f32_to_bf16_bits(xi);
-          o[0] = hr;
-          o[per] = f32_to_bf16_bits(xr - bf16_bits_to_f32(hr));
-          o[2 * per] = hi;
-          o[3 * per] = f32_to_bf16_bits(xi - bf16_bits_to_f32(hi));
-        }
+      for (int a = 0; a < NB; ++a) {
+        xo[a] = xb[a];
+        asm volatile("" : "+v"(xo[a]));
       }
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc)
+      for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) uv[kc][u] = un2[kc][u];
-  }
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int a = 0; a < NB; ++a) {
+            const cd tv = Xs[xo[a] + (16 * kc + u) * XL], uw = uv[kc][u];
+            cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uw.re, cr[a], 0, 0, 0);
+            cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(-tv.im, uw.im, cr[a], 0, 0, 0);
+            ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.re, uw.im, ci[a], 0, 0, 0);
+            ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.im, uw.re, ci[a], 0, 0, 0);
+          }
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * a + q + 4 * v, p = pp;
+          if (c >= N || p >= M) continue;
+          const cd th = mkc(cr[a][v], ci[a][v]);
+          if (pass == 1) {
+            double* o = packed64 + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
+            o[0] = th.re;
+            o[per] = th.im;
+            continue;
+          }
+          if (thetaT) Tw[(size_t)c * M + p] = th;
+          if (thmax) th2max = fmax(th2max, th.re * th.re + th.im * th.im);
+          e1re = fma(hvv[a][v], th.re, e1re);
+          e1im = fma(hvv[a][v], th.im, e1im);
+          if (packed_kind == 3) {
+            double* o = reinterpret_cast<double*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
+            o[0] = th.re;
+            o[per] = th.im;
+          } else if (packed_kind == 1) {
+            float* o = reinterpret_cast<float*>(packed) + ((size_t)wd_ * 2 + s) * 2 * per + (size_t)c * KP + p;
+            o[0] = (float)th.re;
+            o[per] = (float)th.im;
+          } else if (packed_kind == 2) {
+            uint16_t* o = reinterpret_cast<uint16_t*>(packed) + ((size_t)wd_ * 2 + s) * 4 * per + (size_t)c * KP + p;
+            const float xr = (float)th.re, xi = (float)th.im;
+            const uint16_t hr = f32_to_bf16_bits(xr), hi = f32_to_bf16_bits(xi);
+            o[0] = hr;
+            o[per] = f32_to_bf16_bits(xr - bf16_bits_to_f32(hr));
+            o[2 * per] = hi;
+            o[3 * per] = f32_to_bf16_bits(xi - bf16_bits_to_f32(hi));
+          }
+        }
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) uv[kc][u] = un2[kc][u];
+    }
   }
   const size_t ws_ = (size_t)wd_ * 2 + s;
   if (packed_kind == 3)
