@@ -324,6 +324,8 @@ def serving_leg(args):
         torch.cuda.synchronize()
         per = (time.perf_counter() - a) / args.serve_fp64_steps
         fp64_ms.append(1e3 * per)
+        eprint(f"bench: serial FP64 job {len(fp64_ms)}/{len(specs)} (M={sp.M}, "
+               f"{sp.n_walkers} walkers): {1e3 * per:.2f} ms/step")
         gs.close()
         del s
         start = max(sp.arrival, t_end)
